@@ -1,0 +1,154 @@
+"""Python access to the plain FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: used by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark.  The product path never imports it.
+
+The oracle is compiled with gcc (``-O2 -ffp-contract=off``) into
+``oracle/liboracle.so``; :func:`build` does that and :func:`lib` builds on
+first use if the library is missing or older than its source.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+SO = os.path.join(HERE, "liboracle.so")
+
+_lock = threading.Lock()
+_lib = None
+
+
+class OrcGrid(C.Structure):
+    _fields_ = [("n_freq", C.c_int32), ("n_zen", C.c_int32), ("n_az", C.c_int32), ("pad_", C.c_int32),
+                ("f0_hz", C.c_int64), ("df_hz", C.c_int64),
+                ("zen0_deg", C.c_double), ("dzen_deg", C.c_double),
+                ("az0_deg", C.c_double), ("daz_deg", C.c_double)]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so from oracle.c with gcc."""
+    if force or not os.path.exists(SO) or os.path.getmtime(SO) < os.path.getmtime(SRC):
+        tmp = SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, SO)
+    return SO
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build(force=False)
+            L = C.CDLL(SO)
+            dp = C.POINTER(C.c_double)
+            ip = C.POINTER(C.c_int64)
+            L.orc_fft.argtypes = [C.c_int64, dp, dp, C.c_int]
+            L.orc_fft.restype = C.c_int
+            L.orc_in_band.argtypes = [C.c_int64] * 5
+            L.orc_in_band.restype = C.c_int
+            L.orc_pattern_at_bin.argtypes = [C.POINTER(OrcGrid), dp, C.c_int64, C.c_int64, C.c_int64,
+                                             C.c_double, C.c_double, dp]
+            L.orc_pattern_at_bin.restype = C.c_int
+            L.orc_solve2.argtypes = [dp, dp, C.c_double, dp]
+            L.orc_solve2.restype = C.c_int
+            L.orc_unfold_units.argtypes = [C.POINTER(OrcGrid), dp, C.c_int64, C.c_int64, C.c_int64,
+                                           C.c_int64, C.c_int64, C.c_double, dp, C.c_int64, dp,
+                                           C.c_int64, ip, dp, ip, dp]
+            L.orc_unfold_units.restype = C.c_int
+            _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def make_grid(grid) -> OrcGrid:
+    return OrcGrid(grid.n_freq, grid.n_zen, grid.n_az, 0, int(grid.f0_hz), int(grid.df_hz),
+                   float(grid.zen0_deg), float(grid.dzen_deg), float(grid.az0_deg), float(grid.daz_deg))
+
+
+def _table128(grid, table):
+    t = np.ascontiguousarray(np.asarray(table), dtype=np.complex128)
+    if t.shape != (2, 2, grid.n_freq, grid.n_zen, grid.n_az):
+        raise ValueError("table shape %r does not match grid" % (t.shape,))
+    return t
+
+
+def fft(x, sign: int = -1) -> np.ndarray:
+    """Unnormalised DFT, exp(sign 2 pi i j k / n), by the oracle's radix-2 FFT."""
+    x = np.asarray(x, dtype=np.complex128)
+    re = np.ascontiguousarray(x.real.copy())
+    im = np.ascontiguousarray(x.imag.copy())
+    if lib().orc_fft(len(x), _dp(re), _dp(im), int(sign)) != 0:
+        raise ValueError("length must be a power of two")
+    return re + 1j * im
+
+
+def in_band(k: int, n: int, fs_hz: int, lo_hz: int, hi_hz: int) -> bool:
+    return bool(lib().orc_in_band(k, n, fs_hz, lo_hz, hi_hz))
+
+
+def pattern_at_bin(grid, table, k: int, n: int, fs_hz: int, zen: float, az: float) -> np.ndarray:
+    """Interpolated H[c][p] (2x2 complex) at FFT bin k for direction (zen, az) deg."""
+    t = _table128(grid, table)
+    g = make_grid(grid)
+    h = np.zeros(8)
+    if lib().orc_pattern_at_bin(C.byref(g), _dp(t.view(np.float64)), k, n, fs_hz, zen, az, _dp(h)) != 0:
+        raise ValueError("bin outside the table's frequency range")
+    return (h[0::2] + 1j * h[1::2]).reshape(2, 2)
+
+
+def solve2(h, x, singular_rel: float = 1e-12):
+    """Solve the 2x2 complex system h e = x; returns (e, singular)."""
+    hh = np.ascontiguousarray(np.asarray(h, dtype=np.complex128).reshape(4)).view(np.float64).copy()
+    xx = np.ascontiguousarray(np.asarray(x, dtype=np.complex128).reshape(2)).view(np.float64).copy()
+    e = np.zeros(4)
+    s = lib().orc_solve2(_dp(hh), _dp(xx), singular_rel, _dp(e))
+    return e[0::2] + 1j * e[1::2], bool(s)
+
+
+def unfold(grid, table, volt, dirs, fs_hz: int, lo_hz: int, hi_hz: int,
+           singular_rel: float = 1e-12, units=None):
+    """Unfold E-field traces.
+
+    volt [S][2][N] (any real dtype, promoted to float64), dirs [D][2] degrees.
+    With ``units`` = None every (direction, station) pair is computed and E
+    has shape [D][S][2][N]; otherwise ``units`` is an int array [U][2] of
+    (direction, station) pairs and E has shape [U][2][N].
+    Returns (E, singular_bins per unit, max |Im|/peak after the inverse).
+    """
+    t = _table128(grid, table)
+    v = np.ascontiguousarray(np.asarray(volt), dtype=np.float64)
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 2))
+    n_st, two, n = v.shape
+    assert two == 2
+    full = units is None
+    if full:
+        dd, ss = np.meshgrid(np.arange(len(d)), np.arange(n_st), indexing="ij")
+        units = np.stack([dd.ravel(), ss.ravel()], axis=1)
+    u = np.ascontiguousarray(np.asarray(units, dtype=np.int64).reshape(-1, 2))
+    e = np.zeros((len(u), 2, n))
+    sing = np.zeros(len(u), dtype=np.int64)
+    mi = np.zeros(1)
+    g = make_grid(grid)
+    rc = lib().orc_unfold_units(C.byref(g), _dp(t.view(np.float64)), n_st, n, fs_hz, lo_hz, hi_hz,
+                                singular_rel, _dp(v), len(d), _dp(d), len(u), _ip(u),
+                                _dp(e), _ip(sing), _dp(mi))
+    if rc != 0:
+        raise ValueError("orc_unfold_units failed with %d" % rc)
+    if full:
+        e = e.reshape(len(d), n_st, 2, n)
+        sing = sing.reshape(len(d), n_st)
+    return e, sing, float(mi[0])

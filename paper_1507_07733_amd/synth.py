@@ -1,0 +1,235 @@
+"""Seeded synthetic inputs shaped like AERA radio events.
+
+This module only *generates data*: pattern tables, voltage traces, event
+size mixes, candidate-direction grids and arrival times.  It holds none of
+the unfolding arithmetic, so both the HIP path and the CPU oracle can take
+their inputs from it without sharing any of the method's code.
+
+The shapes follow the paper: up to 124 stations with two polarised channels
+each and an antenna band of 30-80 MHz (section 1, AERA description; section
+2, two-channel read-out), and a vector-effective-length table of complex
+(theta, phi) pairs on a discrete (frequency, zenith, azimuth) grid (section
+3).  Measured AERA patterns and traces are not available, so the generators
+below stand in for them:
+
+* pattern table: a crossed-dipole response with smooth low-order angular
+  harmonics, multiplied by a per-channel frequency resonance;
+* traces: unit Gaussian noise plus a pulse that is band-limited exactly to
+  the in-band FFT bins of the trace, at a continuous random time;
+* directions: cell-centred zenith/azimuth grids.
+
+All randomness comes from ``numpy.random.default_rng`` seeded with
+``SeedSequence([7733, cfg, stream, ...])`` so a run can be repeated bit for
+bit on any machine with the same numpy.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+
+SEED_ROOT = 7733
+STREAM_TABLE = 0
+STREAM_TRACES = 1
+STREAM_EVENTS = 2
+STREAM_ARRIVALS = 3
+
+FS_HZ = 200_000_000
+BAND_LO_HZ = 30_000_000
+BAND_HI_HZ = 80_000_000
+
+
+def rng(cfg: int, stream: int, *extra: int) -> np.random.Generator:
+    """Deterministic generator for (configuration, stream, extra keys)."""
+    return np.random.default_rng(np.random.SeedSequence([SEED_ROOT, cfg, stream, *extra]))
+
+
+@dataclass(frozen=True)
+class Grid:
+    """Node grid of a pattern table.
+
+    Frequencies are integers in Hz so that the bin-to-node mapping can be
+    evaluated exactly; angles are in degrees.  The azimuth axis is periodic:
+    ``n_az * daz_deg == 360`` and node ``n_az - 1`` wraps to node 0.
+    """
+    n_freq: int
+    n_zen: int
+    n_az: int
+    f0_hz: int
+    df_hz: int
+    zen0_deg: float
+    dzen_deg: float
+    az0_deg: float
+    daz_deg: float
+
+    @property
+    def shape(self):
+        return (2, 2, self.n_freq, self.n_zen, self.n_az)
+
+    def freqs_hz(self):
+        return self.f0_hz + self.df_hz * np.arange(self.n_freq, dtype=np.int64)
+
+    def zeniths_deg(self):
+        return self.zen0_deg + self.dzen_deg * np.arange(self.n_zen)
+
+    def azimuths_deg(self):
+        return self.az0_deg + self.daz_deg * np.arange(self.n_az)
+
+
+# 0-100 MHz in 1 MHz steps, zenith 0-90 deg in 5 deg, azimuth 0-355 deg in 5 deg.
+GRID_COARSE = Grid(101, 19, 72, 0, 1_000_000, 0.0, 5.0, 0.0, 5.0)
+# 0-100 MHz in 0.5 MHz steps, zenith 0-90 deg in 1 deg, azimuth 0-359 deg in 1 deg.
+GRID_FINE = Grid(201, 91, 360, 0, 500_000, 0.0, 1.0, 0.0, 1.0)
+
+
+def resonance(f_hz: np.ndarray, f_c: float, q: float) -> np.ndarray:
+    """Series-resonance response 1 / (1 + iQ(f/f_c - f_c/f)); zero at DC."""
+    f = np.asarray(f_hz, dtype=np.float64)
+    out = np.zeros(f.shape, dtype=np.complex128)
+    nz = f > 0
+    out[nz] = 1.0 / (1.0 + 1j * q * (f[nz] / f_c - f_c / f[nz]))
+    return out
+
+
+def pattern_table(grid: Grid, cfg: int = 0, eps: float = 0.05, q: float = 2.0,
+                  f_res=(55e6, 60e6)) -> np.ndarray:
+    """Synthetic vector-effective-length table, complex128 [2 ch][2 comp][nf][nz][na].
+
+    H[c][theta] = R_c(f) cos(theta) (d_c(phi) + eps h_c,theta(theta, phi))
+    H[c][phi]   = R_c(f)            (d'_c(phi) + eps h_c,phi(theta, phi))
+    with the crossed-dipole base d_0 = cos phi, d'_0 = -sin phi,
+    d_1 = sin phi, d'_1 = cos phi, and h = sum_{l<=2, |m|<=2} a_lm cos^l(theta) e^{i m phi},
+    a_lm complex normal with variance 1/15 (one independent set per (c, comp)).
+    cos(90 deg) is set to exactly zero, so the horizon row is exactly singular.
+    """
+    r = rng(cfg, STREAM_TABLE)
+    th = np.deg2rad(grid.zeniths_deg())
+    ph = np.deg2rad(grid.azimuths_deg())
+    cth = np.cos(th)
+    cth[grid.zeniths_deg() == 90.0] = 0.0
+    ls = np.arange(3)
+    ms = np.arange(-2, 3)
+    # [nz][l] and [na][m]
+    cpow = cth[:, None] ** ls[None, :]
+    eim = np.exp(1j * ms[None, :] * ph[:, None])
+    base = {
+        (0, 0): np.cos(ph), (0, 1): -np.sin(ph),
+        (1, 0): np.sin(ph), (1, 1): np.cos(ph),
+    }
+    f = grid.freqs_hz()
+    out = np.empty(grid.shape, dtype=np.complex128)
+    for c in range(2):
+        rc = resonance(f, f_res[c], q)
+        for p in range(2):
+            a = (r.standard_normal((3, 5)) + 1j * r.standard_normal((3, 5))) * np.sqrt(1.0 / 30.0)
+            h = cpow @ a @ eim.T                      # [nz][na]
+            ang = base[(c, p)][None, :] + eps * h     # [nz][na]
+            if p == 0:
+                ang = cth[:, None] * ang
+            out[c, p] = rc[:, None, None] * ang[None, :, :]
+    return out
+
+
+def identity_table(grid: Grid) -> np.ndarray:
+    """Pattern H = I at every node: unfolding reduces to a band-pass filter."""
+    out = np.zeros(grid.shape, dtype=np.complex128)
+    out[0, 0] = 1.0
+    out[1, 1] = 1.0
+    return out
+
+
+def band_bins(n: int, fs_hz: int = FS_HZ, lo_hz: int = BAND_LO_HZ, hi_hz: int = BAND_HI_HZ) -> np.ndarray:
+    """Integer FFT bins k in [0, n/2] whose frequency k*fs/n lies in [lo, hi].
+
+    Used here only to shape the synthetic pulse; the band test is integer
+    arithmetic in Hz so it has no rounding.
+    """
+    k = np.arange(n // 2 + 1, dtype=np.int64)
+    return k[(lo_hz * n <= k * fs_hz) & (k * fs_hz <= hi_hz * n)]
+
+
+def pulse(n: int, t0: np.ndarray, amp: np.ndarray, fs_hz: int = FS_HZ,
+          lo_hz: int = BAND_LO_HZ, hi_hz: int = BAND_HI_HZ) -> np.ndarray:
+    """(A/|K|) sum_{k in K} cos(2 pi k (t - t0) / n) for t = 0..n-1, in float64.
+
+    ``t0`` and ``amp`` broadcast against each other; the result has their
+    shape plus a trailing axis of length ``n``.  The band K is a contiguous
+    run of bins k1..k2, so the sum has the Dirichlet closed form
+    [sin((k2+1/2)x) - sin((k1-1/2)x)] / (2 sin(x/2)) with x = 2 pi (t - t0)/n.
+    """
+    kb = band_bins(n, fs_hz, lo_hz, hi_hz)
+    k1, k2, nk = float(kb[0]), float(kb[-1]), len(kb)
+    t0 = np.asarray(t0, dtype=np.float64)[..., None]
+    amp = np.asarray(amp, dtype=np.float64)[..., None]
+    x = 2.0 * np.pi * (np.arange(n, dtype=np.float64) - t0) / n
+    s = np.sin(0.5 * x)
+    small = np.abs(s) < 1e-12
+    ssafe = np.where(small, 1.0, s)
+    val = (np.sin((k2 + 0.5) * x) - np.sin((k1 - 0.5) * x)) / (2.0 * ssafe)
+    val = np.where(small, float(nk), val)
+    return amp * val / nk
+
+
+def traces(n_st: int, n: int, cfg: int, event: int = 0, dtype=np.float64,
+           noise_sigma: float = 1.0, amp_range=(5.0, 20.0)) -> np.ndarray:
+    """Voltage traces [S][2][N]: Gaussian noise (sigma 1) plus an in-band pulse.
+
+    Amplitude is uniform in [5, 20] per (station, channel); the pulse time is
+    uniform in [0, N) per station and shared by both channels.  Generated in
+    float64 and rounded to nearest-even when ``dtype`` is float32.
+    """
+    r = rng(cfg, STREAM_TRACES, event)
+    noise = r.standard_normal((n_st, 2, n)) * noise_sigma
+    amp = r.uniform(amp_range[0], amp_range[1], size=(n_st, 2))
+    t0 = r.uniform(0.0, n, size=(n_st, 1))
+    v = noise + pulse(n, np.broadcast_to(t0, (n_st, 2)), amp)
+    return np.ascontiguousarray(v.astype(dtype))
+
+
+def direction_grid(n_zen: int, n_az: int) -> np.ndarray:
+    """Cell-centred candidate directions [D][2] (zenith, azimuth) in degrees.
+
+    theta_i = (i + 1/2) * 90 / n_zen, phi_j = j * 360 / n_az, zenith-major.
+    """
+    th = (np.arange(n_zen) + 0.5) * 90.0 / n_zen
+    ph = np.arange(n_az) * 360.0 / n_az
+    d = np.empty((n_zen * n_az, 2))
+    d[:, 0] = np.repeat(th, n_az)
+    d[:, 1] = np.tile(ph, n_zen)
+    return d
+
+
+# Horizon stress set: wrap, FP32-determinant fallback and exactly singular cases.
+STRESS_ZENITHS = (0.0, 45.0, 89.0, 89.9, 89.99, 89.999, 89.9999, 89.99999, 90.0)
+STRESS_AZIMUTHS = (0.0, 2.5, 357.5, 359.999)
+
+
+def stress_directions() -> np.ndarray:
+    d = [(z, a) for z in STRESS_ZENITHS for a in STRESS_AZIMUTHS]
+    return np.asarray(d, dtype=np.float64)
+
+
+@dataclass
+class EventSpec:
+    n_stations: int
+    n_samples: int
+    seed_event: int
+    dirs: np.ndarray = field(repr=False)
+
+
+def event_mix(n_events: int, cfg: int, s_range=(3, 124), n_choices=(2048, 4096),
+              dirs: np.ndarray | None = None) -> list:
+    """Uneven event list: S uniform in s_range (inclusive), N drawn with equal probability."""
+    r = rng(cfg, STREAM_EVENTS)
+    s = r.integers(s_range[0], s_range[1] + 1, size=n_events)
+    n = r.choice(np.asarray(n_choices), size=n_events)
+    if dirs is None:
+        dirs = direction_grid(16, 16)
+    return [EventSpec(int(s[i]), int(n[i]), i, dirs) for i in range(n_events)]
+
+
+def poisson_arrivals(rate_hz: float, duration_s: float, cfg: int = 3) -> np.ndarray:
+    """Open-loop arrival times (s): exponential gaps at ``rate_hz`` over ``duration_s``."""
+    r = rng(cfg, STREAM_ARRIVALS)
+    n = int(rate_hz * duration_s * 1.2) + 16
+    t = np.cumsum(r.exponential(1.0 / rate_hz, size=n))
+    return t[t < duration_s]
