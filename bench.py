@@ -1,0 +1,294 @@
+"""Benchmark: station-unfolds/s of the FP32 batched path, with the FP64 plain
+path on the same GPU, the HBM roofline of the dominant kernel and the CPU
+oracle as a reported baseline.
+
+Workloads (synthetic, AERA-shaped; see paper_1507_07733_amd/synth.py):
+* batched FP32 (the value): 256 events, stations uniform in 3..124, traces of
+  2048 or 4096 float32 samples (equal odds), 16 x 16 candidate directions
+  per event, complex64 pattern table on the 0.5 MHz / 1 deg grid, FP32
+  compute with the FP64 determinant fallback, one batched plan.
+* FP64 plain: one event of 124 stations x 4096 float64 samples, 32 x 64
+  directions, complex128 table on the 1 MHz / 5 deg grid,
+  au_unfold_direction_scan in FP64.
+
+A station-unfold is one (event, direction, station) producing E_theta and
+E_phi traces.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def build_batched_workload(n_events=256, seed_cfg=2):
+    from paper_1507_07733_amd import synth
+    dirs = synth.direction_grid(16, 16)
+    ev = synth.event_mix(n_events, cfg=seed_cfg, dirs=dirs)
+    specs = [(e.n_stations, e.n_samples, dirs) for e in ev]
+    return specs
+
+
+def gen_traces(specs, offsets, total, seed_cfg=2):
+    from paper_1507_07733_amd import synth
+    volt = np.empty(total, dtype=np.float32)
+
+    def one(e):
+        s, n, _ = specs[e]
+        v = synth.traces(s, n, cfg=seed_cfg, event=e, dtype=np.float32)
+        volt[offsets[e]:offsets[e] + v.size] = v.ravel()
+        return e
+
+    with cf.ThreadPoolExecutor(8) as ex:
+        list(ex.map(one, range(len(specs))))
+    return volt
+
+
+def cpu_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except Exception:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(grid, table_c64, specs, plan, volt_host, budget_s=12.0):
+    """Oracle throughput on a bounded sample of the batched workload.
+
+    Random (event, direction, station) units of the same workload, in chunks
+    of 16 units, run on a thread pool over the host cores (the oracle is C
+    called through ctypes, which releases the GIL) until budget_s of wall
+    time has passed.
+    """
+    from oracle import oracle as O
+    from paper_1507_07733_amd import synth
+    t128 = np.asarray(table_c64).astype(np.complex128)
+    threads = cpu_threads()
+
+    def task(i):
+        e = int((i * 7919) % len(specs))
+        s, n, dirs = specs[e]
+        o = plan.volt_offsets[e]
+        v = volt_host[o:o + s * 2 * n].reshape(s, 2, n).astype(np.float64)
+        r = np.random.default_rng(i)
+        units = np.stack([r.integers(len(dirs), size=16), r.integers(s, size=16)], axis=1)
+        O.unfold(grid, t128, v, dirs, synth.FS_HZ, synth.BAND_LO_HZ, synth.BAND_HI_HZ, units=units)
+        return 16, n
+
+    O.lib()
+    done = 0
+    n_by = {2048: 0, 4096: 0}
+    t0 = time.perf_counter()
+    i = 0
+    with cf.ThreadPoolExecutor(threads) as ex:
+        futs = set()
+        while True:
+            while len(futs) < 2 * threads and time.perf_counter() - t0 < budget_s:
+                futs.add(ex.submit(task, i))
+                i += 1
+            if not futs:
+                break
+            fin, futs = cf.wait(futs, return_when=cf.FIRST_COMPLETED)
+            for f in fin:
+                u, n = f.result()
+                done += u
+                n_by[n] = n_by.get(n, 0) + u
+    wall = time.perf_counter() - t0
+    return {"value": done / wall, "unit": "station-unfolds/s", "cores": threads, "kind": "oracle",
+            "sample": "%d random (event, direction, station) units of the batched workload "
+                      "(%d at N=2048, %d at N=4096), FP64 on the float32 inputs, %.1f s wall on %d threads"
+                      % (done, n_by.get(2048, 0), n_by.get(4096, 0), wall, threads)}
+
+
+def parity_sample(grid, table_c64, specs, plan, volt_host, efield, n_units=8):
+    """Max per-trace error of a few sampled units against the oracle."""
+    from oracle import oracle as O
+    from paper_1507_07733_amd import synth
+    t128 = np.asarray(table_c64).astype(np.complex128)
+    worst = 0.0
+    r = np.random.default_rng(99)
+    for _ in range(n_units):
+        e = int(r.integers(len(specs)))
+        s, n, dirs = specs[e]
+        d, st = int(r.integers(len(dirs))), int(r.integers(s))
+        o = plan.volt_offsets[e]
+        v = volt_host[o:o + s * 2 * n].reshape(s, 2, n).astype(np.float64)
+        ref, _, _ = O.unfold(grid, t128, v, dirs, synth.FS_HZ, synth.BAND_LO_HZ, synth.BAND_HI_HZ,
+                             units=[[d, st]])
+        got = plan.event_output(efield, e)[d, st].cpu().numpy().astype(np.float64)
+        err = np.max(np.abs(got - ref[0]), axis=-1) / np.max(np.abs(ref[0]), axis=-1)
+        worst = max(worst, float(err.max()))
+    return worst
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--events", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-plain", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--flags", type=int, default=2, help="plan flags: 1 graph, 2 persistent")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(every event is independent; see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1507_07733_amd import api, synth
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    # ---------------- batched FP32 workload -------------------------------
+    t0 = time.perf_counter()
+    grid = synth.GRID_FINE
+    table = synth.pattern_table(grid, cfg=2).astype(np.complex64)
+    tab = api.Table(grid, table)
+    specs = build_batched_workload(args.events)
+    flags = args.flags & ~api.AU_PLAN_GRAPH      # stage timing needs eager launches
+    plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=flags)
+    volt_host = gen_traces(specs, plan.volt_offsets, plan.volt_elems)
+    volt = torch.from_numpy(volt_host).to(dev)
+    efield = torch.empty(plan.efield_elems, dtype=torch.float32, device=dev)
+    counts = torch.zeros(2, dtype=torch.int64, device=dev)
+    log("batched workload ready: %d events, %d station-unfolds, %.1f GB out, setup %.1f s"
+        % (len(specs), plan.station_unfolds, plan.efield_elems * 4 / 1e9, time.perf_counter() - t0))
+
+    for _ in range(args.warmup):
+        plan.run(volt, efield, counts)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.run(volt, efield, counts)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    stage_ms, runs = plan.stage_ms()
+    plan.set_timing(False)
+    ms_per_step = total_ms / args.steps
+    value = plan.station_unfolds * args.steps / (total_ms / 1e3)
+    log("batched fp32: %.3f ms/step, %.1f M station-unfolds/s" % (ms_per_step, value / 1e6))
+
+    classes = plan.classes()
+    per_class = []
+    for ci, (n, su) in enumerate(classes):
+        unfold_ms = stage_ms[ci, 2] / runs
+        bytes_launch = su * 2 * n * 4
+        per_class.append({"kernel": "k_unfold<float, %d, 16>" % n, "n_samples": n,
+                          "station_unfolds": int(su),
+                          "spectrum_ms": stage_ms[ci, 0] / runs, "coef_ms": stage_ms[ci, 1] / runs,
+                          "unfold_ms": unfold_ms,
+                          "unfold_algorithmic_GBs": bytes_launch / (unfold_ms / 1e3) / 1e9})
+    dom = max(per_class, key=lambda c: c["unfold_ms"])
+    achieved = dom["unfold_algorithmic_GBs"]
+    roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None,
+                "bytes_per_unit": "2*N*4 B written per station-unfold",
+                "per_class": per_class}
+
+    # graph replay of the same plan, for reference
+    gplan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=args.flags | api.AU_PLAN_GRAPH)
+    for _ in range(2):
+        gplan.run(volt, efield, counts)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        gplan.run(volt, efield, counts)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = ev0.elapsed_time(ev1) / args.steps
+    log("graph replay: %.3f ms/step" % graph_ms)
+
+    err = parity_sample(grid, table, specs, plan, volt_host, efield)
+    cnt = counts.cpu().tolist()
+    log("parity sample max per-trace error %.3e; fallback/singular counters %s" % (err, cnt))
+    del gplan
+
+    # ---------------- FP64 plain direction scan ----------------------------
+    fp64 = None
+    if not args.no_fp64_plain:
+        g1 = synth.GRID_COARSE
+        t1 = api.Table(g1, synth.pattern_table(g1, cfg=1))
+        s1, n1 = 124, 4096
+        dirs1 = synth.direction_grid(32, 64)
+        v1 = torch.from_numpy(synth.traces(s1, n1, cfg=1, event=0)).to(dev)
+        ev = api.make_event(s1, n1, prec=api.AU_PREC_FP64, trace_dtype=api.AU_F64)
+        work = torch.empty(api.workspace_bytes(t1, ev, len(dirs1)), dtype=torch.uint8, device=dev)
+        del efield
+        out1 = torch.empty((len(dirs1), s1, 2, n1), dtype=torch.float64, device=dev)
+        api.unfold_direction_scan(t1, ev, v1, dirs1, out=out1, work=work)
+        torch.cuda.synchronize()
+        k1 = max(2, args.steps // 3)
+        ev0.record(stream)
+        for _ in range(k1):
+            api.unfold_direction_scan(t1, ev, v1, dirs1, out=out1, work=work)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms1 = ev0.elapsed_time(ev1) / k1
+        su1 = len(dirs1) * s1
+        fp64 = {"value": su1 / (ms1 / 1e3), "unit": "station-unfolds/s", "ms_per_call": ms1,
+                "workload": "plain FP64 direction scan: 1 event x 124 stations x 4096 float64 samples, "
+                            "32x64 directions, complex128 table 1 MHz/5 deg",
+                "station_unfolds": su1,
+                "output_GBs": su1 * 2 * n1 * 8 / (ms1 / 1e3) / 1e9}
+        log("fp64 plain scan: %.3f ms/call, %.1f M station-unfolds/s" % (ms1, fp64["value"] / 1e6))
+        del out1, work
+
+    # ---------------- CPU oracle baseline ---------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(grid, table, specs, plan, volt_host, budget_s=args.cpu_budget)
+        log("cpu oracle: %.1f station-unfolds/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    line = {
+        "metric": "station-unfolds/sec FP32-batched vs FP64-plain at 1 GPU; p50/p99 event latency",
+        "value": value,
+        "unit": "station-unfolds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched FP32 unfolding: %d events, stations U{3..124}, N in {2048,4096}, "
+                               "16x16 directions/event, complex64 table 0.5 MHz/1 deg, FP64 det fallback"
+                               % len(specs),
+                   "events": len(specs), "station_unfolds": int(plan.station_unfolds),
+                   "plan_flags": flags, "graph_ms_per_step": graph_ms},
+        "roofline": roofline,
+        "fp64_plain": fp64,
+        "cpu_baseline": cpu,
+        "parity_sample_max_err": err,
+        "fallback_singular_bins": cnt,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,234 @@
+/*
+ * aeraunfold.h -- C ABI of the MI355X (gfx950) antenna-pattern unfolding library.
+ *
+ * The library reconstructs electric-field traces from the two voltage channels
+ * of radio stations, the step the reconstruction repeats for every candidate
+ * arrival direction (arXiv:1507.07733, section 2 and the algorithm of its
+ * Fig. 1).  Per station and direction it
+ *   1. takes the FFT of both channel traces (section 4);
+ *   2. evaluates the complex vector effective length H[c][p] of channel c and
+ *      component p in {theta, phi} at the direction by linear interpolation
+ *      between the (frequency, zenith, azimuth) nodes of a pattern table
+ *      (section 3; trilinear, azimuth periodic, zenith clamped);
+ *   3. per frequency bin solves the 2x2 complex system V_c = sum_p H[c][p] E_p
+ *      for (E_theta, E_phi) (section 2: reconstruct the E-field from the
+ *      voltages with the pattern for the direction);
+ *   4. keeps only bins inside the antenna band, 30-80 MHz by default
+ *      (section 1), and
+ *   5. inverse-FFTs back to E_theta and E_phi traces.
+ *
+ * Conventions for every entry point:
+ *   - Pointers prefixed d_ are device memory on the current HIP device; h_
+ *     pointers are host memory.  The caller owns every pointer it passes; the
+ *     library never frees or retains them past the call (except a batch plan,
+ *     which may keep device pointers inside a captured graph, see au_plan_run).
+ *   - Traces are [S][2][N] (station, channel, sample), sample fastest.  Outputs
+ *     are [D][S][2][N] (direction, station, component theta/phi, sample).
+ *   - Float outputs have the compute precision's type: float for AU_PREC_FP32,
+ *     double for AU_PREC_FP64.  Input traces may be float or double.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  Calls
+ *     validate synchronously, enqueue on the stream and return; results and
+ *     counters are valid once the stream has completed the work.
+ *   - `d_counts` (nullable) is a device array of two uint64: [0] += number of
+ *     (direction, in-band bin) pairs whose FP32 determinant fell below
+ *     fallback_rel * ||H||_F^2 and were redone in FP64, [1] += number of pairs
+ *     treated as singular (|det| <= singular_rel * ||H||_F^2, field set to 0).
+ *     The library only adds to them.
+ *   - Return codes: AU_OK (0) or a negative au_status.  On error nothing has
+ *     been enqueued and au_last_error() returns a message (per thread).
+ */
+#ifndef AERAUNFOLD_H
+#define AERAUNFOLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t au_status;
+#define AU_OK 0
+#define AU_EINVAL (-1)     /* bad argument: sizes, band, grid, dtype, null pointer */
+#define AU_ENOMEM (-2)     /* device or host allocation failed, or workspace too small */
+#define AU_EDEVICE (-3)    /* a HIP call failed */
+#define AU_EAGAIN (-4)     /* not ready yet (au_poll) or over budget (au_submit) */
+#define AU_ENOTFOUND (-5)  /* unknown ticket */
+
+/* element types */
+#define AU_F32 1           /* float; tables: complex64 */
+#define AU_F64 2           /* double; tables: complex128 */
+
+/* compute precision */
+#define AU_PREC_FP64 0     /* everything in double; needs a complex128 table */
+#define AU_PREC_FP32 1     /* FFT, interpolation and solve in float; the 2x2
+                              determinant and inverse are redone in double where
+                              |det| < fallback_rel * ||H||_F^2 */
+
+/*
+ * Node grid of a pattern table (section 3: the vector effective length is
+ * known at discrete frequencies, zenith and azimuth angles).  Frequencies are
+ * integers in Hz so that FFT-bin positions on the grid are exact; angles in
+ * degrees.  Node f has frequency f0_hz + f*df_hz, node z zenith
+ * zen0_deg + z*dzen_deg, node a azimuth az0_deg + a*daz_deg.  The azimuth
+ * axis must close the circle: n_az*daz_deg == 360 (or (n_az-1)*daz_deg == 360
+ * with the last column equal to the first, which is then dropped).
+ */
+typedef struct {
+    int32_t n_freq, n_zen, n_az, reserved;
+    int64_t f0_hz, df_hz;
+    double zen0_deg, dzen_deg, az0_deg, daz_deg;
+} au_grid;
+
+/*
+ * One event: S stations with two channels of N samples at fs_hz.  The band
+ * is the set of FFT bins k in [0, N/2] with band_lo_hz*N <= k*fs_hz <=
+ * band_hi_hz*N, tested exactly in 64-bit integers.  Requirements: N a power
+ * of two in [16, 4096]; S >= 1; 0 <= band_lo_hz <= band_hi_hz < fs_hz/2; every
+ * in-band bin frequency inside the table's frequency range.
+ * fallback_rel (FP32 only) and singular_rel: see d_counts above; the usual
+ * values are 1e-6 and 1e-12.
+ */
+typedef struct {
+    int32_t n_stations, n_samples;
+    int64_t fs_hz, band_lo_hz, band_hi_hz;
+    int32_t trace_dtype;          /* AU_F32 or AU_F64: element type of d_volt */
+    int32_t prec;                 /* AU_PREC_FP64 or AU_PREC_FP32 */
+    double fallback_rel;
+    double singular_rel;
+} au_event;
+
+typedef struct au_table au_table;
+typedef struct au_plan au_plan;
+typedef struct au_server au_server;
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* au_last_error(void);
+
+/* Library version string. */
+const char* au_version(void);
+
+/*
+ * Load a pattern table onto the current device (section 3: the pattern is
+ * copied and converted once, then stays resident for every later lookup).
+ *   grid:        node grid (see au_grid).
+ *   table_dtype: AU_F64 (complex128) or AU_F32 (complex64) for h_vel.
+ *   h_vel:       host array [2 channel][2 component theta/phi][n_freq][n_zen][n_az]
+ *                of interleaved (re, im) pairs of that type.
+ *   out:         receives the handle; free with au_free_pattern_table.
+ * The device copy is re-laid out node-major [freq][zen][az][channel][component]
+ * so one interpolation corner is one contiguous 32 or 64 byte read.  The
+ * call is synchronous.  Errors: AU_EINVAL (grid or dtype), AU_ENOMEM, AU_EDEVICE.
+ */
+au_status au_load_pattern_table(const au_grid* grid, int32_t table_dtype, const void* h_vel,
+                                au_table** out);
+au_status au_free_pattern_table(au_table* table);
+
+/*
+ * Size in bytes of the device workspace a call on this event with n_dir
+ * directions needs (in-band spectra of every station, the per-direction
+ * inverse-pattern coefficients, and the direction list).
+ */
+au_status au_workspace_bytes(const au_table* table, const au_event* ev, int32_t n_dir, uint64_t* bytes);
+
+/* In-band bin range of an event: bins k_lo .. k_lo + n_band - 1 (n_band may be 0). */
+au_status au_band_bins(const au_event* ev, int32_t* k_lo, int32_t* n_band);
+
+/*
+ * Unfold one event for one direction (zen_deg, az_deg) (section 2: the
+ * pattern for the direction is evaluated and the E-field trace of each
+ * station reconstructed from its voltage traces).
+ *   d_volt:   [S][2][N] traces of ev->trace_dtype.
+ *   d_efield: [S][2][N] output (E_theta, E_phi), float or double per ev->prec.
+ *   d_work:   workspace of au_workspace_bytes(ev, 1) bytes, or NULL to let the
+ *             library take it from the stream-ordered pool (hipMallocAsync).
+ * Errors: AU_EINVAL, AU_ENOMEM (work_bytes too small or pool exhausted), AU_EDEVICE.
+ */
+au_status au_unfold_event(const au_table* table, const au_event* ev, const void* d_volt,
+                          double zen_deg, double az_deg, void* d_efield,
+                          void* d_work, uint64_t work_bytes, void* stream, uint64_t* d_counts);
+
+/*
+ * Unfold one event for each of n_dir candidate directions (the direction fit
+ * repeats the unfolding for every candidate; section 2).  The station
+ * spectra are computed once and reused for every direction (section 4: the
+ * trace container keeps the frequency domain and only recomputes it when the
+ * trace changes).
+ *   h_dirs:   host [n_dir][2] (zenith, azimuth) in degrees.
+ *   d_efield: [n_dir][S][2][N] output.
+ *   d_work:   au_workspace_bytes(ev, n_dir) bytes, or NULL (pool).
+ */
+au_status au_unfold_direction_scan(const au_table* table, const au_event* ev, const void* d_volt,
+                                   int32_t n_dir, const double* h_dirs, void* d_efield,
+                                   void* d_work, uint64_t work_bytes, void* stream,
+                                   uint64_t* d_counts);
+
+/*
+ * Interpolated pattern H[c][p](f_k; zen, az) at every in-band bin of ev, for
+ * n_dir directions (section 3: linear interpolation between nodes).  Output
+ * d_resp [n_dir][n_band][2][2] complex (interleaved re, im) of the precision's
+ * type.  Used to check the interpolation on its own.
+ */
+au_status au_pattern_response(const au_table* table, const au_event* ev, int32_t n_dir,
+                              const double* h_dirs, void* d_resp, void* stream);
+
+/*
+ * Batched unfolding of many events of uneven size (stations x directions x
+ * events) in one launch per trace length, optionally replayed from a captured
+ * HIP graph.  Motivation: the paper's GPU time was dominated by host<->device
+ * copies of isolated calls and names keeping traces on the device as the way
+ * to use the GPU better (section 5).
+ *
+ * au_batch describes E events sharing fs, band and precision:
+ *   n_stations[e], n_samples[e], n_dirs[e]: per-event sizes (host arrays);
+ *   h_dirs: host [sum_e n_dirs[e]][2] degrees, event-major;
+ *   volt_offset[e]: element offset of event e's [S][2][N] traces inside d_volt;
+ *   efield_offset[e]: element offset of its [D][S][2][N] output inside d_efield.
+ * au_plan_create validates, sorts work longest-first, uploads the work lists
+ * and allocates the plan's workspace (the only allocation; au_plan_run
+ * allocates nothing).  flags: AU_PLAN_GRAPH to capture the launch sequence in
+ * a hipGraph on first run (re-captured if d_volt / d_efield change),
+ * AU_PLAN_PERSISTENT to run the unfold stage as a persistent kernel fed by an
+ * atomic work counter.
+ */
+#define AU_PLAN_GRAPH 1
+#define AU_PLAN_PERSISTENT 2
+typedef struct {
+    int32_t n_events;
+    int32_t prec;
+    int32_t trace_dtype;
+    int32_t flags;
+    int64_t fs_hz, band_lo_hz, band_hi_hz;
+    double fallback_rel, singular_rel;
+    const int32_t* n_stations;
+    const int32_t* n_samples;
+    const int32_t* n_dirs;
+    const double* h_dirs;
+    const int64_t* volt_offset;
+    const int64_t* efield_offset;
+} au_batch;
+
+au_status au_plan_create(const au_table* table, const au_batch* batch, au_plan** out);
+/* Number of station-unfolds (event, direction, station triples) in the plan. */
+au_status au_plan_units(const au_plan* plan, uint64_t* station_unfolds);
+au_status au_plan_run(au_plan* plan, const void* d_volt, void* d_efield, void* stream,
+                      uint64_t* d_counts);
+
+/*
+ * Stage timing for measurement: with timing enabled (plans without
+ * AU_PLAN_GRAPH only), au_plan_run records a HIP event on the run's stream
+ * before the first launch and after each launch, waits for the last one and
+ * adds each launch's elapsed time to a per-stage total.  Enabling resets the
+ * totals.  Stages are ordered [class][spectrum, coef, unfold]; classes are
+ * the plan's distinct trace lengths, longest first (au_plan_classes).
+ */
+au_status au_plan_timing(au_plan* plan, int32_t enable);
+au_status au_plan_classes(const au_plan* plan, int32_t max, int32_t* n_samples,
+                          uint64_t* station_unfolds, int32_t* n_classes);
+au_status au_plan_stage_ms(const au_plan* plan, int32_t max, double* ms, uint64_t* runs);
+au_status au_plan_free(au_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AERAUNFOLD_H */

@@ -1,0 +1,346 @@
+"""Python binding of libaeraunfold.so (argument marshalling only).
+
+Every computation runs in the HIP library; PyTorch is used here only to
+allocate device memory and to name the stream work is enqueued on.  The
+functions mirror the C ABI in include/aeraunfold.h.  If the library has not
+been built, :func:`lib` raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libaeraunfold.so")
+
+AU_OK = 0
+AU_EINVAL = -1
+AU_ENOMEM = -2
+AU_EDEVICE = -3
+AU_EAGAIN = -4
+AU_ENOTFOUND = -5
+
+AU_F32 = 1
+AU_F64 = 2
+AU_PREC_FP64 = 0
+AU_PREC_FP32 = 1
+AU_PLAN_GRAPH = 1
+AU_PLAN_PERSISTENT = 2
+
+FS_HZ = 200_000_000
+BAND_LO_HZ = 30_000_000
+BAND_HI_HZ = 80_000_000
+
+
+class AuGrid(C.Structure):
+    _fields_ = [("n_freq", C.c_int32), ("n_zen", C.c_int32), ("n_az", C.c_int32), ("reserved", C.c_int32),
+                ("f0_hz", C.c_int64), ("df_hz", C.c_int64),
+                ("zen0_deg", C.c_double), ("dzen_deg", C.c_double),
+                ("az0_deg", C.c_double), ("daz_deg", C.c_double)]
+
+
+class AuEvent(C.Structure):
+    _fields_ = [("n_stations", C.c_int32), ("n_samples", C.c_int32),
+                ("fs_hz", C.c_int64), ("band_lo_hz", C.c_int64), ("band_hi_hz", C.c_int64),
+                ("trace_dtype", C.c_int32), ("prec", C.c_int32),
+                ("fallback_rel", C.c_double), ("singular_rel", C.c_double)]
+
+
+class AuBatch(C.Structure):
+    _fields_ = [("n_events", C.c_int32), ("prec", C.c_int32), ("trace_dtype", C.c_int32), ("flags", C.c_int32),
+                ("fs_hz", C.c_int64), ("band_lo_hz", C.c_int64), ("band_hi_hz", C.c_int64),
+                ("fallback_rel", C.c_double), ("singular_rel", C.c_double),
+                ("n_stations", C.POINTER(C.c_int32)), ("n_samples", C.POINTER(C.c_int32)),
+                ("n_dirs", C.POINTER(C.c_int32)), ("h_dirs", C.POINTER(C.c_double)),
+                ("volt_offset", C.POINTER(C.c_int64)), ("efield_offset", C.POINTER(C.c_int64))]
+
+
+class AuError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("aeraunfold status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lock = threading.Lock()
+_lib = None
+
+# exported symbol -> (restype, argtypes)
+_VP = C.c_void_p
+_SIG = {
+    "au_last_error": (C.c_char_p, []),
+    "au_version": (C.c_char_p, []),
+    "au_load_pattern_table": (C.c_int32, [C.POINTER(AuGrid), C.c_int32, _VP, C.POINTER(_VP)]),
+    "au_free_pattern_table": (C.c_int32, [_VP]),
+    "au_workspace_bytes": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.POINTER(C.c_uint64)]),
+    "au_band_bins": (C.c_int32, [C.POINTER(AuEvent), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "au_unfold_event": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.c_double, C.c_double, _VP, _VP,
+                                    C.c_uint64, _VP, _VP]),
+    "au_unfold_direction_scan": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.c_int32, C.POINTER(C.c_double),
+                                             _VP, _VP, C.c_uint64, _VP, _VP]),
+    "au_pattern_response": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.POINTER(C.c_double), _VP, _VP]),
+    "au_plan_create": (C.c_int32, [_VP, C.POINTER(AuBatch), C.POINTER(_VP)]),
+    "au_plan_units": (C.c_int32, [_VP, C.POINTER(C.c_uint64)]),
+    "au_plan_run": (C.c_int32, [_VP, _VP, _VP, _VP, _VP]),
+    "au_plan_free": (C.c_int32, [_VP]),
+    "au_plan_timing": (C.c_int32, [_VP, C.c_int32]),
+    "au_plan_classes": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_uint64),
+                                    C.POINTER(C.c_int32)]),
+    "au_plan_stage_ms": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
+}
+
+
+def lib():
+    """Load libaeraunfold.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libaeraunfold.so is not built; run __graft_entry__.build() "
+                                   "or python paper_1507_07733_amd/build.py")
+            L = C.CDLL(LIB_PATH)
+            for name, (res, args) in _SIG.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+    return _lib
+
+
+def declared_symbols():
+    return sorted(_SIG)
+
+
+def _check(rc: int):
+    if rc != AU_OK:
+        raise AuError(rc, lib().au_last_error().decode(errors="replace"))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def make_grid(g) -> AuGrid:
+    return AuGrid(g.n_freq, g.n_zen, g.n_az, 0, int(g.f0_hz), int(g.df_hz),
+                  float(g.zen0_deg), float(g.dzen_deg), float(g.az0_deg), float(g.daz_deg))
+
+
+def make_event(n_stations: int, n_samples: int, prec: int = AU_PREC_FP64, trace_dtype: int = AU_F64,
+               fs_hz: int = FS_HZ, band_lo_hz: int = BAND_LO_HZ, band_hi_hz: int = BAND_HI_HZ,
+               fallback_rel: float = 1e-6, singular_rel: float = 1e-12) -> AuEvent:
+    return AuEvent(int(n_stations), int(n_samples), int(fs_hz), int(band_lo_hz), int(band_hi_hz),
+                   int(trace_dtype), int(prec), float(fallback_rel), float(singular_rel))
+
+
+def out_dtype(prec: int):
+    import torch
+    return torch.float64 if prec == AU_PREC_FP64 else torch.float32
+
+
+def trace_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return AU_F64
+    if t.dtype == torch.float32:
+        return AU_F32
+    raise TypeError("traces must be float32 or float64")
+
+
+class Table:
+    """A pattern table resident on the current device."""
+
+    def __init__(self, grid, table: np.ndarray):
+        t = np.asarray(table)
+        if t.dtype == np.complex128:
+            code = AU_F64
+        elif t.dtype == np.complex64:
+            code = AU_F32
+        else:
+            raise TypeError("pattern table must be complex64 or complex128")
+        t = np.ascontiguousarray(t)
+        h = C.c_void_p()
+        g = make_grid(grid)
+        _check(lib().au_load_pattern_table(C.byref(g), code, t.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self.handle = h
+        self.grid = grid
+        self.dtype = code
+
+    def free(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _check(lib().au_free_pattern_table(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def load_pattern_table(grid, table) -> Table:
+    return Table(grid, table)
+
+
+def band_bins(ev: AuEvent):
+    a, b = C.c_int32(), C.c_int32()
+    _check(lib().au_band_bins(C.byref(ev), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def workspace_bytes(table: Table, ev: AuEvent, n_dir: int) -> int:
+    n = C.c_uint64()
+    _check(lib().au_workspace_bytes(table.handle, C.byref(ev), int(n_dir), C.byref(n)))
+    return n.value
+
+
+def _check_traces(volt, ev: AuEvent):
+    if not volt.is_cuda or not volt.is_contiguous():
+        raise ValueError("traces must be a contiguous device tensor")
+    if tuple(volt.shape) != (ev.n_stations, 2, ev.n_samples):
+        raise ValueError("traces must have shape [S][2][N]")
+    if trace_code(volt) != ev.trace_dtype:
+        raise ValueError("trace dtype does not match the event")
+
+
+def _work(work):
+    if work is None:
+        return C.c_void_p(0), 0
+    return C.c_void_p(work.data_ptr()), work.numel() * work.element_size()
+
+
+def unfold_event(table: Table, ev: AuEvent, volt, zen_deg: float, az_deg: float, out=None, work=None,
+                 counts=None, stream=None):
+    """E-field [S][2][N] for one direction; see au_unfold_event."""
+    import torch
+    _check_traces(volt, ev)
+    if out is None:
+        out = torch.empty((ev.n_stations, 2, ev.n_samples), dtype=out_dtype(ev.prec), device=volt.device)
+    wp, wb = _work(work)
+    _check(lib().au_unfold_event(table.handle, C.byref(ev), _ptr(volt), float(zen_deg), float(az_deg),
+                                 _ptr(out), wp, wb, _stream_handle(stream), _ptr(counts)))
+    return out
+
+
+def unfold_direction_scan(table: Table, ev: AuEvent, volt, dirs, out=None, work=None, counts=None,
+                          stream=None):
+    """E-field [D][S][2][N] for every direction of dirs [D][2] (degrees)."""
+    import torch
+    _check_traces(volt, ev)
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 2))
+    if out is None:
+        out = torch.empty((len(d), ev.n_stations, 2, ev.n_samples), dtype=out_dtype(ev.prec),
+                          device=volt.device)
+    wp, wb = _work(work)
+    _check(lib().au_unfold_direction_scan(table.handle, C.byref(ev), _ptr(volt), len(d),
+                                          d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(out), wp, wb,
+                                          _stream_handle(stream), _ptr(counts)))
+    return out
+
+
+def pattern_response(table: Table, ev: AuEvent, dirs, device=None, stream=None):
+    """Interpolated H at every in-band bin: complex tensor [D][n_band][2][2]."""
+    import torch
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 2))
+    _, nb = band_bins(ev)
+    rd = out_dtype(ev.prec)
+    out = torch.zeros((len(d), nb, 2, 2, 2), dtype=rd, device=device or "cuda")
+    _check(lib().au_pattern_response(table.handle, C.byref(ev), len(d),
+                                     d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(out),
+                                     _stream_handle(stream)))
+    return torch.view_as_complex(out)
+
+
+class Plan:
+    """A batched unfolding plan over events of uneven size (au_plan_*).
+
+    events: list of (n_stations, n_samples, dirs[D][2]); traces of event e
+    live at element offset volt_offsets[e] of one flat trace buffer and its
+    output [D][S][2][N] at efield_offsets[e] of one flat output buffer.
+    """
+
+    def __init__(self, table: Table, events, prec: int, trace_dtype: int, flags: int = 0,
+                 volt_offsets=None, efield_offsets=None, fs_hz: int = FS_HZ,
+                 band_lo_hz: int = BAND_LO_HZ, band_hi_hz: int = BAND_HI_HZ,
+                 fallback_rel: float = 1e-6, singular_rel: float = 1e-12):
+        self.table = table
+        s = np.array([e[0] for e in events], dtype=np.int32)
+        n = np.array([e[1] for e in events], dtype=np.int32)
+        dl = [np.asarray(e[2], dtype=np.float64).reshape(-1, 2) for e in events]
+        dcount = np.array([len(x) for x in dl], dtype=np.int32)
+        dirs = np.ascontiguousarray(np.concatenate(dl, axis=0))
+        vsz = s.astype(np.int64) * 2 * n
+        esz = dcount.astype(np.int64) * s * 2 * n
+        if volt_offsets is None:
+            volt_offsets = np.concatenate([[0], np.cumsum(vsz)[:-1]]).astype(np.int64)
+        if efield_offsets is None:
+            efield_offsets = np.concatenate([[0], np.cumsum(esz)[:-1]]).astype(np.int64)
+        self.volt_offsets = np.ascontiguousarray(volt_offsets, dtype=np.int64)
+        self.efield_offsets = np.ascontiguousarray(efield_offsets, dtype=np.int64)
+        self.volt_elems = int((self.volt_offsets + vsz).max())
+        self.efield_elems = int((self.efield_offsets + esz).max())
+        self.n_stations, self.n_samples, self.n_dirs, self.dirs = s, n, dcount, dirs
+        self.prec, self.trace_dtype = prec, trace_dtype
+        b = AuBatch(len(events), int(prec), int(trace_dtype), int(flags), int(fs_hz), int(band_lo_hz),
+                    int(band_hi_hz), float(fallback_rel), float(singular_rel),
+                    s.ctypes.data_as(C.POINTER(C.c_int32)), n.ctypes.data_as(C.POINTER(C.c_int32)),
+                    dcount.ctypes.data_as(C.POINTER(C.c_int32)), dirs.ctypes.data_as(C.POINTER(C.c_double)),
+                    self.volt_offsets.ctypes.data_as(C.POINTER(C.c_int64)),
+                    self.efield_offsets.ctypes.data_as(C.POINTER(C.c_int64)))
+        h = C.c_void_p()
+        _check(lib().au_plan_create(table.handle, C.byref(b), C.byref(h)))
+        self.handle = h
+        u = C.c_uint64()
+        _check(lib().au_plan_units(h, C.byref(u)))
+        self.station_unfolds = u.value
+
+    def run(self, volt, efield, counts=None, stream=None):
+        if volt.numel() < self.volt_elems or efield.numel() < self.efield_elems:
+            raise ValueError("buffers smaller than the plan's offsets require")
+        if trace_code(volt) != self.trace_dtype or efield.dtype != out_dtype(self.prec):
+            raise ValueError("buffer dtypes do not match the plan")
+        _check(lib().au_plan_run(self.handle, _ptr(volt), _ptr(efield), _stream_handle(stream), _ptr(counts)))
+
+    def set_timing(self, enable: bool):
+        _check(lib().au_plan_timing(self.handle, 1 if enable else 0))
+
+    def classes(self):
+        """[(n_samples, station_unfolds)] per trace-length class, in stage order."""
+        nc = C.c_int32()
+        _check(lib().au_plan_classes(self.handle, 0, None, None, C.byref(nc)))
+        ns = (C.c_int32 * max(nc.value, 1))()
+        su = (C.c_uint64 * max(nc.value, 1))()
+        _check(lib().au_plan_classes(self.handle, nc.value, ns, su, C.byref(nc)))
+        return [(ns[i], su[i]) for i in range(nc.value)]
+
+    def stage_ms(self):
+        """(per-class [spectrum, coef, unfold] summed ms, number of timed runs)."""
+        nc = len(self.classes())
+        ms = (C.c_double * (3 * nc))()
+        runs = C.c_uint64()
+        _check(lib().au_plan_stage_ms(self.handle, 3 * nc, ms, C.byref(runs)))
+        return np.array(ms[:]).reshape(nc, 3), runs.value
+
+    def event_output(self, efield, e: int):
+        n, s, d = int(self.n_samples[e]), int(self.n_stations[e]), int(self.n_dirs[e])
+        o = int(self.efield_offsets[e])
+        return efield[o:o + d * s * 2 * n].view(d, s, 2, n)
+
+    def free(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _check(lib().au_plan_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

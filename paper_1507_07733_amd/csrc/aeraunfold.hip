@@ -1,0 +1,1245 @@
+// aeraunfold.hip -- kernels, launch dispatch and the C ABI of the unfolding
+// library (declarations and contracts in include/aeraunfold.h).
+//
+// Path per event (arXiv:1507.07733, section 2, the E-field step of the
+// reconstruction; section 3 pattern interpolation; section 4 FFTs; band of
+// section 1):
+//   k_spectrum  once per station       V[2][N] -> X_0, X_1 at in-band bins
+//   k_coef      once per direction     H(f_k) interpolated, inverted -> coef
+//   k_unfold    per direction x station coef * X -> packed iFFT -> E_theta, E_phi
+// k_unfold writes the only large data stream (2 N values per station and
+// direction), so the whole path is bound by HBM write bandwidth when the
+// FFT keeps up.
+#include "aeraunfold.h"
+#include "au_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace au;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static au_status fail(au_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(AU_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+extern "C" const char* au_last_error(void) { return g_err.c_str(); }
+extern "C" const char* au_version(void) { return "aeraunfold 0.1 gfx950"; }
+
+// ---------------------------------------------------------------------------
+// device helpers: pattern-grid cells (section 3: linear interpolation
+// between frequency / zenith / azimuth nodes)
+// ---------------------------------------------------------------------------
+
+// Zenith cell and weight; positions outside the grid are clamped to it.
+// Azimuth cell, its periodic neighbour and weight.
+__device__ __forceinline__ void angle_cells(const GridDev& g, double zen, double az, int& iz,
+                                            double& tz, int& ia, int& ja, double& ta)
+{
+    double v = (zen - g.zen0) / g.dzen;
+    v = v < 0.0 ? 0.0 : v;
+    v = v > (double)(g.n_zen - 1) ? (double)(g.n_zen - 1) : v;
+    int i = (int)floor(v);
+    if (i > g.n_zen - 2) i = g.n_zen - 2;
+    iz = i;
+    tz = v - (double)i;
+    double w = fmod(az - g.az0, 360.0);
+    if (w < 0.0) w += 360.0;
+    w = w / g.daz;
+    const double fl = floor(w);
+    const int a = ((int)fl) % g.n_az;
+    ia = a;
+    ja = (a + 1 == g.n_az) ? 0 : a + 1;
+    ta = w - fl;
+}
+
+// Frequency cell of FFT bin k (N samples at fs): node position
+// (k fs - f0 N) / (N df), split exactly into integer part and remainder.
+__device__ __forceinline__ void freq_cell(const GridDev& g, int64_t k, int n, int64_t fs, int& ifr,
+                                          double& tf)
+{
+    const int64_t num = k * fs - g.f0_hz * (int64_t)n;
+    const int64_t den = (int64_t)n * g.df_hz;
+    int64_t i = num / den;
+    const int64_t r = num - i * den;
+    double t = (double)r / (double)den;
+    if (i > g.n_freq - 2) {
+        i = g.n_freq - 2;
+        t = 1.0;
+    }
+    ifr = (int)i;
+    tf = t;
+}
+
+template <typename T>
+__device__ __forceinline__ C2<T> clerp(C2<T> a, C2<T> b, T t)
+{
+    const T s = (T)1 - t;
+    return {s * a.re + t * b.re, s * a.im + t * b.im};
+}
+
+// Trilinear interpolation of the four (channel, component) entries: along
+// azimuth, then zenith, then frequency.  Table layout [f][z][a][4] complex.
+template <typename Tt, typename T>
+__device__ __forceinline__ void interp4(const C2<Tt>* __restrict__ nodes, const GridDev& g, int ifr,
+                                        T tf, int iz, T tz, int ia, int ja, T ta, C2<T> h[4])
+{
+    C2<T> fz[2][4];
+#pragma unroll
+    for (int df = 0; df < 2; ++df) {
+        C2<T> za[2][4];
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz) {
+            const int64_t row = ((int64_t)(ifr + df) * g.n_zen + (iz + dz)) * g.n_az;
+            const C2<Tt>* p0 = nodes + (row + ia) * 4;
+            const C2<Tt>* p1 = nodes + (row + ja) * 4;
+#pragma unroll
+            for (int cp = 0; cp < 4; ++cp) {
+                const C2<T> a0{(T)p0[cp].re, (T)p0[cp].im};
+                const C2<T> a1{(T)p1[cp].re, (T)p1[cp].im};
+                za[dz][cp] = clerp(a0, a1, ta);
+            }
+        }
+#pragma unroll
+        for (int cp = 0; cp < 4; ++cp) fz[df][cp] = clerp(za[0][cp], za[1][cp], tz);
+    }
+#pragma unroll
+    for (int cp = 0; cp < 4; ++cp) h[cp] = clerp(fz[0][cp], fz[1][cp], tf);
+}
+
+// Coefficients of the bin: (1/N) H^-1 = (1/(N det)) [h3 -h1; -h2 h0], with
+// H = [h0 h1; h2 h3] indexed [channel][component].  Returns 1 if singular.
+template <typename T>
+__device__ __forceinline__ int invert2(const C2<T> h[4], T inv_n, double singular_rel, MBin<T>& m)
+{
+    const C2<T> det = csub(cmul(h[0], h[3]), cmul(h[1], h[2]));
+    T fro2 = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) fro2 += h[i].re * h[i].re + h[i].im * h[i].im;
+    const T ad2 = det.re * det.re + det.im * det.im;
+    const T thr = (T)singular_rel * fro2;
+    if (!(ad2 > thr * thr)) {
+        m.m00 = m.m01 = m.m10 = m.m11 = C2<T>{0, 0};
+        return 1;
+    }
+    const T sc = inv_n / ad2;
+    const C2<T> inv{det.re * sc, -det.im * sc};
+    m.m00 = cmul(h[3], inv);
+    m.m01 = cmul(C2<T>{-h[1].re, -h[1].im}, inv);
+    m.m10 = cmul(C2<T>{-h[2].re, -h[2].im}, inv);
+    m.m11 = cmul(h[0], inv);
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+// Spectra of one station per FFT group: z = V_0 + i V_1, Z = FFT(z), and at
+// each in-band bin X_0 = (Z[k] + conj Z[N-k]) / 2, X_1 = (Z[k] - conj Z[N-k]) / 2i.
+// Units: (event, station); units == nullptr means event ev0, unit = station.
+template <typename Tin, typename T, int N, int E>
+__global__ __launch_bounds__(kBlock) void k_spectrum(const Tin* __restrict__ volt, EvDesc ev0,
+                                                     const EvDesc* __restrict__ evs,
+                                                     const int2* __restrict__ units, int n_units,
+                                                     XBin<T>* __restrict__ X,
+                                                     const C2<T>* __restrict__ tw)
+{
+    constexpr int TT = N / E;
+    constexpr int G = groups_per_block<T, N, E>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int g = threadIdx.x / TT, t = threadIdx.x % TT;
+    C2<T>* lds = reinterpret_cast<C2<T>*>(smem) + g * N;
+    const int u = blockIdx.x * G + g;
+    const bool active = u < n_units;
+    int e = 0, s = active ? u : 0;
+    if (units != nullptr && active) {
+        const int2 w = units[u];
+        e = w.x;
+        s = w.y;
+    }
+    const EvDesc ev = evs ? evs[e] : ev0;
+    const Tin* v = volt + ev.volt_off + (int64_t)s * 2 * N;
+    C2<T> x[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int n = t + TT * i;
+        x[i] = active ? C2<T>{(T)v[n], (T)v[N + n]} : C2<T>{0, 0};
+    }
+    fft<T, N, E, -1>(x, lds, tw, t);
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds[t + TT * i] = x[i];
+    __syncthreads();
+    if (active) {
+        XBin<T>* out = X + ev.x_off + (int64_t)s * ev.nb;
+        for (int j = t; j < ev.nb; j += TT) {
+            const int k = ev.k_lo + j;
+            const C2<T> a = lds[k];
+            const C2<T> b = lds[(N - k) & (N - 1)];
+            XBin<T> r;
+            r.x0 = C2<T>{(T)0.5 * (a.re + b.re), (T)0.5 * (a.im - b.im)};
+            r.x1 = C2<T>{(T)0.5 * (a.im + b.im), (T)0.5 * (b.re - a.re)};
+            out[j] = r;
+        }
+    }
+}
+
+// Coefficients of every in-band bin of one (event, direction) per block.
+// FP32 (T = float): interpolation, determinant and inverse in float; where
+// |det| < fallback_rel ||H||_F^2 in float, the determinant and inverse are
+// redone in double from the same float H.  Singular bins give zero coefs.
+// RESP: write the interpolated H instead (au_pattern_response).
+template <typename Tt, typename T, bool RESP>
+__global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ nodes, GridDev gd,
+                                                 EvDesc ev0, const EvDesc* __restrict__ evs,
+                                                 const int2* __restrict__ units,
+                                                 const double* __restrict__ dirs, double zen1,
+                                                 double az1, int64_t fs, double fallback_rel,
+                                                 double singular_rel, MBin<T>* __restrict__ M,
+                                                 unsigned long long* __restrict__ counts)
+{
+    __shared__ unsigned int cnt[2];
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int e = 0, d = blockIdx.x;
+    if (units != nullptr) {
+        const int2 w = units[blockIdx.x];
+        e = w.x;
+        d = w.y;
+    }
+    const EvDesc ev = evs ? evs[e] : ev0;
+    double zen = zen1, az = az1;
+    if (dirs != nullptr) {
+        zen = dirs[2 * (ev.dir_off + d)];
+        az = dirs[2 * (ev.dir_off + d) + 1];
+    }
+    int iz, ia, ja;
+    double tz, ta;
+    angle_cells(gd, zen, az, iz, tz, ia, ja, ta);
+    const T inv_n = (T)(1.0 / (double)ev.N);
+    unsigned int n_fb = 0, n_sg = 0;
+    MBin<T>* out = M + ev.m_off + (int64_t)d * ev.nb;
+    for (int j = threadIdx.x; j < ev.nb; j += blockDim.x) {
+        int ifr;
+        double tf;
+        freq_cell(gd, (int64_t)(ev.k_lo + j), ev.N, fs, ifr, tf);
+        C2<T> h[4];
+        interp4<Tt, T>(nodes, gd, ifr, (T)tf, iz, (T)tz, ia, ja, (T)ta, h);
+        MBin<T> m;
+        if constexpr (RESP) {
+            m.m00 = h[0];
+            m.m01 = h[1];
+            m.m10 = h[2];
+            m.m11 = h[3];
+        } else if constexpr (sizeof(T) == 4) {
+            const C2<float> det = csub(cmul(h[0], h[3]), cmul(h[1], h[2]));
+            float fro2 = 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fro2 += h[i].re * h[i].re + h[i].im * h[i].im;
+            const float ad2 = det.re * det.re + det.im * det.im;
+            const float thr = (float)fallback_rel * fro2;
+            if (ad2 < thr * thr) {
+                C2<double> hd[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) hd[i] = C2<double>{(double)h[i].re, (double)h[i].im};
+                MBin<double> md;
+                n_sg += invert2<double>(hd, 1.0 / (double)ev.N, singular_rel, md);
+                ++n_fb;
+                m.m00 = C2<T>{(T)md.m00.re, (T)md.m00.im};
+                m.m01 = C2<T>{(T)md.m01.re, (T)md.m01.im};
+                m.m10 = C2<T>{(T)md.m10.re, (T)md.m10.im};
+                m.m11 = C2<T>{(T)md.m11.re, (T)md.m11.im};
+            } else {
+                n_sg += invert2<T>(h, inv_n, singular_rel, m);
+            }
+        } else {
+            n_sg += invert2<T>(h, inv_n, singular_rel, m);
+        }
+        out[j] = m;
+    }
+    if (!RESP && counts != nullptr) {
+        if (n_fb) atomicAdd(&cnt[0], n_fb);
+        if (n_sg) atomicAdd(&cnt[1], n_sg);
+        __syncthreads();
+        if (threadIdx.x < 2 && cnt[threadIdx.x])
+            atomicAdd(&counts[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+    }
+}
+
+// E-field traces of one (event, direction, station range) per block; each
+// FFT group takes one station at a time.  With `counter` non-null the grid
+// is persistent and blocks take units from the atomic counter until the
+// list is exhausted (every block leaves through the same check).
+template <typename T, int N, int E>
+__global__ __launch_bounds__(kBlock) void k_unfold(EvDesc ev0, const EvDesc* __restrict__ evs,
+                                                   const int4* __restrict__ units, int n_units,
+                                                   int spw, const XBin<T>* __restrict__ X,
+                                                   const MBin<T>* __restrict__ M,
+                                                   T* __restrict__ efield,
+                                                   const C2<T>* __restrict__ tw,
+                                                   unsigned int* __restrict__ counter)
+{
+    constexpr int TT = N / E;
+    constexpr int G = groups_per_block<T, N, E>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int sh_u;
+    const int g = threadIdx.x / TT, t = threadIdx.x % TT;
+    C2<T>* lds = reinterpret_cast<C2<T>*>(smem) + g * N;
+    for (int iter = 0;; ++iter) {
+        int u;
+        if (counter != nullptr) {
+            if (threadIdx.x == 0) sh_u = (int)atomicAdd(counter, 1u);
+            __syncthreads();
+            u = sh_u;
+            __syncthreads();
+        } else {
+            if (iter > 0) break;
+            u = blockIdx.x;
+        }
+        if (u >= n_units) break;
+        int e = 0, d, s0, s1;
+        if (units != nullptr) {
+            const int4 w = units[u];
+            e = w.x;
+            d = w.y;
+            s0 = w.z;
+            s1 = w.w;
+        } else {
+            const int chunks = (ev0.S + spw - 1) / spw;
+            d = u / chunks;
+            s0 = (u - d * chunks) * spw;
+            s1 = min(ev0.S, s0 + spw);
+        }
+        const EvDesc ev = evs ? evs[e] : ev0;
+        const MBin<T>* Md = M + ev.m_off + (int64_t)d * ev.nb;
+        for (int base = s0; base < s1; base += G) {
+            const int s = base + g;
+            const bool active = s < s1;
+            const XBin<T>* Xs = X + ev.x_off + (int64_t)s * ev.nb;
+            C2<T> x[E];
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int k = t + TT * i;
+                const int kk = (k <= N / 2) ? k : N - k;
+                const int j = kk - ev.k_lo;
+                C2<T> z{0, 0};
+                if (active && j >= 0 && j < ev.nb) {
+                    const MBin<T> m = Md[j];
+                    const XBin<T> xb = Xs[j];
+                    C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
+                    C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
+                    if (k == 0) {
+                        et.im = 0;
+                        ep.im = 0;
+                    }
+                    // Z[k] = E_th[k] + i E_ph[k];  Z[N-k] = conj E_th[k] + i conj E_ph[k]
+                    z = (k <= N / 2) ? C2<T>{et.re - ep.im, et.im + ep.re}
+                                     : C2<T>{et.re + ep.im, ep.re - et.im};
+                }
+                x[i] = z;
+            }
+            fft<T, N, E, +1>(x, lds, tw, t);
+            if (active) {
+                T* out = efield + ev.efield_off + ((int64_t)d * ev.S + s) * 2 * N;
+#pragma unroll
+                for (int i = 0; i < E; ++i) {
+                    __builtin_nontemporal_store(x[i].re, out + t + TT * i);
+                    __builtin_nontemporal_store(x[i].im, out + N + t + TT * i);
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_zero_u32(unsigned int* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// launch dispatch over N (compile-time FFT sizes)
+// ---------------------------------------------------------------------------
+
+#define AU_FOR_EACH_N(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+// Values per thread of the FFTs, per N.
+constexpr int kE = 16;
+
+template <typename T, int N>
+struct Shape {
+    static constexpr int E = kE;
+    static constexpr int TT = N / E;
+    static constexpr int G = groups_per_block<T, N, E>();
+    static constexpr int BLOCK = G * TT;
+    static constexpr size_t LDS = (size_t)G * N * sizeof(C2<T>);
+};
+
+template <typename Tin, typename T, int N>
+static hipError_t launch_spectrum_n(hipStream_t st, const Tin* volt, const EvDesc& ev0,
+                                    const EvDesc* evs, const int2* units, int n_units, XBin<T>* X,
+                                    const C2<T>* tw)
+{
+    using S = Shape<T, N>;
+    if (n_units <= 0) return hipSuccess;
+    const int grid = (n_units + S::G - 1) / S::G;
+    hipLaunchKernelGGL((k_spectrum<Tin, T, N, S::E>), dim3(grid), dim3(S::BLOCK), S::LDS, st, volt,
+                       ev0, evs, units, n_units, X, tw);
+    return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t launch_unfold_n(hipStream_t st, const EvDesc& ev0, const EvDesc* evs,
+                                  const int4* units, int n_units, int spw, const XBin<T>* X,
+                                  const MBin<T>* M, T* efield, const C2<T>* tw,
+                                  unsigned int* counter, int persistent_blocks)
+{
+    using S = Shape<T, N>;
+    if (n_units <= 0) return hipSuccess;
+    int grid = n_units;
+    if (counter != nullptr) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counter, 1);
+        grid = std::min(n_units, persistent_blocks);
+    }
+    hipLaunchKernelGGL((k_unfold<T, N, S::E>), dim3(grid), dim3(S::BLOCK), S::LDS, st, ev0, evs,
+                       units, n_units, spw, X, M, efield, tw, counter);
+    return hipGetLastError();
+}
+
+template <typename Tin, typename T>
+static hipError_t launch_spectrum(int n, hipStream_t st, const Tin* volt, const EvDesc& ev0,
+                                  const EvDesc* evs, const int2* units, int n_units, XBin<T>* X,
+                                  const C2<T>* tw)
+{
+    switch (n) {
+#define X_(NN) \
+    case NN: return launch_spectrum_n<Tin, T, NN>(st, volt, ev0, evs, units, n_units, X, tw);
+        AU_FOR_EACH_N(X_)
+#undef X_
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t launch_unfold(int n, hipStream_t st, const EvDesc& ev0, const EvDesc* evs,
+                                const int4* units, int n_units, int spw, const XBin<T>* X,
+                                const MBin<T>* M, T* efield, const C2<T>* tw, unsigned int* counter,
+                                int persistent_blocks)
+{
+    switch (n) {
+#define X_(NN)                                                                                  \
+    case NN:                                                                                    \
+        return launch_unfold_n<T, NN>(st, ev0, evs, units, n_units, spw, X, M, efield, tw,      \
+                                      counter, persistent_blocks);
+        AU_FOR_EACH_N(X_)
+#undef X_
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static int persistent_blocks_for(int n, int device)
+{
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    int per_cu = 1;
+    switch (n) {
+#define X_(NN)                                                                               \
+    case NN: {                                                                               \
+        int occ = 0;                                                                         \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_unfold<T, NN, Shape<T, NN>::E>, \
+                                                         Shape<T, NN>::BLOCK,                \
+                                                         Shape<T, NN>::LDS) == hipSuccess && \
+            occ > 0)                                                                         \
+            per_cu = occ;                                                                    \
+        break;                                                                               \
+    }
+        AU_FOR_EACH_N(X_)
+#undef X_
+    }
+    return cus * per_cu;
+}
+
+// ---------------------------------------------------------------------------
+// twiddle tables, one pair (float, double) per device
+// ---------------------------------------------------------------------------
+
+static std::mutex g_mu;
+constexpr int kMaxDev = 64;
+static C2<float>* g_tw32[kMaxDev];
+static C2<double>* g_tw64[kMaxDev];
+
+// exp(+2 pi i q / n) in long double, reduced to the first octant so that
+// quarter turns are exact and the libm argument stays small.
+static void unit_root(int q, int n, long double& c, long double& s)
+{
+    q = ((q % n) + n) % n;
+    const int quarter = n / 4;
+    const int quad = q / quarter, r = q % quarter;
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    long double cr, sr;
+    if (2 * r <= quarter) {
+        const long double a = two_pi * (long double)r / (long double)n;
+        cr = cosl(a);
+        sr = sinl(a);
+    } else {
+        const long double a = two_pi * (long double)(quarter - r) / (long double)n;
+        cr = sinl(a);
+        sr = cosl(a);
+    }
+    switch (quad) {
+        case 0: c = cr; s = sr; break;
+        case 1: c = -sr; s = cr; break;
+        case 2: c = -cr; s = -sr; break;
+        default: c = sr; s = -cr; break;
+    }
+}
+
+static au_status ensure_twiddles(int dev)
+{
+    if (dev < 0 || dev >= kMaxDev) return fail(AU_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_tw32[dev] != nullptr) return AU_OK;
+    std::vector<C2<float>> h32(kTwN);
+    std::vector<C2<double>> h64(kTwN);
+    for (int q = 0; q < kTwN; ++q) {
+        long double c, s;
+        unit_root(q, kTwN, c, s);
+        h64[q] = C2<double>{(double)c, (double)-s};
+        h32[q] = C2<float>{(float)c, (float)-s};
+    }
+    void *p32 = nullptr, *p64 = nullptr;
+    HIP_TRY(hipMalloc(&p32, sizeof(C2<float>) * kTwN));
+    HIP_TRY(hipMalloc(&p64, sizeof(C2<double>) * kTwN));
+    HIP_TRY(hipMemcpy(p32, h32.data(), sizeof(C2<float>) * kTwN, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p64, h64.data(), sizeof(C2<double>) * kTwN, hipMemcpyHostToDevice));
+    g_tw32[dev] = (C2<float>*)p32;
+    g_tw64[dev] = (C2<double>*)p64;
+    return AU_OK;
+}
+
+template <typename T>
+static const C2<T>* twiddles(int dev);
+template <>
+const C2<float>* twiddles<float>(int dev) { return g_tw32[dev]; }
+template <>
+const C2<double>* twiddles<double>(int dev) { return g_tw64[dev]; }
+
+// ---------------------------------------------------------------------------
+// pattern table
+// ---------------------------------------------------------------------------
+
+struct au_table {
+    int device;
+    int dtype;
+    GridDev g;
+    void* d_nodes;
+    size_t bytes;
+};
+
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+extern "C" au_status au_load_pattern_table(const au_grid* grid, int32_t dtype, const void* h_vel,
+                                           au_table** out)
+{
+    if (!grid || !h_vel || !out) return fail(AU_EINVAL, "null argument");
+    if (dtype != AU_F32 && dtype != AU_F64) return fail(AU_EINVAL, "table dtype must be AU_F32 or AU_F64");
+    const au_grid& G = *grid;
+    if (G.n_freq < 2 || G.n_zen < 2 || G.n_az < 2)
+        return fail(AU_EINVAL, "grid needs at least 2 nodes per axis");
+    if (G.df_hz <= 0 || G.f0_hz < 0 || !finite_pos(G.dzen_deg) || !finite_pos(G.daz_deg) ||
+        !std::isfinite(G.zen0_deg) || !std::isfinite(G.az0_deg))
+        return fail(AU_EINVAL, "grid steps must be positive and finite");
+    const int nf = G.n_freq, nz = G.n_zen, na = G.n_az;
+    const size_t esz = dtype == AU_F64 ? 16 : 8;
+    const size_t col = (size_t)nz * na;
+    int na_eff = na;
+    if (std::fabs(na * G.daz_deg - 360.0) <= 1e-9 * 360.0) {
+        na_eff = na;
+    } else if (std::fabs((na - 1) * G.daz_deg - 360.0) <= 1e-9 * 360.0) {
+        // duplicated 360-degree column: accepted only if equal to column 0
+        const unsigned char* b = (const unsigned char*)h_vel;
+        for (size_t cpf = 0; cpf < (size_t)4 * nf * nz; ++cpf) {
+            const unsigned char* row = b + cpf * na * esz;
+            if (std::memcmp(row, row + (size_t)(na - 1) * esz, esz) != 0)
+                return fail(AU_EINVAL, "last azimuth column duplicates 360 deg but differs from column 0");
+        }
+        na_eff = na - 1;
+    } else {
+        return fail(AU_EINVAL, "azimuth grid must cover 360 degrees periodically (n_az * daz == 360)");
+    }
+    if (na_eff < 2) return fail(AU_EINVAL, "azimuth grid too small");
+    (void)col;
+    const size_t n_nodes = (size_t)nf * nz * na_eff;
+    std::vector<unsigned char> host(n_nodes * 4 * esz);
+    const unsigned char* src = (const unsigned char*)h_vel;
+    for (int cp = 0; cp < 4; ++cp)
+        for (int f = 0; f < nf; ++f)
+            for (int z = 0; z < nz; ++z)
+                for (int a = 0; a < na_eff; ++a) {
+                    const size_t si = (((size_t)cp * nf + f) * nz + z) * na + a;
+                    const size_t di = (((size_t)f * nz + z) * na_eff + a) * 4 + cp;
+                    std::memcpy(&host[di * esz], src + si * esz, esz);
+                }
+    for (size_t i = 0; i < host.size() / (esz / 2); ++i) {
+        const double v = esz == 16 ? ((const double*)host.data())[i] : ((const float*)host.data())[i];
+        if (!std::isfinite(v)) return fail(AU_EINVAL, "pattern table holds a non-finite value");
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    au_status st = ensure_twiddles(dev);
+    if (st != AU_OK) return st;
+    au_table* t = new au_table();
+    t->device = dev;
+    t->dtype = dtype;
+    t->g = GridDev{nf, nz, na_eff, 0, G.f0_hz, G.df_hz, G.zen0_deg, G.dzen_deg, G.az0_deg, G.daz_deg};
+    t->bytes = host.size();
+    hipError_t e = hipMalloc(&t->d_nodes, t->bytes);
+    if (e != hipSuccess) {
+        delete t;
+        return fail(AU_ENOMEM, std::string("hipMalloc(table): ") + hipGetErrorString(e));
+    }
+    e = hipMemcpy(t->d_nodes, host.data(), t->bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(t->d_nodes);
+        delete t;
+        return fail(AU_EDEVICE, std::string("hipMemcpy(table): ") + hipGetErrorString(e));
+    }
+    *out = t;
+    return AU_OK;
+}
+
+extern "C" au_status au_free_pattern_table(au_table* t)
+{
+    if (!t) return AU_OK;
+    if (t->d_nodes) HIP_TRY(hipFree(t->d_nodes));
+    delete t;
+    return AU_OK;
+}
+
+// ---------------------------------------------------------------------------
+// event validation and the band
+// ---------------------------------------------------------------------------
+
+struct EvParams {
+    int S, N, k_lo, nb;
+};
+
+static au_status band_of(int64_t n, int64_t fs, int64_t lo, int64_t hi, int* k_lo, int* nb)
+{
+    const int64_t klo = (lo * n + fs - 1) / fs;  // smallest k with k fs >= lo n
+    const int64_t khi = (hi * n) / fs;           // largest k with k fs <= hi n
+    *k_lo = (int)klo;
+    *nb = khi >= klo ? (int)(khi - klo + 1) : 0;
+    return AU_OK;
+}
+
+static au_status check_common(const au_table* tb, int64_t fs, int64_t lo, int64_t hi, int prec,
+                              int tin, double fb, double sg)
+{
+    if (!tb) return fail(AU_EINVAL, "null table");
+    if (fs <= 0 || fs > (int64_t)1000000000000000LL) return fail(AU_EINVAL, "fs_hz out of range");
+    if (lo < 0 || hi < lo || 2 * hi >= fs) return fail(AU_EINVAL, "band must satisfy 0 <= lo <= hi < fs/2");
+    if (prec != AU_PREC_FP32 && prec != AU_PREC_FP64) return fail(AU_EINVAL, "prec must be AU_PREC_FP32 or AU_PREC_FP64");
+    if (tin != AU_F32 && tin != AU_F64) return fail(AU_EINVAL, "trace_dtype must be AU_F32 or AU_F64");
+    if (prec == AU_PREC_FP64 && tb->dtype != AU_F64)
+        return fail(AU_EINVAL, "FP64 precision needs a complex128 pattern table");
+    if (!(fb >= 0.0) || !std::isfinite(fb) || !(sg >= 0.0) || !std::isfinite(sg))
+        return fail(AU_EINVAL, "fallback_rel and singular_rel must be finite and >= 0");
+    return AU_OK;
+}
+
+static au_status check_n(const au_table* tb, int s, int n, int64_t fs, int64_t lo, int64_t hi,
+                         EvParams* p)
+{
+    if (n < 16 || n > 4096 || (n & (n - 1)) != 0)
+        return fail(AU_EINVAL, "n_samples must be a power of two in [16, 4096]");
+    if (s < 1) return fail(AU_EINVAL, "n_stations must be >= 1");
+    int k_lo, nb;
+    band_of(n, fs, lo, hi, &k_lo, &nb);
+    if (nb > 0) {
+        const GridDev& g = tb->g;
+        const int64_t den = (int64_t)n * g.df_hz;
+        const int64_t num_lo = (int64_t)k_lo * fs - g.f0_hz * n;
+        const int64_t num_hi = (int64_t)(k_lo + nb - 1) * fs - g.f0_hz * n;
+        if (num_lo < 0 || num_hi > (int64_t)(g.n_freq - 1) * den)
+            return fail(AU_EINVAL, "band lies outside the pattern table's frequency range");
+    }
+    p->S = s;
+    p->N = n;
+    p->k_lo = k_lo;
+    p->nb = nb;
+    return AU_OK;
+}
+
+static au_status check_event(const au_table* tb, const au_event* ev, EvParams* p)
+{
+    if (!ev) return fail(AU_EINVAL, "null event");
+    au_status st = check_common(tb, ev->fs_hz, ev->band_lo_hz, ev->band_hi_hz, ev->prec,
+                                ev->trace_dtype, ev->fallback_rel, ev->singular_rel);
+    if (st != AU_OK) return st;
+    return check_n(tb, ev->n_stations, ev->n_samples, ev->fs_hz, ev->band_lo_hz, ev->band_hi_hz, p);
+}
+
+static bool dirs_finite(const double* h, int64_t n)
+{
+    for (int64_t i = 0; i < 2 * n; ++i)
+        if (!std::isfinite(h[i]) || std::fabs(h[i]) > 1e6) return false;
+    return true;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WsLayout {
+    size_t x, m, dirs, total;
+};
+
+static WsLayout ws_layout(const EvParams& p, int prec, int n_dir)
+{
+    const size_t xb = prec == AU_PREC_FP64 ? sizeof(XBin<double>) : sizeof(XBin<float>);
+    const size_t mb = prec == AU_PREC_FP64 ? sizeof(MBin<double>) : sizeof(MBin<float>);
+    WsLayout w;
+    w.x = align256((size_t)p.S * p.nb * xb + 1);
+    w.m = align256((size_t)n_dir * p.nb * mb + 1);
+    w.dirs = align256((size_t)n_dir * 2 * sizeof(double) + 1);
+    w.total = w.x + w.m + w.dirs;
+    return w;
+}
+
+extern "C" au_status au_band_bins(const au_event* ev, int32_t* k_lo, int32_t* n_band)
+{
+    if (!ev || !k_lo || !n_band) return fail(AU_EINVAL, "null argument");
+    if (ev->fs_hz <= 0 || ev->band_lo_hz < 0 || ev->band_hi_hz < ev->band_lo_hz)
+        return fail(AU_EINVAL, "bad band");
+    int a, b;
+    band_of(ev->n_samples, ev->fs_hz, ev->band_lo_hz, ev->band_hi_hz, &a, &b);
+    *k_lo = a;
+    *n_band = b;
+    return AU_OK;
+}
+
+extern "C" au_status au_workspace_bytes(const au_table* tb, const au_event* ev, int32_t n_dir,
+                                        uint64_t* bytes)
+{
+    if (!bytes) return fail(AU_EINVAL, "null argument");
+    EvParams p;
+    au_status st = check_event(tb, ev, &p);
+    if (st != AU_OK) return st;
+    if (n_dir < 1) return fail(AU_EINVAL, "n_dir must be >= 1");
+    *bytes = ws_layout(p, ev->prec, n_dir).total;
+    return AU_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single-event path: spectra, coefficients, unfold as three launches
+// ---------------------------------------------------------------------------
+
+constexpr int kStationsPerUnit = 8;
+
+template <typename Tt, typename T>
+static void launch_coef(hipStream_t st, const au_table* tb, const EvDesc& ev0, const EvDesc* evs,
+                        const int2* units, int n_units, const double* dirs, double zen, double az,
+                        int64_t fs, double fb, double sg, MBin<T>* M, unsigned long long* counts)
+{
+    hipLaunchKernelGGL((k_coef<Tt, T, false>), dim3(n_units), dim3(kBlock), 0, st,
+                       (const C2<Tt>*)tb->d_nodes, tb->g, ev0, evs, units, dirs, zen, az, fs, fb, sg,
+                       M, counts);
+}
+
+template <typename T>
+static au_status run_event(const au_table* tb, const au_event* ev, const EvParams& p,
+                           const void* d_volt, int n_dir, const double* h_dirs, double zen,
+                           double az, void* d_efield, void* d_work, hipStream_t st,
+                           uint64_t* d_counts)
+{
+    const WsLayout w = ws_layout(p, ev->prec, n_dir);
+    unsigned char* base = (unsigned char*)d_work;
+    XBin<T>* X = (XBin<T>*)base;
+    MBin<T>* M = (MBin<T>*)(base + w.x);
+    double* dirs = (double*)(base + w.x + w.m);
+    if (h_dirs != nullptr)
+        HIP_TRY(hipMemcpyAsync(dirs, h_dirs, sizeof(double) * 2 * n_dir, hipMemcpyHostToDevice, st));
+    EvDesc ev0{};
+    ev0.S = p.S;
+    ev0.N = p.N;
+    ev0.D = n_dir;
+    ev0.k_lo = p.k_lo;
+    ev0.nb = p.nb;
+    const C2<T>* tw = twiddles<T>(tb->device);
+    if (tw == nullptr) return fail(AU_EDEVICE, "twiddle tables missing on this device");
+    hipError_t e;
+    if (ev->trace_dtype == AU_F64)
+        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+    else
+        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
+    unsigned long long* cnt = (unsigned long long*)d_counts;
+    if (tb->dtype == AU_F64)
+        launch_coef<double, T>(st, tb, ev0, nullptr, nullptr, n_dir, h_dirs ? dirs : nullptr, zen,
+                               az, ev->fs_hz, ev->fallback_rel, ev->singular_rel, M,
+                               cnt);
+    else
+        launch_coef<float, T>(st, tb, ev0, nullptr, nullptr, n_dir, h_dirs ? dirs : nullptr, zen, az,
+                              ev->fs_hz, ev->fallback_rel, ev->singular_rel, M, cnt);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_coef: ") + hipGetErrorString(e));
+    const int chunks = (p.S + kStationsPerUnit - 1) / kStationsPerUnit;
+    const int64_t n_units = (int64_t)n_dir * chunks;
+    if (n_units > (int64_t)0x7fffffff) return fail(AU_EINVAL, "too many work units");
+    e = launch_unfold<T>(p.N, st, ev0, nullptr, nullptr, (int)n_units, kStationsPerUnit, X, M,
+                         (T*)d_efield, tw, nullptr, 0);
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_unfold: ") + hipGetErrorString(e));
+    return AU_OK;
+}
+
+static au_status unfold_common(const au_table* tb, const au_event* ev, const void* d_volt,
+                               int32_t n_dir, const double* h_dirs, double zen, double az,
+                               void* d_efield, void* d_work, uint64_t work_bytes, void* stream,
+                               uint64_t* d_counts)
+{
+    EvParams p;
+    au_status s = check_event(tb, ev, &p);
+    if (s != AU_OK) return s;
+    if (!d_volt || !d_efield) return fail(AU_EINVAL, "null trace or output pointer");
+    if (n_dir < 1) return fail(AU_EINVAL, "n_dir must be >= 1");
+    if (h_dirs != nullptr && !dirs_finite(h_dirs, n_dir))
+        return fail(AU_EINVAL, "directions must be finite");
+    if (h_dirs == nullptr && (!std::isfinite(zen) || !std::isfinite(az) || std::fabs(az) > 1e6))
+        return fail(AU_EINVAL, "direction must be finite");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != tb->device) return fail(AU_EINVAL, "table lives on another device");
+    const WsLayout w = ws_layout(p, ev->prec, n_dir);
+    hipStream_t st = (hipStream_t)stream;
+    void* work = d_work;
+    bool pooled = false;
+    if (work == nullptr) {
+        hipError_t e = hipMallocAsync(&work, w.total, st);
+        if (e != hipSuccess) return fail(AU_ENOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        pooled = true;
+    } else if (work_bytes < w.total) {
+        return fail(AU_ENOMEM, "workspace smaller than au_workspace_bytes");
+    }
+    if (ev->prec == AU_PREC_FP64)
+        s = run_event<double>(tb, ev, p, d_volt, n_dir, h_dirs, zen, az, d_efield, work, st, d_counts);
+    else
+        s = run_event<float>(tb, ev, p, d_volt, n_dir, h_dirs, zen, az, d_efield, work, st, d_counts);
+    if (pooled) {
+        hipError_t e = hipFreeAsync(work, st);
+        if (s == AU_OK && e != hipSuccess)
+            return fail(AU_EDEVICE, std::string("hipFreeAsync: ") + hipGetErrorString(e));
+    }
+    return s;
+}
+
+extern "C" au_status au_unfold_event(const au_table* tb, const au_event* ev, const void* d_volt,
+                                     double zen_deg, double az_deg, void* d_efield, void* d_work,
+                                     uint64_t work_bytes, void* stream, uint64_t* d_counts)
+{
+    return unfold_common(tb, ev, d_volt, 1, nullptr, zen_deg, az_deg, d_efield, d_work, work_bytes,
+                         stream, d_counts);
+}
+
+extern "C" au_status au_unfold_direction_scan(const au_table* tb, const au_event* ev,
+                                              const void* d_volt, int32_t n_dir,
+                                              const double* h_dirs, void* d_efield, void* d_work,
+                                              uint64_t work_bytes, void* stream, uint64_t* d_counts)
+{
+    if (!h_dirs) return fail(AU_EINVAL, "null direction list");
+    return unfold_common(tb, ev, d_volt, n_dir, h_dirs, 0.0, 0.0, d_efield, d_work, work_bytes,
+                         stream, d_counts);
+}
+
+extern "C" au_status au_pattern_response(const au_table* tb, const au_event* ev, int32_t n_dir,
+                                         const double* h_dirs, void* d_resp, void* stream)
+{
+    EvParams p;
+    au_status s = check_event(tb, ev, &p);
+    if (s != AU_OK) return s;
+    if (!h_dirs || !d_resp || n_dir < 1) return fail(AU_EINVAL, "bad direction list or output");
+    if (!dirs_finite(h_dirs, n_dir)) return fail(AU_EINVAL, "directions must be finite");
+    if (p.nb == 0) return AU_OK;
+    hipStream_t st = (hipStream_t)stream;
+    double* dirs = nullptr;
+    hipError_t e = hipMallocAsync((void**)&dirs, sizeof(double) * 2 * n_dir, st);
+    if (e != hipSuccess) return fail(AU_ENOMEM, "hipMallocAsync(dirs)");
+    HIP_TRY(hipMemcpyAsync(dirs, h_dirs, sizeof(double) * 2 * n_dir, hipMemcpyHostToDevice, st));
+    EvDesc ev0{};
+    ev0.S = p.S;
+    ev0.N = p.N;
+    ev0.D = n_dir;
+    ev0.k_lo = p.k_lo;
+    ev0.nb = p.nb;
+    const bool f64 = ev->prec == AU_PREC_FP64;
+#define RESP_(TT, T)                                                                        \
+    hipLaunchKernelGGL((k_coef<TT, T, true>), dim3(n_dir), dim3(kBlock), 0, st,            \
+                       (const C2<TT>*)tb->d_nodes, tb->g, ev0, nullptr, nullptr, dirs, 0.0, 0.0, \
+                       ev->fs_hz, 0.0, 0.0, (MBin<T>*)d_resp, nullptr)
+    if (f64)
+        RESP_(double, double);
+    else if (tb->dtype == AU_F64)
+        RESP_(double, float);
+    else
+        RESP_(float, float);
+#undef RESP_
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_coef(resp): ") + hipGetErrorString(e));
+    HIP_TRY(hipFreeAsync(dirs, st));
+    return AU_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched plans: many uneven events, one launch sequence per trace length
+// ---------------------------------------------------------------------------
+
+struct ClassPlan {
+    int N = 0;
+    uint64_t station_unfolds = 0;
+    int n_sunits = 0, n_cunits = 0, n_uunits = 0;
+    EvDesc* d_evs = nullptr;
+    int2* d_sunits = nullptr;
+    int2* d_cunits = nullptr;
+    int4* d_uunits = nullptr;
+    unsigned int* d_counter = nullptr;
+    int persistent_blocks = 0;
+};
+
+struct au_plan {
+    const au_table* tb = nullptr;
+    int device = 0;
+    int prec = 0, tin = 0, flags = 0;
+    int64_t fs = 0;
+    double fb = 0, sg = 0;
+    void* d_mem = nullptr;
+    void* d_x = nullptr;
+    void* d_m = nullptr;
+    double* d_dirs = nullptr;
+    std::vector<ClassPlan> classes;
+    uint64_t station_unfolds = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* g_volt = nullptr;
+    void* g_efield = nullptr;
+    uint64_t* g_counts = nullptr;
+    // stage timing (au_plan_timing): one event before the first launch and
+    // one after every launch of a run; elapsed times summed per stage
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<double> stage_ms;  // [class][spectrum, coef, unfold]
+    uint64_t timed_runs = 0;
+};
+
+template <typename T>
+static au_status plan_enqueue(au_plan* pl, const void* d_volt, void* d_efield, hipStream_t st,
+                              uint64_t* d_counts)
+{
+    const au_table* tb = pl->tb;
+    const C2<T>* tw = twiddles<T>(tb->device);
+    XBin<T>* X = (XBin<T>*)pl->d_x;
+    MBin<T>* M = (MBin<T>*)pl->d_m;
+    EvDesc ev0{};
+    const bool tm = pl->timing && !pl->ev.empty();
+    if (tm) HIP_TRY(hipEventRecord(pl->ev[0], st));
+    int ei = 1;
+    for (const ClassPlan& c : pl->classes) {
+        hipError_t e;
+        if (pl->tin == AU_F64)
+            e = launch_spectrum<double, T>(c.N, st, (const double*)d_volt, ev0, c.d_evs, c.d_sunits,
+                                           c.n_sunits, X, tw);
+        else
+            e = launch_spectrum<float, T>(c.N, st, (const float*)d_volt, ev0, c.d_evs, c.d_sunits,
+                                          c.n_sunits, X, tw);
+        if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
+        if (tm) HIP_TRY(hipEventRecord(pl->ev[ei++], st));
+        if (c.n_cunits > 0) {
+            if (tb->dtype == AU_F64)
+                launch_coef<double, T>(st, tb, ev0, c.d_evs, c.d_cunits, c.n_cunits, pl->d_dirs, 0, 0,
+                                       pl->fs, pl->fb, pl->sg, M, (unsigned long long*)d_counts);
+            else
+                launch_coef<float, T>(st, tb, ev0, c.d_evs, c.d_cunits, c.n_cunits, pl->d_dirs, 0, 0,
+                                      pl->fs, pl->fb, pl->sg, M, (unsigned long long*)d_counts);
+            e = hipGetLastError();
+            if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_coef: ") + hipGetErrorString(e));
+        }
+        if (tm) HIP_TRY(hipEventRecord(pl->ev[ei++], st));
+        const bool pers = (pl->flags & AU_PLAN_PERSISTENT) != 0;
+        e = launch_unfold<T>(c.N, st, ev0, c.d_evs, c.d_uunits, c.n_uunits, kStationsPerUnit, X, M,
+                             (T*)d_efield, tw, pers ? c.d_counter : nullptr, c.persistent_blocks);
+        if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_unfold: ") + hipGetErrorString(e));
+        if (tm) HIP_TRY(hipEventRecord(pl->ev[ei++], st));
+    }
+    if (tm) {
+        HIP_TRY(hipEventSynchronize(pl->ev[ei - 1]));
+        for (int i = 1; i < ei; ++i) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, pl->ev[i - 1], pl->ev[i]));
+            pl->stage_ms[i - 1] += ms;
+        }
+        ++pl->timed_runs;
+    }
+    return AU_OK;
+}
+
+extern "C" au_status au_plan_free(au_plan* pl)
+{
+    if (!pl) return AU_OK;
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    if (pl->d_mem) (void)hipFree(pl->d_mem);
+    for (hipEvent_t e : pl->ev) (void)hipEventDestroy(e);
+    delete pl;
+    return AU_OK;
+}
+
+extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_plan** out)
+{
+    if (!b || !out) return fail(AU_EINVAL, "null argument");
+    au_status s = check_common(tb, b->fs_hz, b->band_lo_hz, b->band_hi_hz, b->prec, b->trace_dtype,
+                               b->fallback_rel, b->singular_rel);
+    if (s != AU_OK) return s;
+    if (b->n_events < 1 || !b->n_stations || !b->n_samples || !b->n_dirs || !b->h_dirs ||
+        !b->volt_offset || !b->efield_offset)
+        return fail(AU_EINVAL, "batch arrays missing");
+    if (b->flags & ~(AU_PLAN_GRAPH | AU_PLAN_PERSISTENT)) return fail(AU_EINVAL, "unknown plan flags");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != tb->device) return fail(AU_EINVAL, "table lives on another device");
+    const int E = b->n_events;
+    const bool f64 = b->prec == AU_PREC_FP64;
+    const size_t xb = f64 ? sizeof(XBin<double>) : sizeof(XBin<float>);
+    const size_t mb = f64 ? sizeof(MBin<double>) : sizeof(MBin<float>);
+    std::vector<EvParams> ps(E);
+    std::vector<EvDesc> descs(E);
+    int64_t dir_total = 0, x_total = 0, m_total = 0;
+    uint64_t su = 0;
+    for (int e = 0; e < E; ++e) {
+        s = check_n(tb, b->n_stations[e], b->n_samples[e], b->fs_hz, b->band_lo_hz, b->band_hi_hz, &ps[e]);
+        if (s != AU_OK) return fail(s, "event " + std::to_string(e) + ": " + g_err);
+        if (b->n_dirs[e] < 1) return fail(AU_EINVAL, "event " + std::to_string(e) + ": n_dirs must be >= 1");
+        if (b->volt_offset[e] < 0 || b->efield_offset[e] < 0)
+            return fail(AU_EINVAL, "negative buffer offset");
+        EvDesc& d = descs[e];
+        d = EvDesc{};
+        d.volt_off = b->volt_offset[e];
+        d.efield_off = b->efield_offset[e];
+        d.x_off = x_total;
+        d.m_off = m_total;
+        d.dir_off = dir_total;
+        d.S = ps[e].S;
+        d.N = ps[e].N;
+        d.D = b->n_dirs[e];
+        d.k_lo = ps[e].k_lo;
+        d.nb = ps[e].nb;
+        x_total += (int64_t)d.S * d.nb;
+        m_total += (int64_t)d.D * d.nb;
+        dir_total += d.D;
+        su += (uint64_t)d.S * d.D;
+    }
+    if (!dirs_finite(b->h_dirs, dir_total)) return fail(AU_EINVAL, "directions must be finite");
+    // group by trace length; units sorted longest first
+    std::vector<int> ns;
+    for (int e = 0; e < E; ++e)
+        if (std::find(ns.begin(), ns.end(), descs[e].N) == ns.end()) ns.push_back(descs[e].N);
+    std::sort(ns.begin(), ns.end(), std::greater<int>());
+    struct HostClass {
+        int N;
+        std::vector<EvDesc> evs;
+        std::vector<int2> su, cu;
+        std::vector<int4> uu;
+    };
+    std::vector<HostClass> hc;
+    for (int n : ns) {
+        HostClass c;
+        c.N = n;
+        for (int e = 0; e < E; ++e) {
+            if (descs[e].N != n) continue;
+            const int ci = (int)c.evs.size();
+            c.evs.push_back(descs[e]);
+            for (int st = 0; st < descs[e].S; ++st) c.su.push_back(int2{ci, st});
+            for (int d = 0; d < descs[e].D; ++d) {
+                c.cu.push_back(int2{ci, d});
+                for (int s0 = 0; s0 < descs[e].S; s0 += kStationsPerUnit)
+                    c.uu.push_back(int4{ci, d, s0, std::min(descs[e].S, s0 + kStationsPerUnit)});
+            }
+        }
+        std::stable_sort(c.uu.begin(), c.uu.end(),
+                         [](const int4& a, const int4& bb) { return (a.w - a.z) > (bb.w - bb.z); });
+        if (c.uu.size() > 0x7fffffffu || c.cu.size() > 0x7fffffffu || c.su.size() > 0x7fffffffu)
+            return fail(AU_EINVAL, "too many work units in one trace-length class");
+        hc.push_back(std::move(c));
+    }
+    // one device allocation for everything the plan owns
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes + 1);
+        return o;
+    };
+    const size_t o_x = take((size_t)x_total * xb);
+    const size_t o_m = take((size_t)m_total * mb);
+    const size_t o_dirs = take((size_t)dir_total * 2 * sizeof(double));
+    struct Offs {
+        size_t evs, su, cu, uu, ctr;
+    };
+    std::vector<Offs> co;
+    for (auto& c : hc)
+        co.push_back(Offs{take(c.evs.size() * sizeof(EvDesc)), take(c.su.size() * sizeof(int2)),
+                          take(c.cu.size() * sizeof(int2)), take(c.uu.size() * sizeof(int4)),
+                          take(sizeof(unsigned int))});
+    au_plan* pl = new au_plan();
+    pl->tb = tb;
+    pl->device = dev;
+    pl->prec = b->prec;
+    pl->tin = b->trace_dtype;
+    pl->flags = b->flags;
+    pl->fs = b->fs_hz;
+    pl->fb = b->fallback_rel;
+    pl->sg = b->singular_rel;
+    pl->station_unfolds = su;
+    hipError_t e = hipMalloc(&pl->d_mem, off);
+    if (e != hipSuccess) {
+        au_plan_free(pl);
+        return fail(AU_ENOMEM, std::string("hipMalloc(plan): ") + hipGetErrorString(e));
+    }
+    unsigned char* base = (unsigned char*)pl->d_mem;
+    pl->d_x = base + o_x;
+    pl->d_m = base + o_m;
+    pl->d_dirs = (double*)(base + o_dirs);
+#define PLAN_TRY(expr)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            au_plan_free(pl);                                                               \
+            return fail(AU_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+        }                                                                                   \
+    } while (0)
+    PLAN_TRY(hipMemcpy(pl->d_dirs, b->h_dirs, (size_t)dir_total * 2 * sizeof(double), hipMemcpyHostToDevice));
+    for (size_t i = 0; i < hc.size(); ++i) {
+        ClassPlan c;
+        c.N = hc[i].N;
+        for (const EvDesc& d : hc[i].evs) c.station_unfolds += (uint64_t)d.S * d.D;
+        c.n_sunits = (int)hc[i].su.size();
+        c.n_cunits = (int)hc[i].cu.size();
+        c.n_uunits = (int)hc[i].uu.size();
+        c.d_evs = (EvDesc*)(base + co[i].evs);
+        c.d_sunits = (int2*)(base + co[i].su);
+        c.d_cunits = (int2*)(base + co[i].cu);
+        c.d_uunits = (int4*)(base + co[i].uu);
+        c.d_counter = (unsigned int*)(base + co[i].ctr);
+        PLAN_TRY(hipMemcpy(c.d_evs, hc[i].evs.data(), hc[i].evs.size() * sizeof(EvDesc), hipMemcpyHostToDevice));
+        PLAN_TRY(hipMemcpy(c.d_sunits, hc[i].su.data(), hc[i].su.size() * sizeof(int2), hipMemcpyHostToDevice));
+        PLAN_TRY(hipMemcpy(c.d_cunits, hc[i].cu.data(), hc[i].cu.size() * sizeof(int2), hipMemcpyHostToDevice));
+        PLAN_TRY(hipMemcpy(c.d_uunits, hc[i].uu.data(), hc[i].uu.size() * sizeof(int4), hipMemcpyHostToDevice));
+        c.persistent_blocks = f64 ? persistent_blocks_for<double>(c.N, dev) : persistent_blocks_for<float>(c.N, dev);
+        pl->classes.push_back(c);
+    }
+    if (pl->flags & AU_PLAN_GRAPH) PLAN_TRY(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+#undef PLAN_TRY
+    *out = pl;
+    return AU_OK;
+}
+
+extern "C" au_status au_plan_timing(au_plan* pl, int32_t enable)
+{
+    if (!pl) return fail(AU_EINVAL, "null plan");
+    if (enable && (pl->flags & AU_PLAN_GRAPH)) return fail(AU_EINVAL, "stage timing needs a plan without AU_PLAN_GRAPH");
+    if (enable && pl->ev.empty()) {
+        pl->ev.resize(3 * pl->classes.size() + 1);
+        for (auto& e : pl->ev) HIP_TRY(hipEventCreate(&e));
+    }
+    pl->timing = enable != 0;
+    pl->stage_ms.assign(3 * pl->classes.size(), 0.0);
+    pl->timed_runs = 0;
+    return AU_OK;
+}
+
+extern "C" au_status au_plan_classes(const au_plan* pl, int32_t max, int32_t* n_samples,
+                                     uint64_t* station_unfolds, int32_t* n_classes)
+{
+    if (!pl || !n_classes) return fail(AU_EINVAL, "null argument");
+    *n_classes = (int32_t)pl->classes.size();
+    for (int32_t i = 0; i < max && i < (int32_t)pl->classes.size(); ++i) {
+        if (n_samples) n_samples[i] = pl->classes[i].N;
+        if (station_unfolds) station_unfolds[i] = pl->classes[i].station_unfolds;
+    }
+    return AU_OK;
+}
+
+extern "C" au_status au_plan_stage_ms(const au_plan* pl, int32_t max, double* ms, uint64_t* runs)
+{
+    if (!pl || !ms || !runs) return fail(AU_EINVAL, "null argument");
+    for (int32_t i = 0; i < max && i < (int32_t)pl->stage_ms.size(); ++i) ms[i] = pl->stage_ms[i];
+    *runs = pl->timed_runs;
+    return AU_OK;
+}
+
+extern "C" au_status au_plan_units(const au_plan* pl, uint64_t* n)
+{
+    if (!pl || !n) return fail(AU_EINVAL, "null argument");
+    *n = pl->station_unfolds;
+    return AU_OK;
+}
+
+extern "C" au_status au_plan_run(au_plan* pl, const void* d_volt, void* d_efield, void* stream,
+                                 uint64_t* d_counts)
+{
+    if (!pl || !d_volt || !d_efield) return fail(AU_EINVAL, "null argument");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != pl->device) return fail(AU_EINVAL, "plan lives on another device");
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = pl->prec == AU_PREC_FP64;
+    if (!(pl->flags & AU_PLAN_GRAPH))
+        return f64 ? plan_enqueue<double>(pl, d_volt, d_efield, st, d_counts)
+                   : plan_enqueue<float>(pl, d_volt, d_efield, st, d_counts);
+    if (pl->exec == nullptr || pl->g_volt != d_volt || pl->g_efield != d_efield || pl->g_counts != d_counts) {
+        if (pl->exec) {
+            (void)hipGraphExecDestroy(pl->exec);
+            pl->exec = nullptr;
+        }
+        if (pl->graph) {
+            (void)hipGraphDestroy(pl->graph);
+            pl->graph = nullptr;
+        }
+        HIP_TRY(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+        au_status s = f64 ? plan_enqueue<double>(pl, d_volt, d_efield, pl->cap_stream, d_counts)
+                          : plan_enqueue<float>(pl, d_volt, d_efield, pl->cap_stream, d_counts);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(pl->cap_stream, &g);
+        if (s != AU_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return fail(AU_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        pl->graph = g;
+        HIP_TRY(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0));
+        pl->g_volt = d_volt;
+        pl->g_efield = d_efield;
+        pl->g_counts = d_counts;
+    }
+    HIP_TRY(hipGraphLaunch(pl->exec, st));
+    return AU_OK;
+}
