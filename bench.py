@@ -135,6 +135,103 @@ def parity_sample(grid, table_c64, specs, plan, volt_host, efield, n_units=8):
     return worst
 
 
+def serving_benchmark(api, synth, tab32, tab64, rate_hz=2000.0, duration_s=3.0, warm_s=0.5,
+                      plain_s=1.5, pool=48):
+    """Open-loop Poisson stream of events (stations U{3..124}, 2048 float32
+    samples, 8x8 directions) served by the continuous-batching server, and the
+    same stream by a plain FP64 per-event loop.  Latency = completion time -
+    scheduled arrival time (no coordinated omission); the first warm_s
+    seconds are discarded."""
+    import threading
+    import torch
+    r = synth.rng(3, synth.STREAM_EVENTS)
+    sizes = r.integers(3, 125, size=pool)
+    vols = [synth.traces(int(sz), 2048, cfg=3, event=i, dtype=np.float32) for i, sz in enumerate(sizes)]
+    dirs = synth.direction_grid(8, 8)
+    arrivals = synth.poisson_arrivals(rate_hz, duration_s, cfg=3)
+    n_ev = len(arrivals)
+    sv = api.Server(tab32, hbm_budget_bytes=48 << 30, staging_bytes=4 << 30, max_inflight=256,
+                    n_streams=4, max_batch_events=16, tick_s=0.0)
+    tickets = [None] * n_ev
+    t_start = sv.now() + 0.2
+    rejected = [0]
+
+    def producer():
+        for i, a in enumerate(arrivals):
+            target = t_start + a
+            while sv.now() < target:
+                pass
+            while True:
+                try:
+                    tickets[i] = sv.submit(vols[i % pool], dirs, t_arrival=target)
+                    break
+                except api.AuError as e:
+                    if e.status != api.AU_EAGAIN:
+                        raise
+                    rejected[0] += 1
+                    time.sleep(1e-4)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    lat, batch, done_t, units = [], [], [], 0
+    for i in range(n_ev):
+        while tickets[i] is None:
+            time.sleep(5e-5)
+        res = sv.wait(tickets[i], timeout_s=120, sleep_s=5e-5)
+        if arrivals[i] >= warm_s:
+            lat.append(res.t_complete - res.t_arrival)
+            batch.append(res.batch_events)
+            done_t.append(res.t_complete)
+            units += res.n_stations * res.n_dirs
+        sv.release(tickets[i])
+    th.join()
+    st = sv.stats()
+    sv.close()
+    lat = np.array(lat) * 1e3
+    span = max(done_t) - (t_start + warm_s)
+    served = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+              "max_ms": float(lat.max()), "events": len(lat), "offered_events_per_s": rate_hz,
+              "events_per_s": len(lat) / span, "station_unfolds_per_s": units / span,
+              "mean_batch_events": float(np.mean(batch)), "submit_retries": rejected[0],
+              "arena_peak_GB": st["arena_peak"] / 1e9,
+              "workload": "Poisson %.0f events/s for %.1f s (first %.1f s discarded), stations U{3..124}, "
+                          "2048 float32 samples, 8x8 directions, FP32 server, 4 streams" % (rate_hz, duration_s, warm_s)}
+
+    # plain FP64 per-event loop on the same arrival stream
+    dev = torch.device("cuda:0")
+    smax = int(sizes.max())
+    out = torch.empty((len(dirs), smax, 2, 2048), dtype=torch.float64, device=dev)
+    ev_max = api.make_event(smax, 2048, prec=api.AU_PREC_FP64, trace_dtype=api.AU_F64)
+    work = torch.empty(api.workspace_bytes(tab64, ev_max, len(dirs)), dtype=torch.uint8, device=dev)
+    vols64 = [torch.from_numpy(v.astype(np.float64)).pin_memory() for v in vols]
+    dvol = torch.empty((smax, 2, 2048), dtype=torch.float64, device=dev)
+    sel = arrivals[arrivals < plain_s]
+    lat2 = []
+    t0 = time.perf_counter() + 0.1
+    for i, a in enumerate(sel):
+        target = t0 + a
+        while time.perf_counter() < target:
+            pass
+        v = vols64[i % pool]
+        s = v.shape[0]
+        dv = dvol[:s]
+        dv.copy_(v)
+        ev = api.make_event(s, 2048, prec=api.AU_PREC_FP64, trace_dtype=api.AU_F64)
+        o = out[:, :s]
+        api.unfold_direction_scan(tab64, ev, dv, dirs, out=o.view(-1)[: len(dirs) * s * 2 * 2048].view(len(dirs), s, 2, 2048),
+                                  work=work)
+        torch.cuda.synchronize()
+        if a >= warm_s:
+            lat2.append(time.perf_counter() - target)
+    lat2 = np.array(lat2) * 1e3
+    plain = {"p50_ms": float(np.percentile(lat2, 50)), "p99_ms": float(np.percentile(lat2, 99)),
+             "events": len(lat2),
+             "workload": "same arrivals (first %.1f s), one au_unfold_direction_scan FP64 call per event "
+                         "after its host-to-device copy, synchronised" % plain_s}
+    served["plain_fp64_loop"] = plain
+    return served
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +242,8 @@ def main():
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--flags", type=int, default=2, help="plan flags: 1 graph, 2 persistent")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -164,6 +263,12 @@ def main():
     table = synth.pattern_table(grid, cfg=2).astype(np.complex64)
     tab = api.Table(grid, table)
     specs = build_batched_workload(args.events)
+    tuned = {}
+    for n in sorted(set(sp[1] for sp in specs)):
+        best, ms = api.autotune(tab, api.make_event(124, n, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32),
+                                n_dir=64, reps=3)
+        tuned["fp32_N%d" % n] = {"variant": best, "shape": api.unfold_variants()[best], "ms": ms}
+        log("autotune fp32 N=%d: variant %d %s" % (n, best, api.unfold_variants()[best]))
     flags = args.flags & ~api.AU_PLAN_GRAPH      # stage timing needs eager launches
     plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=flags)
     volt_host = gen_traces(specs, plan.volt_offsets, plan.volt_elems)
@@ -236,8 +341,12 @@ def main():
         dirs1 = synth.direction_grid(32, 64)
         v1 = torch.from_numpy(synth.traces(s1, n1, cfg=1, event=0)).to(dev)
         ev = api.make_event(s1, n1, prec=api.AU_PREC_FP64, trace_dtype=api.AU_F64)
+        best, ms = api.autotune(t1, ev, n_dir=64, reps=3)
+        tuned["fp64_N%d" % n1] = {"variant": best, "shape": api.unfold_variants()[best], "ms": ms}
+        log("autotune fp64 N=%d: variant %d" % (n1, best))
         work = torch.empty(api.workspace_bytes(t1, ev, len(dirs1)), dtype=torch.uint8, device=dev)
         del efield
+        torch.cuda.empty_cache()
         out1 = torch.empty((len(dirs1), s1, 2, n1), dtype=torch.float64, device=dev)
         api.unfold_direction_scan(t1, ev, v1, dirs1, out=out1, work=work)
         torch.cuda.synchronize()
@@ -256,6 +365,17 @@ def main():
                 "output_GBs": su1 * 2 * n1 * 8 / (ms1 / 1e3) / 1e9}
         log("fp64 plain scan: %.3f ms/call, %.1f M station-unfolds/s" % (ms1, fp64["value"] / 1e6))
         del out1, work
+        torch.cuda.empty_cache()
+
+    # ---------------- serving -------------------------------------------
+    serving = None
+    if not args.no_serving:
+        tab64f = api.Table(grid, synth.pattern_table(grid, cfg=2))
+        serving = serving_benchmark(api, synth, tab, tab64f, duration_s=args.serve_seconds)
+        log("serving: p50 %.3f ms p99 %.3f ms at %.0f events/s; plain fp64 loop p50 %.3f p99 %.3f ms"
+            % (serving["p50_ms"], serving["p99_ms"], serving["events_per_s"],
+               serving["plain_fp64_loop"]["p50_ms"], serving["plain_fp64_loop"]["p99_ms"]))
+        del tab64f
 
     # ---------------- CPU oracle baseline ---------------------------------
     cpu = None
@@ -280,9 +400,10 @@ def main():
                                "16x16 directions/event, complex64 table 0.5 MHz/1 deg, FP64 det fallback"
                                % len(specs),
                    "events": len(specs), "station_unfolds": int(plan.station_unfolds),
-                   "plan_flags": flags, "graph_ms_per_step": graph_ms},
+                   "plan_flags": flags, "graph_ms_per_step": graph_ms, "autotuned": tuned},
         "roofline": roofline,
         "fp64_plain": fp64,
+        "serving": serving,
         "cpu_baseline": cpu,
         "parity_sample_max_err": err,
         "fallback_singular_bins": cnt,

@@ -228,6 +228,99 @@ au_status au_plan_classes(const au_plan* plan, int32_t max, int32_t* n_samples,
 au_status au_plan_stage_ms(const au_plan* plan, int32_t max, double* ms, uint64_t* runs);
 au_status au_plan_free(au_plan* plan);
 
+/*
+ * Serving: a continuous-batching request loop (section 5 motivates keeping
+ * traces resident on the GPU instead of copying around isolated calls).
+ * The server owns one device arena of hbm_budget_bytes (traces, outputs and
+ * work space of admitted events plus batch descriptors) and a pinned host
+ * staging area of staging_bytes; both are allocated at creation and carved
+ * up by a first-fit allocator, so submit/poll/release never allocate device
+ * memory.  A scheduler thread admits queued events in FIFO order when the
+ * arena has room and fewer than max_inflight events are admitted and not
+ * released, gathers admitted events into micro-batches (launched when
+ * max_batch_events are ready or the oldest has waited tick_s seconds), and
+ * spreads batches round-robin over n_streams streams so that the work of
+ * events arriving while others run overlaps on the device.  Each event's
+ * result stays in the arena until au_release.  Per-event arithmetic is the
+ * same whatever the batch mix, so a result is identical alone and in a mix.
+ * Thread safety: submit/poll/release/stats may be called from any thread;
+ * au_copy_result must not race with au_release of the same ticket.
+ * Timestamps are seconds on the server's steady clock (au_server_now).
+ */
+typedef struct {
+    uint64_t hbm_budget_bytes;    /* device arena size */
+    uint64_t staging_bytes;       /* pinned host staging size */
+    int32_t max_inflight;         /* admitted-and-unreleased events at most */
+    int32_t n_streams;            /* 1..16 */
+    int32_t max_batch_events;     /* events per micro-batch at most */
+    int32_t prec;                 /* AU_PREC_FP32 / AU_PREC_FP64 */
+    int32_t trace_dtype;          /* AU_F32 / AU_F64 of submitted traces */
+    int32_t reserved;
+    int64_t fs_hz, band_lo_hz, band_hi_hz;
+    double fallback_rel, singular_rel;
+    double tick_s;                /* longest wait of an admitted event before launch */
+} au_server_cfg;
+
+typedef struct {
+    int32_t n_stations, n_samples, n_dirs, reserved;
+    const void* h_volt;           /* host [S][2][N] of cfg.trace_dtype (copied by au_submit) */
+    const double* h_dirs;         /* host [n_dirs][2] degrees (copied) */
+    double t_arrival;             /* scheduled arrival on the server clock; <= 0: now */
+} au_request;
+
+typedef struct {
+    void* d_efield;               /* [n_dirs][S][2][N] in the arena, valid until au_release */
+    uint64_t efield_bytes;
+    int32_t n_stations, n_samples, n_dirs, batch_events;
+    double t_arrival, t_submit, t_admit, t_launch, t_complete;
+} au_result;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, batches, queued, in_flight;
+    uint64_t arena_bytes, arena_in_use, arena_peak;
+    uint64_t fallback_bins, singular_bins;
+} au_server_counters;
+
+/* Errors: AU_EINVAL (configuration, request), AU_ENOMEM (arena or staging
+ * cannot be allocated; a request larger than the whole arena), AU_EAGAIN
+ * (au_submit: staging full, retry later; au_poll: not complete yet),
+ * AU_ENOTFOUND (unknown or released ticket), AU_EDEVICE (a HIP call failed;
+ * the server then fails every pending request). */
+au_status au_server_create(const au_table* table, const au_server_cfg* cfg, au_server** out);
+au_status au_server_destroy(au_server* server);
+au_status au_server_now(const au_server* server, double* seconds);
+au_status au_submit(au_server* server, const au_request* request, uint64_t* ticket);
+au_status au_poll(au_server* server, uint64_t ticket, au_result* result);
+au_status au_copy_result(au_server* server, uint64_t ticket, void* dst, uint64_t dst_bytes);
+au_status au_release(au_server* server, uint64_t ticket);
+au_status au_server_stats(au_server* server, au_server_counters* stats);
+
+/*
+ * Kernel shapes and autotuning (the batched form picks its FFT radix
+ * schedule per trace length and precision by measurement).  The unfold
+ * kernel is built in au_unfold_variant_count() shapes, described by four
+ * arrays (each may be NULL): e_values = values per thread (0: one wavefront
+ * per transform, N/64 values per lane), rmax = largest radix per pass,
+ * twmode = where the inverse FFT's twiddles live (0 table, 1 registers,
+ * 2 registers times compile-time constants), wave = 1 if a single wavefront
+ * owns each transform (no workgroup barriers).  Shapes other than the first
+ * two exist only for N >= 1024, and only where they fit in registers.  The selection is process-wide per (precision,
+ * N); plans read it when they are created.
+ *
+ * au_autotune runs the single-event path on a synthetic event of ev's sizes
+ * and n_dir directions with every built variant (reps timed runs each after
+ * one warm-up, HIP events on a private stream), writes the average ms per
+ * variant to ms[] (-1 where not built; may be NULL), selects the fastest
+ * and returns it in *best.  It allocates its own buffers (hipMalloc) and is
+ * synchronous.
+ */
+au_status au_unfold_variant_count(int32_t* count, int32_t* e_values, int32_t* rmax, int32_t* twmode,
+                                  int32_t* wave);
+au_status au_set_unfold_variant(int32_t prec, int32_t n_samples, int32_t variant);
+au_status au_get_unfold_variant(int32_t prec, int32_t n_samples, int32_t* variant);
+au_status au_autotune(const au_table* table, const au_event* ev, int32_t n_dir, int32_t reps,
+                      double* ms, int32_t* best);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,32 @@ class AuBatch(C.Structure):
                 ("volt_offset", C.POINTER(C.c_int64)), ("efield_offset", C.POINTER(C.c_int64))]
 
 
+class AuServerCfg(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("staging_bytes", C.c_uint64), ("max_inflight", C.c_int32),
+                ("n_streams", C.c_int32), ("max_batch_events", C.c_int32), ("prec", C.c_int32),
+                ("trace_dtype", C.c_int32), ("reserved", C.c_int32),
+                ("fs_hz", C.c_int64), ("band_lo_hz", C.c_int64), ("band_hi_hz", C.c_int64),
+                ("fallback_rel", C.c_double), ("singular_rel", C.c_double), ("tick_s", C.c_double)]
+
+
+class AuRequest(C.Structure):
+    _fields_ = [("n_stations", C.c_int32), ("n_samples", C.c_int32), ("n_dirs", C.c_int32), ("reserved", C.c_int32),
+                ("h_volt", C.c_void_p), ("h_dirs", C.POINTER(C.c_double)), ("t_arrival", C.c_double)]
+
+
+class AuResult(C.Structure):
+    _fields_ = [("d_efield", C.c_void_p), ("efield_bytes", C.c_uint64), ("n_stations", C.c_int32),
+                ("n_samples", C.c_int32), ("n_dirs", C.c_int32), ("batch_events", C.c_int32),
+                ("t_arrival", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_launch", C.c_double), ("t_complete", C.c_double)]
+
+
+class AuServerStats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("submitted", "completed", "rejected", "batches", "queued", "in_flight",
+                                          "arena_bytes", "arena_in_use", "arena_peak", "fallback_bins",
+                                          "singular_bins")]
+
+
 class AuError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__("aeraunfold status %d: %s" % (status, msg))
@@ -89,6 +115,19 @@ _SIG = {
     "au_plan_classes": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_uint64),
                                     C.POINTER(C.c_int32)]),
     "au_plan_stage_ms": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
+    "au_unfold_variant_count": (C.c_int32, [C.POINTER(C.c_int32)] * 5),
+    "au_set_unfold_variant": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
+    "au_get_unfold_variant": (C.c_int32, [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
+    "au_autotune": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                C.POINTER(C.c_int32)]),
+    "au_server_create": (C.c_int32, [_VP, C.POINTER(AuServerCfg), C.POINTER(_VP)]),
+    "au_server_destroy": (C.c_int32, [_VP]),
+    "au_server_now": (C.c_int32, [_VP, C.POINTER(C.c_double)]),
+    "au_submit": (C.c_int32, [_VP, C.POINTER(AuRequest), C.POINTER(C.c_uint64)]),
+    "au_poll": (C.c_int32, [_VP, C.c_uint64, C.POINTER(AuResult)]),
+    "au_copy_result": (C.c_int32, [_VP, C.c_uint64, _VP, C.c_uint64]),
+    "au_release": (C.c_int32, [_VP, C.c_uint64]),
+    "au_server_stats": (C.c_int32, [_VP, C.POINTER(AuServerStats)]),
 }
 
 
@@ -259,6 +298,33 @@ def pattern_response(table: Table, ev: AuEvent, dirs, device=None, stream=None):
     return torch.view_as_complex(out)
 
 
+def unfold_variants():
+    """[(E, rmax, twmode, wave)] of the unfold-kernel shapes the library is built in."""
+    n = C.c_int32()
+    e, r, t, w = ((C.c_int32 * 32)() for _ in range(4))
+    _check(lib().au_unfold_variant_count(C.byref(n), e, r, t, w))
+    return [(e[i], r[i], t[i], bool(w[i])) for i in range(n.value)]
+
+
+def set_unfold_variant(prec: int, n_samples: int, variant: int):
+    _check(lib().au_set_unfold_variant(int(prec), int(n_samples), int(variant)))
+
+
+def get_unfold_variant(prec: int, n_samples: int) -> int:
+    v = C.c_int32()
+    _check(lib().au_get_unfold_variant(int(prec), int(n_samples), C.byref(v)))
+    return v.value
+
+
+def autotune(table: Table, ev: AuEvent, n_dir: int = 16, reps: int = 3):
+    """Time every unfold variant for ev's sizes, select the fastest; returns (best, ms list)."""
+    nv = len(unfold_variants())
+    ms = (C.c_double * nv)()
+    best = C.c_int32()
+    _check(lib().au_autotune(table.handle, C.byref(ev), int(n_dir), int(reps), ms, C.byref(best)))
+    return best.value, list(ms)
+
+
 class Plan:
     """A batched unfolding plan over events of uneven size (au_plan_*).
 
@@ -342,5 +408,92 @@ class Plan:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching unfolding server (au_server_*)."""
+
+    def __init__(self, table: Table, hbm_budget_bytes: int, staging_bytes: int = 1 << 30,
+                 max_inflight: int = 64, n_streams: int = 4, max_batch_events: int = 16,
+                 prec: int = AU_PREC_FP32, trace_dtype: int = AU_F32, tick_s: float = 0.0,
+                 fs_hz: int = FS_HZ, band_lo_hz: int = BAND_LO_HZ, band_hi_hz: int = BAND_HI_HZ,
+                 fallback_rel: float = 1e-6, singular_rel: float = 1e-12):
+        self.table = table
+        self.prec, self.trace_dtype = prec, trace_dtype
+        cfg = AuServerCfg(int(hbm_budget_bytes), int(staging_bytes), int(max_inflight), int(n_streams),
+                          int(max_batch_events), int(prec), int(trace_dtype), 0, int(fs_hz), int(band_lo_hz),
+                          int(band_hi_hz), float(fallback_rel), float(singular_rel), float(tick_s))
+        h = C.c_void_p()
+        _check(lib().au_server_create(table.handle, C.byref(cfg), C.byref(h)))
+        self.handle = h
+
+    def now(self) -> float:
+        t = C.c_double()
+        _check(lib().au_server_now(self.handle, C.byref(t)))
+        return t.value
+
+    def submit(self, volt: np.ndarray, dirs, t_arrival: float = 0.0) -> int:
+        """Queue one event (host traces [S][2][N]); returns its ticket.  Raises AuError
+        with status AU_EAGAIN when the staging area is full."""
+        want = np.float64 if self.trace_dtype == AU_F64 else np.float32
+        v = np.ascontiguousarray(volt, dtype=want)
+        d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 2))
+        s, two, n = v.shape
+        if two != 2:
+            raise ValueError("traces must have shape [S][2][N]")
+        rq = AuRequest(s, n, len(d), 0, v.ctypes.data_as(C.c_void_p), d.ctypes.data_as(C.POINTER(C.c_double)),
+                       float(t_arrival))
+        t = C.c_uint64()
+        _check(lib().au_submit(self.handle, C.byref(rq), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """AuResult when complete, None while pending."""
+        r = AuResult()
+        rc = lib().au_poll(self.handle, C.c_uint64(ticket), C.byref(r))
+        if rc == AU_EAGAIN:
+            return None
+        _check(rc)
+        return r
+
+    def wait(self, ticket: int, timeout_s: float = 60.0, sleep_s: float = 1e-4):
+        import time
+        t_end = time.perf_counter() + timeout_s
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.perf_counter() > t_end:
+                raise TimeoutError("ticket %d not complete after %.1f s" % (ticket, timeout_s))
+            time.sleep(sleep_s)
+
+    def result(self, ticket: int) -> np.ndarray:
+        """Copy a completed result to a host array [D][S][2][N]."""
+        r = self.poll(ticket)
+        if r is None:
+            raise AuError(AU_EAGAIN, "not complete")
+        dt = np.float64 if self.prec == AU_PREC_FP64 else np.float32
+        out = np.empty((r.n_dirs, r.n_stations, 2, r.n_samples), dtype=dt)
+        _check(lib().au_copy_result(self.handle, C.c_uint64(ticket), out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+    def release(self, ticket: int):
+        _check(lib().au_release(self.handle, C.c_uint64(ticket)))
+
+    def stats(self) -> dict:
+        st = AuServerStats()
+        _check(lib().au_server_stats(self.handle, C.byref(st)))
+        return {n: getattr(st, n) for n, _ in AuServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _check(lib().au_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

@@ -11,6 +11,7 @@
 // direction), so the whole path is bound by HBM write bandwidth when the
 // FFT keeps up.
 #include "aeraunfold.h"
+#include "au_internal.h"
 #include "au_kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -36,6 +37,9 @@ static au_status fail(au_status s, const std::string& msg)
     g_err = msg;
     return s;
 }
+
+au_status au::set_error(au_status s, const std::string& msg) { return fail(s, msg); }
+const std::string& au::error_string() { return g_err; }
 
 #define HIP_TRY(expr)                                                                        \
     do {                                                                                     \
@@ -170,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_spectrum(const Tin* __restrict__ vol
     constexpr int G = groups_per_block<T, N, E>();
     extern __shared__ __align__(16) unsigned char smem[];
     const int g = threadIdx.x / TT, t = threadIdx.x % TT;
-    C2<T>* lds = reinterpret_cast<C2<T>*>(smem) + g * N;
+    C2<T>* lds = reinterpret_cast<C2<T>*>(smem) + g * lds_elems<N>();
     const int u = blockIdx.x * G + g;
     const bool active = u < n_units;
     int e = 0, s = active ? u : 0;
@@ -189,14 +193,14 @@ __global__ __launch_bounds__(kBlock) void k_spectrum(const Tin* __restrict__ vol
     }
     fft<T, N, E, -1>(x, lds, tw, t);
 #pragma unroll
-    for (int i = 0; i < E; ++i) lds[t + TT * i] = x[i];
+    for (int i = 0; i < E; ++i) lds[lpad(t + TT * i)] = x[i];
     __syncthreads();
     if (active) {
         XBin<T>* out = X + ev.x_off + (int64_t)s * ev.nb;
         for (int j = t; j < ev.nb; j += TT) {
             const int k = ev.k_lo + j;
-            const C2<T> a = lds[k];
-            const C2<T> b = lds[(N - k) & (N - 1)];
+            const C2<T> a = lds[lpad(k)];
+            const C2<T> b = lds[lpad((N - k) & (N - 1))];
             XBin<T> r;
             r.x0 = C2<T>{(T)0.5 * (a.re + b.re), (T)0.5 * (a.im - b.im)};
             r.x1 = C2<T>{(T)0.5 * (a.im + b.im), (T)0.5 * (b.re - a.re)};
@@ -288,11 +292,19 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
 }
 
 // E-field traces of one (event, direction, station range) per block; each
-// FFT group takes one station at a time.  With `counter` non-null the grid
-// is persistent and blocks take units from the atomic counter until the
-// list is exhausted (every block leaves through the same check).
-template <typename T, int N, int E>
-__global__ __launch_bounds__(kBlock) void k_unfold(EvDesc ev0, const EvDesc* __restrict__ evs,
+// FFT group takes one station at a time.  Per station:
+//   1. every in-band bin k is handled once: (E_th, E_ph) = coef * (X_0, X_1),
+//      and the packed spectrum Z[k] = E_th + i E_ph, Z[N-k] = conj E_th +
+//      i conj E_ph is written to LDS (DC keeps real parts only);
+//   2. each thread reads its column of Z (zero outside the band);
+//   3. inverse FFT; thread t ends with z[t + (N/E) i], whose real and
+//      imaginary parts are E_theta and E_phi -- stored with non-temporal,
+//      coalesced writes.
+// With `counter` non-null the grid is persistent and blocks take units from
+// the atomic counter until the list is exhausted (every block leaves through
+// the same check); the per-thread twiddles are loaded once per block.
+template <typename T, int N, int E, int RMAX, int TWMODE, bool WAVE>
+__global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold(EvDesc ev0, const EvDesc* __restrict__ evs,
                                                    const int4* __restrict__ units, int n_units,
                                                    int spw, const XBin<T>* __restrict__ X,
                                                    const MBin<T>* __restrict__ M,
@@ -305,7 +317,9 @@ __global__ __launch_bounds__(kBlock) void k_unfold(EvDesc ev0, const EvDesc* __r
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sh_u;
     const int g = threadIdx.x / TT, t = threadIdx.x % TT;
-    C2<T>* lds = reinterpret_cast<C2<T>*>(smem) + g * N;
+    C2<T>* lds = reinterpret_cast<C2<T>*>(smem) + g * lds_elems<N>();
+    C2<T> w[tw_count<N, E, RMAX, TWMODE>()];
+    load_twiddles<T, N, E, RMAX, TWMODE, +1>(w, tw, t);
     for (int iter = 0;; ++iter) {
         int u;
         if (counter != nullptr) {
@@ -320,11 +334,11 @@ __global__ __launch_bounds__(kBlock) void k_unfold(EvDesc ev0, const EvDesc* __r
         if (u >= n_units) break;
         int e = 0, d, s0, s1;
         if (units != nullptr) {
-            const int4 w = units[u];
-            e = w.x;
-            d = w.y;
-            s0 = w.z;
-            s1 = w.w;
+            const int4 wu = units[u];
+            e = wu.x;
+            d = wu.y;
+            s0 = wu.z;
+            s1 = wu.w;
         } else {
             const int chunks = (ev0.S + spw - 1) / spw;
             d = u / chunks;
@@ -332,34 +346,38 @@ __global__ __launch_bounds__(kBlock) void k_unfold(EvDesc ev0, const EvDesc* __r
             s1 = min(ev0.S, s0 + spw);
         }
         const EvDesc ev = evs ? evs[e] : ev0;
-        const MBin<T>* Md = M + ev.m_off + (int64_t)d * ev.nb;
+        const MBin<T>* __restrict__ Md = M + ev.m_off + (int64_t)d * ev.nb;
+        const unsigned nb = (unsigned)ev.nb, k_lo = (unsigned)ev.k_lo;
         for (int base = s0; base < s1; base += G) {
             const int s = base + g;
             const bool active = s < s1;
-            const XBin<T>* Xs = X + ev.x_off + (int64_t)s * ev.nb;
-            C2<T> x[E];
-#pragma unroll
-            for (int i = 0; i < E; ++i) {
-                const int k = t + TT * i;
-                const int kk = (k <= N / 2) ? k : N - k;
-                const int j = kk - ev.k_lo;
-                C2<T> z{0, 0};
-                if (active && j >= 0 && j < ev.nb) {
+            if (active) {
+                const XBin<T>* __restrict__ Xs = X + ev.x_off + (int64_t)s * ev.nb;
+                for (unsigned j = t; j < nb; j += TT) {
                     const MBin<T> m = Md[j];
                     const XBin<T> xb = Xs[j];
                     C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
                     C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
+                    const unsigned k = k_lo + j;
                     if (k == 0) {
-                        et.im = 0;
-                        ep.im = 0;
+                        lds[0] = C2<T>{et.re, ep.re};
+                    } else {
+                        lds[lpad(k)] = C2<T>{et.re - ep.im, et.im + ep.re};
+                        lds[lpad(N - k)] = C2<T>{et.re + ep.im, ep.re - et.im};
                     }
-                    // Z[k] = E_th[k] + i E_ph[k];  Z[N-k] = conj E_th[k] + i conj E_ph[k]
-                    z = (k <= N / 2) ? C2<T>{et.re - ep.im, et.im + ep.re}
-                                     : C2<T>{et.re + ep.im, ep.re - et.im};
                 }
-                x[i] = z;
             }
-            fft<T, N, E, +1>(x, lds, tw, t);
+            lds_sync<WAVE>();
+            C2<T> x[E];
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const unsigned k = t + TT * i;
+                const unsigned kk = (k <= N / 2) ? k : N - k;
+                const bool inb = active && (kk - k_lo) < nb;
+                x[i] = inb ? lds[lpad(k)] : C2<T>{0, 0};
+            }
+            lds_sync<WAVE>();
+            fft<T, N, E, +1, TWMODE, RMAX, WAVE>(x, lds, tw, t, w);
             if (active) {
                 T* out = efield + ev.efield_off + ((int64_t)d * ev.S + s) * 2 * N;
 #pragma unroll
@@ -384,7 +402,7 @@ __global__ void k_zero_u32(unsigned int* p, int n)
 
 #define AU_FOR_EACH_N(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
-// Values per thread of the FFTs, per N.
+// Values per thread of the forward (station) FFTs.
 constexpr int kE = 16;
 
 template <typename T, int N>
@@ -393,8 +411,75 @@ struct Shape {
     static constexpr int TT = N / E;
     static constexpr int G = groups_per_block<T, N, E>();
     static constexpr int BLOCK = G * TT;
-    static constexpr size_t LDS = (size_t)G * N * sizeof(C2<T>);
+    static constexpr size_t LDS = (size_t)G * lds_elems<N>() * sizeof(C2<T>);
 };
+
+// Shapes the unfold kernel is built in.  E: values per thread (0 = one
+// wavefront per transform, E = N/64); RMAX: largest radix per pass (the
+// radix schedule); twmode: where the inverse transform's twiddles live (see
+// TW_* in au_device.h); wave: the transform is owned by one wavefront and
+// its passes need no workgroup barrier.  The autotuner times them per
+// (trace length, precision).
+struct UnfoldVariant {
+    int E;
+    int rmax;
+    int twmode;
+    bool wave;
+};
+constexpr UnfoldVariant kUnfoldVariants[] = {
+    {16, 16, TW_REG, false}, {16, 16, TW_TABLE, false}, {8, 8, TW_REG, false},    {8, 8, TW_TABLE, false},
+    {32, 32, TW_REG, false}, {32, 32, TW_TABLE, false}, {0, 16, TW_SPLIT, true}, {0, 8, TW_SPLIT, true},
+};
+constexpr int kNumVariants = 8;
+
+constexpr int variant_e(int n, int v) { return kUnfoldVariants[v].E == 0 ? n / 64 : kUnfoldVariants[v].E; }
+
+// Every variant for the long traces, the E=16 pair for the rest.  Shapes that
+// do not fit the register file are not built: more than 16 complex doubles
+// per thread, 32 complex doubles in the block form, and wavefront-owned
+// transforms above 16 values per lane (N > 1024).
+constexpr bool variant_built(int n, int v, int tsize)
+{
+    if (v < 0 || v >= kNumVariants) return false;
+    if (v >= 2 && n < 1024) return false;
+    const int e = variant_e(n, v);
+    if (e < 8 || e > (tsize == 8 ? 16 : 32)) return false;
+    if (kUnfoldVariants[v].wave && e > 16) return false;
+    if (kUnfoldVariants[v].rmax > e) return false;
+    return true;
+}
+
+template <typename T, int N, int V>
+struct UShape {
+    static constexpr int E0 = variant_e(N, V);
+    static constexpr int E = E0 < N ? E0 : N;
+    static constexpr int RMAX = kUnfoldVariants[V].rmax < E ? kUnfoldVariants[V].rmax : E;
+    static constexpr int TWMODE = kUnfoldVariants[V].twmode;
+    static constexpr bool WAVE = kUnfoldVariants[V].wave;
+    static constexpr int TT = N / E;
+    static constexpr int G = groups_per_block<T, N, E>();
+    static constexpr int BLOCK = G * TT;
+    static constexpr size_t LDS = (size_t)G * lds_elems<N>() * sizeof(C2<T>);
+};
+
+static int ilog2(int n)
+{
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+// Selected variant per [precision][log2 N]: float keeps twiddles in
+// registers, double reads them from the table.
+static std::mutex g_var_mu;
+static int g_variant[2][13] = {{1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+                               {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+
+static int unfold_variant(int prec, int n)
+{
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    return g_variant[prec == AU_PREC_FP32 ? 1 : 0][ilog2(n)];
+}
 
 template <typename Tin, typename T, int N>
 static hipError_t launch_spectrum_n(hipStream_t st, const Tin* volt, const EvDesc& ev0,
@@ -409,22 +494,56 @@ static hipError_t launch_spectrum_n(hipStream_t st, const Tin* volt, const EvDes
     return hipGetLastError();
 }
 
+template <typename T, int N, int V>
+static hipError_t launch_unfold_nv(hipStream_t st, const EvDesc& ev0, const EvDesc* evs,
+                                   const int4* units, int n_units, int spw, const XBin<T>* X,
+                                   const MBin<T>* M, T* efield, const C2<T>* tw,
+                                   unsigned int* counter, int persistent_blocks)
+{
+    if constexpr (!variant_built(N, V, (int)sizeof(T))) {
+        return hipErrorInvalidValue;
+    } else {
+        using S = UShape<T, N, V>;
+        if (n_units <= 0) return hipSuccess;
+        int grid = n_units;
+        if (counter != nullptr) {
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counter, 1);
+            grid = std::min(n_units, persistent_blocks);
+        }
+        hipLaunchKernelGGL((k_unfold<T, N, S::E, S::RMAX, S::TWMODE, S::WAVE>), dim3(grid), dim3(S::BLOCK), S::LDS, st,
+                           ev0, evs, units, n_units, spw, X, M, efield, tw, counter);
+        return hipGetLastError();
+    }
+}
+
 template <typename T, int N>
-static hipError_t launch_unfold_n(hipStream_t st, const EvDesc& ev0, const EvDesc* evs,
+static hipError_t launch_unfold_n(int v, hipStream_t st, const EvDesc& ev0, const EvDesc* evs,
                                   const int4* units, int n_units, int spw, const XBin<T>* X,
                                   const MBin<T>* M, T* efield, const C2<T>* tw,
                                   unsigned int* counter, int persistent_blocks)
 {
-    using S = Shape<T, N>;
-    if (n_units <= 0) return hipSuccess;
-    int grid = n_units;
-    if (counter != nullptr) {
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counter, 1);
-        grid = std::min(n_units, persistent_blocks);
+    switch (v) {
+#define V_(VV) \
+    case VV: return launch_unfold_nv<T, N, VV>(st, ev0, evs, units, n_units, spw, X, M, efield, tw, counter, persistent_blocks);
+        V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7)
+#undef V_
     }
-    hipLaunchKernelGGL((k_unfold<T, N, S::E>), dim3(grid), dim3(S::BLOCK), S::LDS, st, ev0, evs,
-                       units, n_units, spw, X, M, efield, tw, counter);
-    return hipGetLastError();
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int N, int V>
+static int occupancy_nv()
+{
+    if constexpr (!variant_built(N, V, (int)sizeof(T))) {
+        return 0;
+    } else {
+        using S = UShape<T, N, V>;
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_unfold<T, N, S::E, S::RMAX, S::TWMODE, S::WAVE>, S::BLOCK,
+                                                         S::LDS) != hipSuccess)
+            return 0;
+        return occ;
+    }
 }
 
 template <typename Tin, typename T>
@@ -442,7 +561,7 @@ static hipError_t launch_spectrum(int n, hipStream_t st, const Tin* volt, const 
 }
 
 template <typename T>
-static hipError_t launch_unfold(int n, hipStream_t st, const EvDesc& ev0, const EvDesc* evs,
+static hipError_t launch_unfold(int n, int v, hipStream_t st, const EvDesc& ev0, const EvDesc* evs,
                                 const int4* units, int n_units, int spw, const XBin<T>* X,
                                 const MBin<T>* M, T* efield, const C2<T>* tw, unsigned int* counter,
                                 int persistent_blocks)
@@ -450,7 +569,7 @@ static hipError_t launch_unfold(int n, hipStream_t st, const EvDesc& ev0, const 
     switch (n) {
 #define X_(NN)                                                                                  \
     case NN:                                                                                    \
-        return launch_unfold_n<T, NN>(st, ev0, evs, units, n_units, spw, X, M, efield, tw,      \
+        return launch_unfold_n<T, NN>(v, st, ev0, evs, units, n_units, spw, X, M, efield, tw,   \
                                       counter, persistent_blocks);
         AU_FOR_EACH_N(X_)
 #undef X_
@@ -459,26 +578,29 @@ static hipError_t launch_unfold(int n, hipStream_t st, const EvDesc& ev0, const 
 }
 
 template <typename T>
-static int persistent_blocks_for(int n, int device)
+static int persistent_blocks_for(int n, int v, int device)
 {
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    int per_cu = 1;
+    int per_cu = 0;
     switch (n) {
-#define X_(NN)                                                                               \
-    case NN: {                                                                               \
-        int occ = 0;                                                                         \
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_unfold<T, NN, Shape<T, NN>::E>, \
-                                                         Shape<T, NN>::BLOCK,                \
-                                                         Shape<T, NN>::LDS) == hipSuccess && \
-            occ > 0)                                                                         \
-            per_cu = occ;                                                                    \
-        break;                                                                               \
-    }
+#define X_(NN)                                                                                  \
+    case NN:                                                                                    \
+        switch (v) {                                                                            \
+            case 0: per_cu = occupancy_nv<T, NN, 0>(); break;                                   \
+            case 1: per_cu = occupancy_nv<T, NN, 1>(); break;                                   \
+            case 2: per_cu = occupancy_nv<T, NN, 2>(); break;                                   \
+            case 3: per_cu = occupancy_nv<T, NN, 3>(); break;                                   \
+            case 4: per_cu = occupancy_nv<T, NN, 4>(); break;                                   \
+            case 5: per_cu = occupancy_nv<T, NN, 5>(); break;                                   \
+            case 6: per_cu = occupancy_nv<T, NN, 6>(); break;                                   \
+            case 7: per_cu = occupancy_nv<T, NN, 7>(); break;                                   \
+        }                                                                                       \
+        break;
         AU_FOR_EACH_N(X_)
 #undef X_
     }
-    return cus * per_cu;
+    return cus * std::max(per_cu, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,14 +671,6 @@ const C2<double>* twiddles<double>(int dev) { return g_tw64[dev]; }
 // ---------------------------------------------------------------------------
 // pattern table
 // ---------------------------------------------------------------------------
-
-struct au_table {
-    int device;
-    int dtype;
-    GridDev g;
-    void* d_nodes;
-    size_t bytes;
-};
 
 static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
@@ -642,10 +756,6 @@ extern "C" au_status au_free_pattern_table(au_table* t)
 // event validation and the band
 // ---------------------------------------------------------------------------
 
-struct EvParams {
-    int S, N, k_lo, nb;
-};
-
 static au_status band_of(int64_t n, int64_t fs, int64_t lo, int64_t hi, int* k_lo, int* nb)
 {
     const int64_t klo = (lo * n + fs - 1) / fs;  // smallest k with k fs >= lo n
@@ -655,7 +765,7 @@ static au_status band_of(int64_t n, int64_t fs, int64_t lo, int64_t hi, int* k_l
     return AU_OK;
 }
 
-static au_status check_common(const au_table* tb, int64_t fs, int64_t lo, int64_t hi, int prec,
+au_status au::check_common(const au_table* tb, int64_t fs, int64_t lo, int64_t hi, int prec,
                               int tin, double fb, double sg)
 {
     if (!tb) return fail(AU_EINVAL, "null table");
@@ -670,7 +780,7 @@ static au_status check_common(const au_table* tb, int64_t fs, int64_t lo, int64_
     return AU_OK;
 }
 
-static au_status check_n(const au_table* tb, int s, int n, int64_t fs, int64_t lo, int64_t hi,
+au_status au::check_n(const au_table* tb, int s, int n, int64_t fs, int64_t lo, int64_t hi,
                          EvParams* p)
 {
     if (n < 16 || n > 4096 || (n & (n - 1)) != 0)
@@ -702,14 +812,12 @@ static au_status check_event(const au_table* tb, const au_event* ev, EvParams* p
     return check_n(tb, ev->n_stations, ev->n_samples, ev->fs_hz, ev->band_lo_hz, ev->band_hi_hz, p);
 }
 
-static bool dirs_finite(const double* h, int64_t n)
+bool au::dirs_finite(const double* h, int64_t n)
 {
     for (int64_t i = 0; i < 2 * n; ++i)
         if (!std::isfinite(h[i]) || std::fabs(h[i]) > 1e6) return false;
     return true;
 }
-
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
     size_t x, m, dirs, total;
@@ -755,8 +863,6 @@ extern "C" au_status au_workspace_bytes(const au_table* tb, const au_event* ev, 
 // single-event path: spectra, coefficients, unfold as three launches
 // ---------------------------------------------------------------------------
 
-constexpr int kStationsPerUnit = 8;
-
 template <typename Tt, typename T>
 static void launch_coef(hipStream_t st, const au_table* tb, const EvDesc& ev0, const EvDesc* evs,
                         const int2* units, int n_units, const double* dirs, double zen, double az,
@@ -771,8 +877,9 @@ template <typename T>
 static au_status run_event(const au_table* tb, const au_event* ev, const EvParams& p,
                            const void* d_volt, int n_dir, const double* h_dirs, double zen,
                            double az, void* d_efield, void* d_work, hipStream_t st,
-                           uint64_t* d_counts)
+                           uint64_t* d_counts, int variant = -1)
 {
+    if (variant < 0) variant = unfold_variant(ev->prec, p.N);
     const WsLayout w = ws_layout(p, ev->prec, n_dir);
     unsigned char* base = (unsigned char*)d_work;
     XBin<T>* X = (XBin<T>*)base;
@@ -807,8 +914,8 @@ static au_status run_event(const au_table* tb, const au_event* ev, const EvParam
     const int chunks = (p.S + kStationsPerUnit - 1) / kStationsPerUnit;
     const int64_t n_units = (int64_t)n_dir * chunks;
     if (n_units > (int64_t)0x7fffffff) return fail(AU_EINVAL, "too many work units");
-    e = launch_unfold<T>(p.N, st, ev0, nullptr, nullptr, (int)n_units, kStationsPerUnit, X, M,
-                         (T*)d_efield, tw, nullptr, 0);
+    e = launch_unfold<T>(p.N, variant, st, ev0, nullptr, nullptr, (int)n_units,
+                         kStationsPerUnit, X, M, (T*)d_efield, tw, nullptr, 0);
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_unfold: ") + hipGetErrorString(e));
     return AU_OK;
 }
@@ -923,6 +1030,7 @@ struct ClassPlan {
     int4* d_uunits = nullptr;
     unsigned int* d_counter = nullptr;
     int persistent_blocks = 0;
+    int variant = 0;
 };
 
 struct au_plan {
@@ -952,43 +1060,82 @@ struct au_plan {
 };
 
 template <typename T>
+static au_status enqueue_class_t(const au_table* tb, int tin, int64_t fs, double fb, double sg,
+                                 const ClassLaunch& c, const void* volt, void* efield, void* Xv, void* Mv,
+                                 const double* dirs, hipStream_t st, uint64_t* d_counts,
+                                 hipEvent_t* stage_events)
+{
+    const C2<T>* tw = twiddles<T>(tb->device);
+    if (tw == nullptr) return fail(AU_EDEVICE, "twiddle tables missing on this device");
+    XBin<T>* X = (XBin<T>*)Xv;
+    MBin<T>* M = (MBin<T>*)Mv;
+    EvDesc ev0{};
+    hipError_t e;
+    if (tin == AU_F64)
+        e = launch_spectrum<double, T>(c.N, st, (const double*)volt, ev0, c.d_evs, c.d_sunits, c.n_sunits, X, tw);
+    else
+        e = launch_spectrum<float, T>(c.N, st, (const float*)volt, ev0, c.d_evs, c.d_sunits, c.n_sunits, X, tw);
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
+    if (stage_events) HIP_TRY(hipEventRecord(stage_events[0], st));
+    if (c.n_cunits > 0) {
+        if (tb->dtype == AU_F64)
+            launch_coef<double, T>(st, tb, ev0, c.d_evs, c.d_cunits, c.n_cunits, dirs, 0, 0, fs, fb, sg, M,
+                                   (unsigned long long*)d_counts);
+        else
+            launch_coef<float, T>(st, tb, ev0, c.d_evs, c.d_cunits, c.n_cunits, dirs, 0, 0, fs, fb, sg, M,
+                                  (unsigned long long*)d_counts);
+        e = hipGetLastError();
+        if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_coef: ") + hipGetErrorString(e));
+    }
+    if (stage_events) HIP_TRY(hipEventRecord(stage_events[1], st));
+    e = launch_unfold<T>(c.N, c.variant, st, ev0, c.d_evs, c.d_uunits, c.n_uunits, kStationsPerUnit, X, M,
+                         (T*)efield, tw, c.d_counter, c.persistent_blocks);
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_unfold: ") + hipGetErrorString(e));
+    if (stage_events) HIP_TRY(hipEventRecord(stage_events[2], st));
+    return AU_OK;
+}
+
+au_status au::enqueue_class(const au_table* tb, int prec, int tin, int64_t fs, double fb, double sg,
+                            const ClassLaunch& c, const void* volt, void* efield, void* X, void* M,
+                            const double* dirs, hipStream_t st, uint64_t* d_counts, hipEvent_t* stage_events)
+{
+    return prec == AU_PREC_FP64
+               ? enqueue_class_t<double>(tb, tin, fs, fb, sg, c, volt, efield, X, M, dirs, st, d_counts, stage_events)
+               : enqueue_class_t<float>(tb, tin, fs, fb, sg, c, volt, efield, X, M, dirs, st, d_counts, stage_events);
+}
+
+int au::current_variant(int prec, int n) { return unfold_variant(prec, n); }
+
+int au::persistent_blocks(int prec, int n, int variant, int device)
+{
+    return prec == AU_PREC_FP64 ? persistent_blocks_for<double>(n, variant, device)
+                                : persistent_blocks_for<float>(n, variant, device);
+}
+
 static au_status plan_enqueue(au_plan* pl, const void* d_volt, void* d_efield, hipStream_t st,
                               uint64_t* d_counts)
 {
-    const au_table* tb = pl->tb;
-    const C2<T>* tw = twiddles<T>(tb->device);
-    XBin<T>* X = (XBin<T>*)pl->d_x;
-    MBin<T>* M = (MBin<T>*)pl->d_m;
-    EvDesc ev0{};
     const bool tm = pl->timing && !pl->ev.empty();
     if (tm) HIP_TRY(hipEventRecord(pl->ev[0], st));
     int ei = 1;
-    for (const ClassPlan& c : pl->classes) {
-        hipError_t e;
-        if (pl->tin == AU_F64)
-            e = launch_spectrum<double, T>(c.N, st, (const double*)d_volt, ev0, c.d_evs, c.d_sunits,
-                                           c.n_sunits, X, tw);
-        else
-            e = launch_spectrum<float, T>(c.N, st, (const float*)d_volt, ev0, c.d_evs, c.d_sunits,
-                                          c.n_sunits, X, tw);
-        if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
-        if (tm) HIP_TRY(hipEventRecord(pl->ev[ei++], st));
-        if (c.n_cunits > 0) {
-            if (tb->dtype == AU_F64)
-                launch_coef<double, T>(st, tb, ev0, c.d_evs, c.d_cunits, c.n_cunits, pl->d_dirs, 0, 0,
-                                       pl->fs, pl->fb, pl->sg, M, (unsigned long long*)d_counts);
-            else
-                launch_coef<float, T>(st, tb, ev0, c.d_evs, c.d_cunits, c.n_cunits, pl->d_dirs, 0, 0,
-                                      pl->fs, pl->fb, pl->sg, M, (unsigned long long*)d_counts);
-            e = hipGetLastError();
-            if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_coef: ") + hipGetErrorString(e));
-        }
-        if (tm) HIP_TRY(hipEventRecord(pl->ev[ei++], st));
-        const bool pers = (pl->flags & AU_PLAN_PERSISTENT) != 0;
-        e = launch_unfold<T>(c.N, st, ev0, c.d_evs, c.d_uunits, c.n_uunits, kStationsPerUnit, X, M,
-                             (T*)d_efield, tw, pers ? c.d_counter : nullptr, c.persistent_blocks);
-        if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_unfold: ") + hipGetErrorString(e));
-        if (tm) HIP_TRY(hipEventRecord(pl->ev[ei++], st));
+    const bool pers = (pl->flags & AU_PLAN_PERSISTENT) != 0;
+    for (const ClassPlan& cp : pl->classes) {
+        ClassLaunch c;
+        c.N = cp.N;
+        c.variant = cp.variant;
+        c.d_evs = cp.d_evs;
+        c.d_sunits = cp.d_sunits;
+        c.n_sunits = cp.n_sunits;
+        c.d_cunits = cp.d_cunits;
+        c.n_cunits = cp.n_cunits;
+        c.d_uunits = cp.d_uunits;
+        c.n_uunits = cp.n_uunits;
+        c.d_counter = pers ? cp.d_counter : nullptr;
+        c.persistent_blocks = cp.persistent_blocks;
+        au_status s = enqueue_class(pl->tb, pl->prec, pl->tin, pl->fs, pl->fb, pl->sg, c, d_volt, d_efield,
+                                    pl->d_x, pl->d_m, pl->d_dirs, st, d_counts, tm ? &pl->ev[ei] : nullptr);
+        if (s != AU_OK) return s;
+        ei += 3;
     }
     if (tm) {
         HIP_TRY(hipEventSynchronize(pl->ev[ei - 1]));
@@ -1153,7 +1300,9 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
         PLAN_TRY(hipMemcpy(c.d_sunits, hc[i].su.data(), hc[i].su.size() * sizeof(int2), hipMemcpyHostToDevice));
         PLAN_TRY(hipMemcpy(c.d_cunits, hc[i].cu.data(), hc[i].cu.size() * sizeof(int2), hipMemcpyHostToDevice));
         PLAN_TRY(hipMemcpy(c.d_uunits, hc[i].uu.data(), hc[i].uu.size() * sizeof(int4), hipMemcpyHostToDevice));
-        c.persistent_blocks = f64 ? persistent_blocks_for<double>(c.N, dev) : persistent_blocks_for<float>(c.N, dev);
+        c.variant = unfold_variant(b->prec, c.N);
+        c.persistent_blocks = f64 ? persistent_blocks_for<double>(c.N, c.variant, dev)
+                                  : persistent_blocks_for<float>(c.N, c.variant, dev);
         pl->classes.push_back(c);
     }
     if (pl->flags & AU_PLAN_GRAPH) PLAN_TRY(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
@@ -1212,9 +1361,8 @@ extern "C" au_status au_plan_run(au_plan* pl, const void* d_volt, void* d_efield
     if (dev != pl->device) return fail(AU_EINVAL, "plan lives on another device");
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = pl->prec == AU_PREC_FP64;
-    if (!(pl->flags & AU_PLAN_GRAPH))
-        return f64 ? plan_enqueue<double>(pl, d_volt, d_efield, st, d_counts)
-                   : plan_enqueue<float>(pl, d_volt, d_efield, st, d_counts);
+    (void)f64;
+    if (!(pl->flags & AU_PLAN_GRAPH)) return plan_enqueue(pl, d_volt, d_efield, st, d_counts);
     if (pl->exec == nullptr || pl->g_volt != d_volt || pl->g_efield != d_efield || pl->g_counts != d_counts) {
         if (pl->exec) {
             (void)hipGraphExecDestroy(pl->exec);
@@ -1225,8 +1373,7 @@ extern "C" au_status au_plan_run(au_plan* pl, const void* d_volt, void* d_efield
             pl->graph = nullptr;
         }
         HIP_TRY(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
-        au_status s = f64 ? plan_enqueue<double>(pl, d_volt, d_efield, pl->cap_stream, d_counts)
-                          : plan_enqueue<float>(pl, d_volt, d_efield, pl->cap_stream, d_counts);
+        au_status s = plan_enqueue(pl, d_volt, d_efield, pl->cap_stream, d_counts);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(pl->cap_stream, &g);
         if (s != AU_OK) {
@@ -1242,4 +1389,146 @@ extern "C" au_status au_plan_run(au_plan* pl, const void* d_volt, void* d_efield
     }
     HIP_TRY(hipGraphLaunch(pl->exec, st));
     return AU_OK;
+}
+
+// ---------------------------------------------------------------------------
+// unfold-kernel variants and the autotuner
+// ---------------------------------------------------------------------------
+
+static au_status check_variant_args(int32_t prec, int32_t n)
+{
+    if (prec != AU_PREC_FP32 && prec != AU_PREC_FP64) return fail(AU_EINVAL, "bad precision");
+    if (n < 16 || n > 4096 || (n & (n - 1)) != 0) return fail(AU_EINVAL, "n_samples must be a power of two in [16, 4096]");
+    return AU_OK;
+}
+
+extern "C" au_status au_unfold_variant_count(int32_t* count, int32_t* e_values, int32_t* rmax,
+                                             int32_t* twmode, int32_t* wave)
+{
+    if (!count) return fail(AU_EINVAL, "null argument");
+    *count = kNumVariants;
+    for (int v = 0; v < kNumVariants; ++v) {
+        if (e_values) e_values[v] = kUnfoldVariants[v].E;
+        if (rmax) rmax[v] = kUnfoldVariants[v].rmax;
+        if (twmode) twmode[v] = kUnfoldVariants[v].twmode;
+        if (wave) wave[v] = kUnfoldVariants[v].wave ? 1 : 0;
+    }
+    return AU_OK;
+}
+
+extern "C" au_status au_set_unfold_variant(int32_t prec, int32_t n_samples, int32_t variant)
+{
+    au_status s = check_variant_args(prec, n_samples);
+    if (s != AU_OK) return s;
+    if (!variant_built(n_samples, variant, prec == AU_PREC_FP64 ? 8 : 4))
+        return fail(AU_EINVAL, "variant not available for this trace length");
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    g_variant[prec == AU_PREC_FP32 ? 1 : 0][ilog2(n_samples)] = variant;
+    return AU_OK;
+}
+
+extern "C" au_status au_get_unfold_variant(int32_t prec, int32_t n_samples, int32_t* variant)
+{
+    au_status s = check_variant_args(prec, n_samples);
+    if (s != AU_OK) return s;
+    if (!variant) return fail(AU_EINVAL, "null argument");
+    *variant = unfold_variant(prec, n_samples);
+    return AU_OK;
+}
+
+// Deterministic filler for autotuning traces (a hash of the index mapped to
+// [-1, 1)); the values do not matter for timing but avoid denormals.
+template <typename Tin>
+__global__ void k_fill_hash(Tin* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t h = (uint32_t)i * 2654435761u;
+    h ^= h >> 16;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    p[i] = (Tin)((double)(h & 0xffffff) / (double)0x800000 - 1.0);
+}
+
+extern "C" au_status au_autotune(const au_table* tb, const au_event* ev, int32_t n_dir, int32_t reps,
+                                 double* ms, int32_t* best)
+{
+    EvParams p;
+    au_status s = check_event(tb, ev, &p);
+    if (s != AU_OK) return s;
+    if (n_dir < 1 || reps < 1) return fail(AU_EINVAL, "n_dir and reps must be >= 1");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != tb->device) return fail(AU_EINVAL, "table lives on another device");
+    const size_t in_el = (size_t)p.S * 2 * p.N;
+    const size_t out_el = (size_t)n_dir * p.S * 2 * p.N;
+    const size_t in_b = in_el * (ev->trace_dtype == AU_F64 ? 8 : 4);
+    const size_t out_b = out_el * (ev->prec == AU_PREC_FP64 ? 8 : 4);
+    const WsLayout w = ws_layout(p, ev->prec, n_dir);
+    std::vector<double> dirs(2 * (size_t)n_dir);
+    for (int d = 0; d < n_dir; ++d) {
+        dirs[2 * d] = tb->g.zen0 + (d + 0.5) * (tb->g.dzen * (tb->g.n_zen - 1)) / n_dir;
+        dirs[2 * d + 1] = tb->g.az0 + d * (360.0 / n_dir);
+    }
+    void *d_in = nullptr, *d_out = nullptr, *d_ws = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    au_status rc = AU_OK;
+    double best_ms = 1e300;
+    int best_v = -1;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st) (void)hipStreamDestroy(st);
+        if (d_in) (void)hipFree(d_in);
+        if (d_out) (void)hipFree(d_out);
+        if (d_ws) (void)hipFree(d_ws);
+    };
+#define TUNE_TRY(expr)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            cleanup();                                                                       \
+            return fail(AU_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+        }                                                                                    \
+    } while (0)
+    TUNE_TRY(hipMalloc(&d_in, in_b));
+    TUNE_TRY(hipMalloc(&d_out, out_b));
+    TUNE_TRY(hipMalloc(&d_ws, w.total));
+    TUNE_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    TUNE_TRY(hipEventCreate(&e0));
+    TUNE_TRY(hipEventCreate(&e1));
+    const int fill_blocks = (int)((in_el + 255) / 256);
+    if (ev->trace_dtype == AU_F64)
+        hipLaunchKernelGGL(k_fill_hash<double>, dim3(fill_blocks), dim3(256), 0, st, (double*)d_in, (int64_t)in_el);
+    else
+        hipLaunchKernelGGL(k_fill_hash<float>, dim3(fill_blocks), dim3(256), 0, st, (float*)d_in, (int64_t)in_el);
+    TUNE_TRY(hipGetLastError());
+    for (int v = 0; v < kNumVariants; ++v) {
+        if (ms) ms[v] = -1.0;
+        if (!variant_built(p.N, v, ev->prec == AU_PREC_FP64 ? 8 : 4)) continue;
+        for (int r = 0; r <= reps && rc == AU_OK; ++r) {
+            if (r == 1) TUNE_TRY(hipEventRecord(e0, st));
+            rc = ev->prec == AU_PREC_FP64
+                     ? run_event<double>(tb, ev, p, d_in, n_dir, dirs.data(), 0, 0, d_out, d_ws, st, nullptr, v)
+                     : run_event<float>(tb, ev, p, d_in, n_dir, dirs.data(), 0, 0, d_out, d_ws, st, nullptr, v);
+        }
+        if (rc != AU_OK) break;
+        TUNE_TRY(hipEventRecord(e1, st));
+        TUNE_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        TUNE_TRY(hipEventElapsedTime(&t, e0, e1));
+        const double avg = (double)t / reps;
+        if (ms) ms[v] = avg;
+        if (avg < best_ms) {
+            best_ms = avg;
+            best_v = v;
+        }
+    }
+#undef TUNE_TRY
+    cleanup();
+    if (rc != AU_OK) return rc;
+    if (best_v < 0) return fail(AU_EINVAL, "no variant could be timed");
+    if (best) *best = best_v;
+    return au_set_unfold_variant(ev->prec, p.N, best_v);
 }

@@ -150,23 +150,176 @@ __device__ __forceinline__ C2<T> twiddle_tab(const C2<T>* __restrict__ tw, int q
     return SIGN < 0 ? w : cconj(w);
 }
 
-// One Stockham pass (and, recursively, all later ones) of an N-point
-// transform held as x[i] = seq[t + (N/E) i] by thread t of its group.
-// NS is the length of the sub-transforms already completed.
-//
-// Butterfly j (j < N/R) takes seq[j + r N/R], r < R; with j = t + (N/E) m it
-// finds them in x[m + r E/R].  It multiplies input r by
-// exp(SIGN 2 pi i r k / (NS R)), k = j mod NS, runs the R-point DFT, and
-// output r belongs at position (j - k) R + k + r NS of the next sequence.
-template <typename T, int N, int E, int NS, int SIGN>
-__device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
-                                         const C2<T>* __restrict__ tw, int t)
+// ---------------------------------------------------------------------------
+// Compile-time roots of unity: exp(2 pi i p / q) for integers p, q.  The
+// turn fraction is reduced exactly to a quadrant and then to [0, pi/4], where
+// the Taylor series of sin and cos converge to double precision in 14 terms.
+// ---------------------------------------------------------------------------
+struct CxRoot {
+    double c, s;
+};
+
+constexpr double cx_half_pi = 1.57079632679489661923132169163975144;
+
+constexpr double cx_sin_series(double x)
 {
-    constexpr int R = (N / NS < E) ? N / NS : E;
+    double term = x, sum = x;
+    for (int n = 1; n < 14; ++n) {
+        term *= -x * x / (double)((2 * n) * (2 * n + 1));
+        sum += term;
+    }
+    return sum;
+}
+
+constexpr double cx_cos_series(double x)
+{
+    double term = 1.0, sum = 1.0;
+    for (int n = 1; n < 14; ++n) {
+        term *= -x * x / (double)((2 * n - 1) * (2 * n));
+        sum += term;
+    }
+    return sum;
+}
+
+constexpr CxRoot cx_root(long long p, long long q)
+{
+    p %= q;
+    if (p < 0) p += q;
+    const long long quad = (4 * p) / q;       // quarter turns
+    const long long rem = 4 * p - quad * q;   // remaining angle = (pi/2) rem / q
+    double c0 = 1.0, s0 = 0.0;
+    if (2 * rem <= q) {
+        const double x = cx_half_pi * (double)rem / (double)q;
+        c0 = cx_cos_series(x);
+        s0 = cx_sin_series(x);
+    } else {
+        const double x = cx_half_pi * (double)(q - rem) / (double)q;
+        c0 = cx_sin_series(x);
+        s0 = cx_cos_series(x);
+    }
+    if (rem == 0) {
+        c0 = 1.0;
+        s0 = 0.0;
+    }
+    switch (quad & 3) {
+        case 0: return CxRoot{c0, s0};
+        case 1: return CxRoot{-s0, c0};
+        case 2: return CxRoot{-c0, -s0};
+        default: return CxRoot{s0, -c0};
+    }
+}
+
+// LDS index with one pad slot every 16 elements: the radix-R scatter of a
+// pass (stride R or NS between lanes) no longer lands every lane of a wave in
+// the same bank.
+__device__ __forceinline__ constexpr int lpad(int i) { return i + (i >> 4); }
+
+template <int N>
+constexpr int lds_elems() { return N + N / 16; }
+
+// ---------------------------------------------------------------------------
+// Pass structure.  An N-point transform runs on TT = N/E threads holding E
+// values each; the pass that starts from completed sub-transforms of length
+// NS has radix R = min(RMAX, N/NS), and each thread runs B = E/R of its
+// butterflies (butterfly j = t + TT m, m < B).
+//
+// Twiddle modes (the pass multiplies input r of butterfly j by
+// exp(SIGN 2 pi i r k / (NS R)), k = j mod NS):
+//   TW_TABLE: read from the table each time.
+//   TW_REG:   every (m, r) factor of every pass in registers, loaded once.
+//   TW_SPLIT: R-1 registers per pass.  If NS <= TT then k = t mod NS for
+//             every m and the registers hold the factors themselves; if
+//             NS > TT then k = t + (TT m mod NS) and the factor splits into
+//             exp(SIGN 2 pi i r t / (NS R)) (register) times
+//             exp(SIGN 2 pi i r (TT m mod NS) / (NS R)) (compile-time
+//             constant).
+// ---------------------------------------------------------------------------
+enum { TW_TABLE = 0, TW_REG = 1, TW_SPLIT = 2 };
+
+template <int N, int RMAX>
+constexpr int pass_radix(int ns) { return (N / ns < RMAX) ? N / ns : RMAX; }
+
+template <int N, int E, int RMAX, int TWMODE>
+constexpr int tw_offset(int ns_target)
+{
+    int off = 0;
+    for (int ns = 1; ns < ns_target && ns < N; ns *= pass_radix<N, RMAX>(ns)) {
+        if (ns == 1) continue;
+        const int r = pass_radix<N, RMAX>(ns);
+        off += TWMODE == TW_REG ? (E / r) * (r - 1) : (r - 1);
+    }
+    return off;
+}
+
+template <int N, int E, int RMAX, int TWMODE>
+constexpr int tw_count()
+{
+    return TWMODE == TW_TABLE ? 1 : (tw_offset<N, E, RMAX, TWMODE>(N) > 0 ? tw_offset<N, E, RMAX, TWMODE>(N) : 1);
+}
+
+template <typename T, int N, int E, int RMAX, int TWMODE, int NS, int SIGN>
+__device__ __forceinline__ void load_twiddles_from(C2<T>* __restrict__ w, const C2<T>* __restrict__ tw, int t)
+{
+    if constexpr (NS < N) {
+        constexpr int R = pass_radix<N, RMAX>(NS);
+        if constexpr (NS > 1) {
+            constexpr int TT = N / E, B = E / R, STRIDE = kTwN / (NS * R);
+            constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
+            if constexpr (TWMODE == TW_REG) {
+#pragma unroll
+                for (int m = 0; m < B; ++m) {
+                    const int k = (t + TT * m) & (NS - 1);
+#pragma unroll
+                    for (int r = 1; r < R; ++r) w[OFF + m * (R - 1) + r - 1] = twiddle_tab<SIGN>(tw, r * k * STRIDE);
+                }
+            } else {
+                // TW_SPLIT: k = t mod NS (NS <= TT) or the t part of k (NS > TT)
+                const int k = (NS <= TT) ? (t & (NS - 1)) : t;
+#pragma unroll
+                for (int r = 1; r < R; ++r) w[OFF + r - 1] = twiddle_tab<SIGN>(tw, r * k * STRIDE);
+            }
+        }
+        load_twiddles_from<T, N, E, RMAX, TWMODE, NS * R, SIGN>(w, tw, t);
+    }
+}
+
+template <typename T, int N, int E, int RMAX, int TWMODE, int SIGN>
+__device__ __forceinline__ void load_twiddles(C2<T>* __restrict__ w, const C2<T>* __restrict__ tw, int t)
+{
+    if constexpr (TWMODE != TW_TABLE) load_twiddles_from<T, N, E, RMAX, TWMODE, 1, SIGN>(w, tw, t);
+}
+
+// Synchronisation between the LDS scatter of one pass and the gather of the
+// next: a workgroup barrier, or -- when one wavefront owns the transform --
+// only a wave-level fence (LDS operations of one wave complete in order).
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// One Stockham pass (and, recursively, all later ones) of an N-point
+// transform held as x[i] = seq[t + TT i] by thread t of its group.
+// Butterfly j takes seq[j + r N/R], r < R; with j = t + TT m it finds them in
+// x[m + r B].  It multiplies input r by exp(SIGN 2 pi i r k / (NS R)),
+// k = j mod NS, runs the R-point DFT, and output r belongs at position
+// (j - k) R + k + r NS of the next sequence (natural order after the last
+// pass, which therefore stays in registers).  LDS positions use lpad().
+template <typename T, int N, int E, int RMAX, int TWMODE, bool WAVE, int NS, int SIGN>
+__device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
+                                         const C2<T>* __restrict__ tw, const C2<T>* __restrict__ w, int t)
+{
+    constexpr int R = pass_radix<N, RMAX>(NS);
     constexpr int TT = N / E;
     constexpr int B = E / R;
     constexpr bool LAST = (NS * R == N);
-    static_assert(R >= 2 || N == 1, "radix");
+    static_assert(R >= 2 && E % R == 0, "radix");
 #pragma unroll
     for (int m = 0; m < B; ++m) {
         const int j = t + TT * m;
@@ -176,8 +329,27 @@ __device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
         for (int r = 0; r < R; ++r) v[r] = x[m + r * B];
         if constexpr (NS > 1) {
             constexpr int STRIDE = kTwN / (NS * R);
+            constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twiddle_tab<SIGN>(tw, r * k * STRIDE));
+            for (int r = 1; r < R; ++r) {
+                C2<T> wr;
+                if constexpr (TWMODE == TW_TABLE) {
+                    wr = twiddle_tab<SIGN>(tw, r * k * STRIDE);
+                } else if constexpr (TWMODE == TW_REG) {
+                    wr = w[OFF + m * (R - 1) + r - 1];
+                } else {
+                    wr = w[OFF + r - 1];
+                    if constexpr (NS > TT) {
+                        const int p = (r * ((TT * m) % NS)) % (NS * R);
+                        if (p != 0) {
+                            constexpr int Q = NS * R;
+                            const CxRoot cr = cx_root(SIGN > 0 ? p : Q - p, Q);
+                            wr = cmul(wr, C2<T>{(T)cr.c, (T)cr.s});
+                        }
+                    }
+                }
+                v[r] = cmul(v[r], wr);
+            }
         }
         Dft<R, SIGN, T>::run(v);
         if constexpr (LAST) {
@@ -186,27 +358,29 @@ __device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
         } else {
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[base + r * NS] = v[r];
+            for (int r = 0; r < R; ++r) lds[lpad(base + r * NS)] = v[r];
         }
     }
     if constexpr (!LAST) {
-        __syncthreads();
+        lds_sync<WAVE>();
 #pragma unroll
-        for (int i = 0; i < E; ++i) x[i] = lds[t + TT * i];
-        __syncthreads();
-        fft_pass<T, N, E, NS * R, SIGN>(x, lds, tw, t);
+        for (int i = 0; i < E; ++i) x[i] = lds[lpad(t + TT * i)];
+        lds_sync<WAVE>();
+        fft_pass<T, N, E, RMAX, TWMODE, WAVE, NS * R, SIGN>(x, lds, tw, w, t);
     }
 }
 
 // Full N-point transform of the group's sequence, exp(SIGN ...) kernel, no
-// scaling.  Every thread of the workgroup must call it (it contains
-// workgroup barriers when N > E).
-template <typename T, int N, int E, int SIGN>
+// scaling.  Every thread of the group must call it; unless WAVE it contains
+// workgroup barriers, so every thread of the workgroup must call it.
+// `w` holds the per-thread twiddles of load_twiddles (unused for TW_TABLE).
+template <typename T, int N, int E, int SIGN, int TWMODE = TW_TABLE, int RMAX = E, bool WAVE = false>
 __device__ __forceinline__ void fft(C2<T> (&x)[E], C2<T>* __restrict__ lds,
-                                    const C2<T>* __restrict__ tw, int t)
+                                    const C2<T>* __restrict__ tw, int t,
+                                    const C2<T>* __restrict__ w = nullptr)
 {
-    static_assert((N & (N - 1)) == 0 && N >= E && (E & (E - 1)) == 0 && E <= 32, "sizes");
-    fft_pass<T, N, E, 1, SIGN>(x, lds, tw, t);
+    static_assert((N & (N - 1)) == 0 && N >= E && (E & (E - 1)) == 0 && RMAX <= 32, "sizes");
+    fft_pass<T, N, E, (RMAX < E ? RMAX : E), TWMODE, WAVE, 1, SIGN>(x, lds, tw, w, t);
 }
 
 }  // namespace au

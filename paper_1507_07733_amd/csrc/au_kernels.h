@@ -57,7 +57,7 @@ constexpr int groups_per_block()
 {
     constexpr int tt = N / E;
     int g = tt >= kBlock ? 1 : kBlock / tt;
-    const int cap = 65536 / (N * (int)sizeof(C2<T>));
+    const int cap = 65536 / (lds_elems<N>() * (int)sizeof(C2<T>));
     if (g > cap) g = cap;
     return g < 1 ? 1 : g;
 }

@@ -251,3 +251,39 @@ def test_workspace_argument_and_errors(api, coarse):
     t32 = api.Table(G, t.astype(np.complex64))
     with pytest.raises(api.AuError):
         api.workspace_bytes(t32, ev32, 1)        # FP64 needs a complex128 table
+
+
+@pytest.mark.parametrize("n", [1024, 2048, 4096])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_every_unfold_variant(api, coarse, n, prec):
+    t, tab = coarse
+    p = api.AU_PREC_FP64 if prec == "fp64" else api.AU_PREC_FP32
+    s = 5
+    v = S.traces(s, n, cfg=3, event=n)
+    dirs = np.array([[40.0, 120.0], [72.5, 359.0], [5.0, 3.0]])
+    ev = api.make_event(s, n, prec=p)
+    ref, _, _ = oracle_unfold(G, t, v, dirs)
+    keep = api.get_unfold_variant(p, n)
+    built = 0
+    try:
+        for vi, (e, rmax, twmode, wave) in enumerate(api.unfold_variants()):
+            try:
+                api.set_unfold_variant(p, n, vi)
+            except api.AuError:
+                continue                      # not built for this size / precision
+            built += 1
+            say("variant", vi, "E", e, "rmax", rmax, "twmode", twmode, "wave", wave, prec, "N", n)
+            out = api.unfold_direction_scan(tab, ev, to_dev(v), dirs).cpu().numpy()
+            assert_traces_close(out, ref, TOL_FP64 if prec == "fp64" else TOL_FP32, "variant %d" % vi)
+    finally:
+        api.set_unfold_variant(p, n, keep)
+    assert built >= 4
+
+
+def test_autotune_selects_a_built_variant(api, coarse):
+    t, tab = coarse
+    ev = api.make_event(16, 2048, prec=api.AU_PREC_FP64)
+    say("autotune fp64 2048")
+    best, ms = api.autotune(tab, ev, n_dir=4, reps=1)
+    assert ms[best] > 0 and ms[best] == min(m for m in ms if m > 0)
+    assert api.get_unfold_variant(api.AU_PREC_FP64, 2048) == best
