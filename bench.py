@@ -200,7 +200,7 @@ def serving_benchmark(api, synth, tab32, tab64, rate_hz=2000.0, duration_s=3.0, 
     # plain FP64 per-event loop on the same arrival stream
     dev = torch.device("cuda:0")
     smax = int(sizes.max())
-    out = torch.empty((len(dirs), smax, 2, 2048), dtype=torch.float64, device=dev)
+    out_flat = torch.empty(len(dirs) * smax * 2 * 2048, dtype=torch.float64, device=dev)
     ev_max = api.make_event(smax, 2048, prec=api.AU_PREC_FP64, trace_dtype=api.AU_F64)
     work = torch.empty(api.workspace_bytes(tab64, ev_max, len(dirs)), dtype=torch.uint8, device=dev)
     vols64 = [torch.from_numpy(v.astype(np.float64)).pin_memory() for v in vols]
@@ -217,9 +217,8 @@ def serving_benchmark(api, synth, tab32, tab64, rate_hz=2000.0, duration_s=3.0, 
         dv = dvol[:s]
         dv.copy_(v)
         ev = api.make_event(s, 2048, prec=api.AU_PREC_FP64, trace_dtype=api.AU_F64)
-        o = out[:, :s]
-        api.unfold_direction_scan(tab64, ev, dv, dirs, out=o.view(-1)[: len(dirs) * s * 2 * 2048].view(len(dirs), s, 2, 2048),
-                                  work=work)
+        o = out_flat[: len(dirs) * s * 2 * 2048].view(len(dirs), s, 2, 2048)
+        api.unfold_direction_scan(tab64, ev, dv, dirs, out=o, work=work)
         torch.cuda.synchronize()
         if a >= warm_s:
             lat2.append(time.perf_counter() - target)
@@ -243,6 +242,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--flags", type=int, default=2, help="plan flags: 1 graph, 2 persistent")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults or --variant-*)")
+    ap.add_argument("--variant-fp32", default="", help="pin FP32 unfold variants: V (every N >= 1024) or N=V,N=V")
+    ap.add_argument("--variant-fp64", default="", help="pin FP64 unfold variants: V (every N >= 1024) or N=V,N=V")
+    ap.add_argument("--probe-gib", type=float, default=4.0, help="size of the HBM copy probe")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -257,6 +260,34 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
 
+    for prec, spec in ((api.AU_PREC_FP32, args.variant_fp32), (api.AU_PREC_FP64, args.variant_fp64)):
+        for item in filter(None, spec.split(",")):
+            if "=" in item:
+                n, v = item.split("=")
+                api.set_unfold_variant(prec, int(n), int(v))
+            else:
+                for n in (1024, 2048, 4096):
+                    api.set_unfold_variant(prec, n, int(item))
+
+    # ---------------- HBM copy probe ---------------------------------------
+    nbytes = int(args.probe_gib * (1 << 30)) // 16 * 16
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    api.hbm_copy(dst, src, nbytes)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    ev0.record(stream)
+    for _ in range(reps):
+        api.hbm_copy(dst, src, nbytes)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = ev0.elapsed_time(ev1) / reps
+    copy_gbs = 2 * nbytes / (copy_ms / 1e3) / 1e9
+    log("hbm copy probe: %.0f MiB in %.3f ms -> %.0f GB/s (read + write)" % (nbytes / 2**20, copy_ms, copy_gbs))
+    del src, dst
+    torch.cuda.empty_cache()
+
     # ---------------- batched FP32 workload -------------------------------
     t0 = time.perf_counter()
     grid = synth.GRID_FINE
@@ -264,9 +295,9 @@ def main():
     tab = api.Table(grid, table)
     specs = build_batched_workload(args.events)
     tuned = {}
-    for n in sorted(set(sp[1] for sp in specs)):
+    for n in sorted(set(sp[1] for sp in specs)) if not args.no_tune else []:
         best, ms = api.autotune(tab, api.make_event(124, n, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32),
-                                n_dir=64, reps=3)
+                                n_dir=256, reps=5)
         tuned["fp32_N%d" % n] = {"variant": best, "shape": api.unfold_variants()[best], "ms": ms}
         log("autotune fp32 N=%d: variant %d %s" % (n, best, api.unfold_variants()[best]))
     flags = args.flags & ~api.AU_PLAN_GRAPH      # stage timing needs eager launches
@@ -298,10 +329,11 @@ def main():
 
     classes = plan.classes()
     per_class = []
-    for ci, (n, su) in enumerate(classes):
+    for ci, (n, su, var) in enumerate(classes):
         unfold_ms = stage_ms[ci, 2] / runs
         bytes_launch = su * 2 * n * 4
-        per_class.append({"kernel": "k_unfold<float, %d, 16>" % n, "n_samples": n,
+        per_class.append({"kernel": api.unfold_kernel_name(api.AU_PREC_FP32, n, var), "variant": var,
+                          "n_samples": n,
                           "station_unfolds": int(su),
                           "spectrum_ms": stage_ms[ci, 0] / runs, "coef_ms": stage_ms[ci, 1] / runs,
                           "unfold_ms": unfold_ms,
@@ -312,6 +344,8 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None,
                 "bytes_per_unit": "2*N*4 B written per station-unfold",
+                "launch_ms": dom["unfold_ms"], "station_unfolds_per_launch": dom["station_unfolds"],
+                "measured_copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "per_class": per_class}
 
     # graph replay of the same plan, for reference
@@ -341,9 +375,10 @@ def main():
         dirs1 = synth.direction_grid(32, 64)
         v1 = torch.from_numpy(synth.traces(s1, n1, cfg=1, event=0)).to(dev)
         ev = api.make_event(s1, n1, prec=api.AU_PREC_FP64, trace_dtype=api.AU_F64)
-        best, ms = api.autotune(t1, ev, n_dir=64, reps=3)
-        tuned["fp64_N%d" % n1] = {"variant": best, "shape": api.unfold_variants()[best], "ms": ms}
-        log("autotune fp64 N=%d: variant %d" % (n1, best))
+        if not args.no_tune:
+            best, ms = api.autotune(t1, ev, n_dir=256, reps=5)
+            tuned["fp64_N%d" % n1] = {"variant": best, "shape": api.unfold_variants()[best], "ms": ms}
+            log("autotune fp64 N=%d: variant %d" % (n1, best))
         work = torch.empty(api.workspace_bytes(t1, ev, len(dirs1)), dtype=torch.uint8, device=dev)
         del efield
         torch.cuda.empty_cache()

@@ -224,7 +224,7 @@ au_status au_plan_run(au_plan* plan, const void* d_volt, void* d_efield, void* s
  */
 au_status au_plan_timing(au_plan* plan, int32_t enable);
 au_status au_plan_classes(const au_plan* plan, int32_t max, int32_t* n_samples,
-                          uint64_t* station_unfolds, int32_t* n_classes);
+                          uint64_t* station_unfolds, int32_t* variants, int32_t* n_classes);
 au_status au_plan_stage_ms(const au_plan* plan, int32_t max, double* ms, uint64_t* runs);
 au_status au_plan_free(au_plan* plan);
 
@@ -320,6 +320,15 @@ au_status au_set_unfold_variant(int32_t prec, int32_t n_samples, int32_t variant
 au_status au_get_unfold_variant(int32_t prec, int32_t n_samples, int32_t* variant);
 au_status au_autotune(const au_table* table, const au_event* ev, int32_t n_dir, int32_t reps,
                       double* ms, int32_t* best);
+
+/*
+ * HBM copy probe: copies `bytes` (a multiple of 16; both pointers 16-byte
+ * aligned) from d_src to d_dst with 16-byte loads and non-temporal stores on
+ * a grid-stride loop, enqueued on `stream`.  It is the reference for
+ * achievable HBM bandwidth and for calibrating the memory-traffic counters
+ * of a profiler against a transfer of known size.
+ */
+au_status au_hbm_copy(void* d_dst, const void* d_src, uint64_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -113,7 +113,8 @@ _SIG = {
     "au_plan_free": (C.c_int32, [_VP]),
     "au_plan_timing": (C.c_int32, [_VP, C.c_int32]),
     "au_plan_classes": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_uint64),
-                                    C.POINTER(C.c_int32)]),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "au_hbm_copy": (C.c_int32, [_VP, _VP, C.c_uint64, _VP]),
     "au_plan_stage_ms": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "au_unfold_variant_count": (C.c_int32, [C.POINTER(C.c_int32)] * 5),
     "au_set_unfold_variant": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
@@ -298,6 +299,22 @@ def pattern_response(table: Table, ev: AuEvent, dirs, device=None, stream=None):
     return torch.view_as_complex(out)
 
 
+def hbm_copy(dst, src, nbytes: int = None, stream=None):
+    """Device-to-device copy with the library's bandwidth probe kernel."""
+    n = nbytes if nbytes is not None else min(dst.numel() * dst.element_size(), src.numel() * src.element_size())
+    _check(lib().au_hbm_copy(_ptr(dst), _ptr(src), int(n), _stream_handle(stream)))
+
+
+def unfold_kernel_name(prec: int, n: int, variant: int) -> str:
+    """Template name of the unfold kernel a (precision, N, variant) launches."""
+    e, rmax, tw, wave = unfold_variants()[variant]
+    e = n // 64 if e == 0 else e
+    e = min(e, n)
+    rmax = min(rmax, e)
+    t = "double" if prec == AU_PREC_FP64 else "float"
+    return "k_unfold<%s, %d, %d, %d, %d, %s>" % (t, n, e, rmax, tw, "true" if wave else "false")
+
+
 def unfold_variants():
     """[(E, rmax, twmode, wave)] of the unfold-kernel shapes the library is built in."""
     n = C.c_int32()
@@ -379,13 +396,14 @@ class Plan:
         _check(lib().au_plan_timing(self.handle, 1 if enable else 0))
 
     def classes(self):
-        """[(n_samples, station_unfolds)] per trace-length class, in stage order."""
+        """[(n_samples, station_unfolds, unfold variant)] per trace-length class, in stage order."""
         nc = C.c_int32()
-        _check(lib().au_plan_classes(self.handle, 0, None, None, C.byref(nc)))
+        _check(lib().au_plan_classes(self.handle, 0, None, None, None, C.byref(nc)))
         ns = (C.c_int32 * max(nc.value, 1))()
         su = (C.c_uint64 * max(nc.value, 1))()
-        _check(lib().au_plan_classes(self.handle, nc.value, ns, su, C.byref(nc)))
-        return [(ns[i], su[i]) for i in range(nc.value)]
+        va = (C.c_int32 * max(nc.value, 1))()
+        _check(lib().au_plan_classes(self.handle, nc.value, ns, su, va, C.byref(nc)))
+        return [(ns[i], su[i], va[i]) for i in range(nc.value)]
 
     def stage_ms(self):
         """(per-class [spectrum, coef, unfold] summed ms, number of timed runs)."""
