@@ -240,7 +240,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--flags", type=int, default=2, help="plan flags: 1 graph, 2 persistent")
+    ap.add_argument("--flags", type=int, default=6, help="plan flags: 1 graph, 2 persistent, 4 XCD placement")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults or --variant-*)")
     ap.add_argument("--variant-fp32", default="", help="pin FP32 unfold variants: V (every N >= 1024) or N=V,N=V")

@@ -189,10 +189,14 @@ au_status au_pattern_response(const au_table* table, const au_event* ev, int32_t
  * allocates nothing).  flags: AU_PLAN_GRAPH to capture the launch sequence in
  * a hipGraph on first run (re-captured if d_volt / d_efield change),
  * AU_PLAN_PERSISTENT to run the unfold stage as a persistent kernel fed by an
- * atomic work counter.
+ * atomic work counter, AU_PLAN_XCD to place all station chunks of one
+ * (event, direction) on one of the 8 XCDs (8 unit lists balanced by work;
+ * workgroup b takes units from list b mod 8, then steals) so that the
+ * direction's coefficient row is fetched into one XCD's L2 only.
  */
 #define AU_PLAN_GRAPH 1
 #define AU_PLAN_PERSISTENT 2
+#define AU_PLAN_XCD 4
 typedef struct {
     int32_t n_events;
     int32_t prec;
@@ -329,6 +333,9 @@ au_status au_autotune(const au_table* table, const au_event* ev, int32_t n_dir, 
  * of a profiler against a transfer of known size.
  */
 au_status au_hbm_copy(void* d_dst, const void* d_src, uint64_t bytes, void* stream);
+/* Write-only probe: fills `bytes` (multiple of 16, aligned) with a 32-bit value
+ * using non-temporal stores -- the reference for a write-bound kernel. */
+au_status au_hbm_fill(void* d_dst, uint64_t bytes, uint32_t value, void* stream);
 
 #ifdef __cplusplus
 }

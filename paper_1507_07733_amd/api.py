@@ -29,6 +29,7 @@ AU_PREC_FP64 = 0
 AU_PREC_FP32 = 1
 AU_PLAN_GRAPH = 1
 AU_PLAN_PERSISTENT = 2
+AU_PLAN_XCD = 4
 
 FS_HZ = 200_000_000
 BAND_LO_HZ = 30_000_000
@@ -115,6 +116,7 @@ _SIG = {
     "au_plan_classes": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_uint64),
                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "au_hbm_copy": (C.c_int32, [_VP, _VP, C.c_uint64, _VP]),
+    "au_hbm_fill": (C.c_int32, [_VP, C.c_uint64, C.c_uint32, _VP]),
     "au_plan_stage_ms": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "au_unfold_variant_count": (C.c_int32, [C.POINTER(C.c_int32)] * 5),
     "au_set_unfold_variant": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
@@ -303,6 +305,12 @@ def hbm_copy(dst, src, nbytes: int = None, stream=None):
     """Device-to-device copy with the library's bandwidth probe kernel."""
     n = nbytes if nbytes is not None else min(dst.numel() * dst.element_size(), src.numel() * src.element_size())
     _check(lib().au_hbm_copy(_ptr(dst), _ptr(src), int(n), _stream_handle(stream)))
+
+
+def hbm_fill(dst, nbytes: int = None, value: int = 0, stream=None):
+    """Write-only bandwidth probe (non-temporal stores)."""
+    n = nbytes if nbytes is not None else dst.numel() * dst.element_size()
+    _check(lib().au_hbm_fill(_ptr(dst), int(n), int(value), _stream_handle(stream)))
 
 
 def unfold_kernel_name(prec: int, n: int, variant: int) -> str:

@@ -310,26 +310,58 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold(
                                                    const MBin<T>* __restrict__ M,
                                                    T* __restrict__ efield,
                                                    const C2<T>* __restrict__ tw,
-                                                   unsigned int* __restrict__ counter)
+                                                   unsigned int* __restrict__ counter,
+                                                   const int* __restrict__ xcd_off)
 {
     constexpr int TT = N / E;
     constexpr int G = groups_per_block<T, N, E>();
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sh_u;
+    __shared__ int sh_list;
     const int g = threadIdx.x / TT, t = threadIdx.x % TT;
     C2<T>* lds = reinterpret_cast<C2<T>*>(smem) + g * lds_elems<N>();
     C2<T> w[tw_count<N, E, RMAX, TWMODE>()];
     load_twiddles<T, N, E, RMAX, TWMODE, +1>(w, tw, t);
+    // XCD-aware placement (xcd_off != nullptr): the unit array holds 8 lists,
+    // list x = [xcd_off[x], xcd_off[x+1]), built so that all station chunks of
+    // one (event, direction) -- which share a coefficient row -- sit in one
+    // list.  Workgroups are dispatched round-robin over the 8 XCDs, so block b
+    // runs on XCD b mod 8 and takes its units from that list (persistent: from
+    // that list's counter, then from the other lists once it is empty), and
+    // the coefficient row is fetched into one XCD's L2 only.
+    if (threadIdx.x == 0) sh_list = blockIdx.x & 7;
     for (int iter = 0;; ++iter) {
         int u;
         if (counter != nullptr) {
-            if (threadIdx.x == 0) sh_u = (int)atomicAdd(counter, 1u);
+            if (threadIdx.x == 0) {
+                int got = n_units;
+                if (xcd_off != nullptr) {
+                    for (int k = 0; k < 8; ++k) {
+                        const int x = (sh_list + k) & 7;
+                        const unsigned cnt = (unsigned)(xcd_off[x + 1] - xcd_off[x]);
+                        if (cnt == 0) continue;
+                        const unsigned i = atomicAdd(&counter[x], 1u);
+                        if (i < cnt) {
+                            got = xcd_off[x] + (int)i;
+                            sh_list = x;
+                            break;
+                        }
+                    }
+                } else {
+                    got = (int)atomicAdd(counter, 1u);
+                }
+                sh_u = got;
+            }
             __syncthreads();
             u = sh_u;
             __syncthreads();
         } else {
             if (iter > 0) break;
             u = blockIdx.x;
+            if (xcd_off != nullptr) {
+                const int x = blockIdx.x & 7, i = blockIdx.x >> 3;
+                u = (i < xcd_off[x + 1] - xcd_off[x]) ? xcd_off[x] + i : n_units;
+            }
         }
         if (u >= n_units) break;
         int e = 0, d, s0, s1;
@@ -500,20 +532,21 @@ template <typename T, int N, int V>
 static hipError_t launch_unfold_nv(hipStream_t st, const EvDesc& ev0, const EvDesc* evs,
                                    const int4* units, int n_units, int spw, const XBin<T>* X,
                                    const MBin<T>* M, T* efield, const C2<T>* tw,
-                                   unsigned int* counter, int persistent_blocks)
+                                   unsigned int* counter, int persistent_blocks, const int* xcd_off,
+                                   int xcd_max_list)
 {
     if constexpr (!variant_built(N, V, (int)sizeof(T))) {
         return hipErrorInvalidValue;
     } else {
         using S = UShape<T, N, V>;
         if (n_units <= 0) return hipSuccess;
-        int grid = n_units;
+        int grid = xcd_off != nullptr ? 8 * xcd_max_list : n_units;
         if (counter != nullptr) {
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counter, 1);
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counter, 8);
             grid = std::min(n_units, persistent_blocks);
         }
         hipLaunchKernelGGL((k_unfold<T, N, S::E, S::RMAX, S::TWMODE, S::WAVE>), dim3(grid), dim3(S::BLOCK), S::LDS, st,
-                           ev0, evs, units, n_units, spw, X, M, efield, tw, counter);
+                           ev0, evs, units, n_units, spw, X, M, efield, tw, counter, xcd_off);
         return hipGetLastError();
     }
 }
@@ -522,11 +555,12 @@ template <typename T, int N>
 static hipError_t launch_unfold_n(int v, hipStream_t st, const EvDesc& ev0, const EvDesc* evs,
                                   const int4* units, int n_units, int spw, const XBin<T>* X,
                                   const MBin<T>* M, T* efield, const C2<T>* tw,
-                                  unsigned int* counter, int persistent_blocks)
+                                  unsigned int* counter, int persistent_blocks, const int* xcd_off,
+                                  int xcd_max_list)
 {
     switch (v) {
 #define V_(VV) \
-    case VV: return launch_unfold_nv<T, N, VV>(st, ev0, evs, units, n_units, spw, X, M, efield, tw, counter, persistent_blocks);
+    case VV: return launch_unfold_nv<T, N, VV>(st, ev0, evs, units, n_units, spw, X, M, efield, tw, counter, persistent_blocks, xcd_off, xcd_max_list);
         V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7)
 #undef V_
     }
@@ -566,13 +600,13 @@ template <typename T>
 static hipError_t launch_unfold(int n, int v, hipStream_t st, const EvDesc& ev0, const EvDesc* evs,
                                 const int4* units, int n_units, int spw, const XBin<T>* X,
                                 const MBin<T>* M, T* efield, const C2<T>* tw, unsigned int* counter,
-                                int persistent_blocks)
+                                int persistent_blocks, const int* xcd_off = nullptr, int xcd_max_list = 0)
 {
     switch (n) {
 #define X_(NN)                                                                                  \
     case NN:                                                                                    \
         return launch_unfold_n<T, NN>(v, st, ev0, evs, units, n_units, spw, X, M, efield, tw,   \
-                                      counter, persistent_blocks);
+                                      counter, persistent_blocks, xcd_off, xcd_max_list);
         AU_FOR_EACH_N(X_)
 #undef X_
     }
@@ -1033,6 +1067,8 @@ struct ClassPlan {
     unsigned int* d_counter = nullptr;
     int persistent_blocks = 0;
     int variant = 0;
+    int* d_xcd_off = nullptr;
+    int xcd_max_list = 0;
 };
 
 struct au_plan {
@@ -1091,7 +1127,7 @@ static au_status enqueue_class_t(const au_table* tb, int tin, int64_t fs, double
     }
     if (stage_events) HIP_TRY(hipEventRecord(stage_events[1], st));
     e = launch_unfold<T>(c.N, c.variant, st, ev0, c.d_evs, c.d_uunits, c.n_uunits, kStationsPerUnit, X, M,
-                         (T*)efield, tw, c.d_counter, c.persistent_blocks);
+                         (T*)efield, tw, c.d_counter, c.persistent_blocks, c.d_xcd_off, c.xcd_max_list);
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_unfold: ") + hipGetErrorString(e));
     if (stage_events) HIP_TRY(hipEventRecord(stage_events[2], st));
     return AU_OK;
@@ -1134,6 +1170,8 @@ static au_status plan_enqueue(au_plan* pl, const void* d_volt, void* d_efield, h
         c.n_uunits = cp.n_uunits;
         c.d_counter = pers ? cp.d_counter : nullptr;
         c.persistent_blocks = cp.persistent_blocks;
+        c.d_xcd_off = cp.d_xcd_off;
+        c.xcd_max_list = cp.xcd_max_list;
         au_status s = enqueue_class(pl->tb, pl->prec, pl->tin, pl->fs, pl->fb, pl->sg, c, d_volt, d_efield,
                                     pl->d_x, pl->d_m, pl->d_dirs, st, d_counts, tm ? &pl->ev[ei] : nullptr);
         if (s != AU_OK) return s;
@@ -1172,7 +1210,7 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
     if (b->n_events < 1 || !b->n_stations || !b->n_samples || !b->n_dirs || !b->h_dirs ||
         !b->volt_offset || !b->efield_offset)
         return fail(AU_EINVAL, "batch arrays missing");
-    if (b->flags & ~(AU_PLAN_GRAPH | AU_PLAN_PERSISTENT)) return fail(AU_EINVAL, "unknown plan flags");
+    if (b->flags & ~(AU_PLAN_GRAPH | AU_PLAN_PERSISTENT | AU_PLAN_XCD)) return fail(AU_EINVAL, "unknown plan flags");
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (dev != tb->device) return fail(AU_EINVAL, "table lives on another device");
@@ -1218,6 +1256,8 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
         std::vector<EvDesc> evs;
         std::vector<int2> su, cu;
         std::vector<int4> uu;
+        std::vector<int> xcd_off;
+        int xcd_max = 0;
     };
     std::vector<HostClass> hc;
     for (int n : ns) {
@@ -1234,8 +1274,34 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
                     c.uu.push_back(int4{ci, d, s0, std::min(descs[e].S, s0 + kStationsPerUnit)});
             }
         }
-        std::stable_sort(c.uu.begin(), c.uu.end(),
-                         [](const int4& a, const int4& bb) { return (a.w - a.z) > (bb.w - bb.z); });
+        if (b->flags & AU_PLAN_XCD) {
+            // all station chunks of one (event, direction) go to one of 8 lists,
+            // the list with the least work so far (work = stations)
+            std::vector<std::vector<int4>> lists(8);
+            std::vector<int64_t> load(8, 0);
+            for (size_t i = 0; i < c.uu.size();) {
+                size_t j = i;
+                int64_t work = 0;
+                while (j < c.uu.size() && c.uu[j].x == c.uu[i].x && c.uu[j].y == c.uu[i].y) {
+                    work += c.uu[j].w - c.uu[j].z;
+                    ++j;
+                }
+                const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                lists[x].insert(lists[x].end(), c.uu.begin() + i, c.uu.begin() + j);
+                load[x] += work;
+                i = j;
+            }
+            c.uu.clear();
+            c.xcd_off.assign(1, 0);
+            for (auto& l : lists) {
+                c.uu.insert(c.uu.end(), l.begin(), l.end());
+                c.xcd_off.push_back((int)c.uu.size());
+                c.xcd_max = std::max(c.xcd_max, (int)l.size());
+            }
+        } else {
+            std::stable_sort(c.uu.begin(), c.uu.end(),
+                             [](const int4& a, const int4& bb) { return (a.w - a.z) > (bb.w - bb.z); });
+        }
         if (c.uu.size() > 0x7fffffffu || c.cu.size() > 0x7fffffffu || c.su.size() > 0x7fffffffu)
             return fail(AU_EINVAL, "too many work units in one trace-length class");
         hc.push_back(std::move(c));
@@ -1251,13 +1317,13 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
     const size_t o_m = take((size_t)m_total * mb);
     const size_t o_dirs = take((size_t)dir_total * 2 * sizeof(double));
     struct Offs {
-        size_t evs, su, cu, uu, ctr;
+        size_t evs, su, cu, uu, ctr, xoff;
     };
     std::vector<Offs> co;
     for (auto& c : hc)
         co.push_back(Offs{take(c.evs.size() * sizeof(EvDesc)), take(c.su.size() * sizeof(int2)),
                           take(c.cu.size() * sizeof(int2)), take(c.uu.size() * sizeof(int4)),
-                          take(sizeof(unsigned int))});
+                          take(8 * sizeof(unsigned int)), take(9 * sizeof(int))});
     au_plan* pl = new au_plan();
     pl->tb = tb;
     pl->device = dev;
@@ -1298,6 +1364,11 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
         c.d_cunits = (int2*)(base + co[i].cu);
         c.d_uunits = (int4*)(base + co[i].uu);
         c.d_counter = (unsigned int*)(base + co[i].ctr);
+        if (!hc[i].xcd_off.empty()) {
+            c.d_xcd_off = (int*)(base + co[i].xoff);
+            c.xcd_max_list = hc[i].xcd_max;
+            PLAN_TRY(hipMemcpy(c.d_xcd_off, hc[i].xcd_off.data(), 9 * sizeof(int), hipMemcpyHostToDevice));
+        }
         PLAN_TRY(hipMemcpy(c.d_evs, hc[i].evs.data(), hc[i].evs.size() * sizeof(EvDesc), hipMemcpyHostToDevice));
         PLAN_TRY(hipMemcpy(c.d_sunits, hc[i].su.data(), hc[i].su.size() * sizeof(int2), hipMemcpyHostToDevice));
         PLAN_TRY(hipMemcpy(c.d_cunits, hc[i].cu.data(), hc[i].cu.size() * sizeof(int2), hipMemcpyHostToDevice));
@@ -1541,15 +1612,44 @@ extern "C" au_status au_autotune(const au_table* tb, const au_event* ev, int32_t
 // the calibration kernel for the memory-traffic counters.
 // ---------------------------------------------------------------------------
 
+// Each thread moves four 16-byte words per trip (all loads issued before the
+// stores) on a grid-stride loop; the tail (fewer than 4 words per thread) is
+// handled one word at a time.
 __global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
+    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = tid;
+    for (; i + 3 * nthr < n16; i += 4 * nthr) {
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = src[i + k * nthr];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            __builtin_nontemporal_store(v[k].x, &dst[i + k * nthr].x);
+            __builtin_nontemporal_store(v[k].y, &dst[i + k * nthr].y);
+            __builtin_nontemporal_store(v[k].z, &dst[i + k * nthr].z);
+            __builtin_nontemporal_store(v[k].w, &dst[i + k * nthr].w);
+        }
+    }
+    for (; i < n16; i += nthr) {
         const uint4 v = src[i];
         __builtin_nontemporal_store(v.x, &dst[i].x);
         __builtin_nontemporal_store(v.y, &dst[i].y);
         __builtin_nontemporal_store(v.z, &dst[i].z);
         __builtin_nontemporal_store(v.w, &dst[i].w);
+    }
+}
+
+// Write-only probe: the unfold kernel's HBM stream is almost all writes.
+__global__ __launch_bounds__(256) void k_fill16(uint4* __restrict__ dst, int64_t n16, uint32_t value)
+{
+    const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += nthr) {
+        __builtin_nontemporal_store(value, &dst[i].x);
+        __builtin_nontemporal_store(value, &dst[i].y);
+        __builtin_nontemporal_store(value, &dst[i].z);
+        __builtin_nontemporal_store(value, &dst[i].w);
     }
 }
 
@@ -1564,8 +1664,24 @@ extern "C" au_status au_hbm_copy(void* d_dst, const void* d_src, uint64_t bytes,
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t n16 = (int64_t)(bytes / 16);
     const int64_t want = (n16 + 255) / 256;
-    const int grid = (int)std::min<int64_t>(want, (int64_t)cus * 16);
+    const int grid = (int)std::min<int64_t>(want, (int64_t)cus * 32);
     hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const uint4*)d_src, (uint4*)d_dst, n16);
+    HIP_TRY(hipGetLastError());
+    return AU_OK;
+}
+
+extern "C" au_status au_hbm_fill(void* d_dst, uint64_t bytes, uint32_t value, void* stream)
+{
+    if (!d_dst) return fail(AU_EINVAL, "null pointer");
+    if (bytes % 16 != 0 || (uintptr_t)d_dst % 16 != 0)
+        return fail(AU_EINVAL, "fill size and address must be multiples of 16 bytes");
+    if (bytes == 0) return AU_OK;
+    int dev = 0, cus = 256;
+    HIP_TRY(hipGetDevice(&dev));
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t n16 = (int64_t)(bytes / 16);
+    const int grid = (int)std::min<int64_t>((n16 + 255) / 256, (int64_t)cus * 32);
+    hipLaunchKernelGGL(k_fill16, dim3(grid), dim3(256), 0, (hipStream_t)stream, (uint4*)d_dst, n16, value);
     HIP_TRY(hipGetLastError());
     return AU_OK;
 }

@@ -53,8 +53,10 @@ struct ClassLaunch {
     int n_cunits = 0;
     const int4* d_uunits = nullptr;  // (event, direction, station begin, end)
     int n_uunits = 0;
-    unsigned int* d_counter = nullptr;  // non-null: persistent unfold grid
+    unsigned int* d_counter = nullptr;  // non-null: persistent unfold grid (8 counters)
     int persistent_blocks = 0;
+    const int* d_xcd_off = nullptr;     // non-null: 8 per-XCD unit lists (9 boundaries)
+    int xcd_max_list = 0;               // longest of the 8 lists
 };
 
 // Enqueue spectrum, coefficient and unfold launches of one class on `st`.

@@ -173,7 +173,7 @@ def test_pattern_response_fp64_and_fp32_bound(api, coarse, coarse_c64):
         print("fp32 interp: worst err / bound = %.3f" % worst)
 
 
-@pytest.mark.parametrize("flags", [0, 1, 2, 3])
+@pytest.mark.parametrize("flags", [0, 1, 2, 3, 4, 6, 7])
 def test_batch_plan_uneven_events(api, coarse, flags):
     import torch
     t, tab = coarse
