@@ -307,8 +307,12 @@ au_status au_server_stats(au_server* server, au_server_counters* stats);
  * per transform, N/64 values per lane), rmax = largest radix per pass,
  * twmode = where the inverse FFT's twiddles live (0 table, 1 registers,
  * 2 registers times compile-time constants), wave = 1 if a single wavefront
- * owns each transform (no workgroup barriers).  Shapes other than the first
- * two exist only for N >= 1024, and only where they fit in registers.  The selection is process-wide per (precision,
+ * owns each transform (no workgroup barriers), pair = 1 if lanes L and L^32
+ * hold mirror bins k and N-k so each in-band bin is solved once and its
+ * mirror taken with a cross-lane swap, pp = 1 if each transform alternates
+ * between two LDS buffers (one workgroup barrier per exchange instead of
+ * two).  Shapes other than the first two exist only for N >= 1024, and only
+ * where they fit in registers and LDS.  The selection is process-wide per (precision,
  * N); plans read it when they are created.
  *
  * au_autotune runs the single-event path on a synthetic event of ev's sizes
@@ -319,7 +323,7 @@ au_status au_server_stats(au_server* server, au_server_counters* stats);
  * synchronous.
  */
 au_status au_unfold_variant_count(int32_t* count, int32_t* e_values, int32_t* rmax, int32_t* twmode,
-                                  int32_t* wave);
+                                  int32_t* wave, int32_t* pair, int32_t* pp);
 au_status au_set_unfold_variant(int32_t prec, int32_t n_samples, int32_t variant);
 au_status au_get_unfold_variant(int32_t prec, int32_t n_samples, int32_t* variant);
 au_status au_autotune(const au_table* table, const au_event* ev, int32_t n_dir, int32_t reps,

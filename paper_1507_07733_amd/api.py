@@ -118,7 +118,7 @@ _SIG = {
     "au_hbm_copy": (C.c_int32, [_VP, _VP, C.c_uint64, _VP]),
     "au_hbm_fill": (C.c_int32, [_VP, C.c_uint64, C.c_uint32, _VP]),
     "au_plan_stage_ms": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
-    "au_unfold_variant_count": (C.c_int32, [C.POINTER(C.c_int32)] * 5),
+    "au_unfold_variant_count": (C.c_int32, [C.POINTER(C.c_int32)] * 7),
     "au_set_unfold_variant": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
     "au_get_unfold_variant": (C.c_int32, [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
     "au_autotune": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.c_int32, C.POINTER(C.c_double),
@@ -315,20 +315,21 @@ def hbm_fill(dst, nbytes: int = None, value: int = 0, stream=None):
 
 def unfold_kernel_name(prec: int, n: int, variant: int) -> str:
     """Template name of the unfold kernel a (precision, N, variant) launches."""
-    e, rmax, tw, wave = unfold_variants()[variant]
+    e, rmax, tw, wave, pair, pp = unfold_variants()[variant]
     e = n // 64 if e == 0 else e
     e = min(e, n)
     rmax = min(rmax, e)
     t = "double" if prec == AU_PREC_FP64 else "float"
-    return "k_unfold<%s, %d, %d, %d, %d, %s>" % (t, n, e, rmax, tw, "true" if wave else "false")
+    b = lambda x: "true" if x else "false"
+    return "k_unfold<%s, %d, %d, %d, %d, %s, %s, %s>" % (t, n, e, rmax, tw, b(wave), b(pair), b(pp))
 
 
 def unfold_variants():
-    """[(E, rmax, twmode, wave)] of the unfold-kernel shapes the library is built in."""
+    """[(E, rmax, twmode, wave, pair, pp)] of the unfold-kernel shapes the library is built in."""
     n = C.c_int32()
-    e, r, t, w = ((C.c_int32 * 32)() for _ in range(4))
-    _check(lib().au_unfold_variant_count(C.byref(n), e, r, t, w))
-    return [(e[i], r[i], t[i], bool(w[i])) for i in range(n.value)]
+    e, r, t, w, p, q = ((C.c_int32 * 32)() for _ in range(6))
+    _check(lib().au_unfold_variant_count(C.byref(n), e, r, t, w, p, q))
+    return [(e[i], r[i], t[i], bool(w[i]), bool(p[i]), bool(q[i])) for i in range(n.value)]
 
 
 def set_unfold_variant(prec: int, n_samples: int, variant: int):

@@ -303,7 +303,25 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
 // With `counter` non-null the grid is persistent and blocks take units from
 // the atomic counter until the list is exhausted (every block leaves through
 // the same check); the per-thread twiddles are loaded once per block.
-template <typename T, int N, int E, int RMAX, int TWMODE, bool WAVE>
+// Lane -> FFT thread index.  With PAIR, every wavefront plays FFT threads t
+// (lanes 0-31) and TT - t (lanes 32-63, the partner of lane L is lane L ^ 32),
+// so the mirror bin N - k of any bin k a lane holds lives in the partner
+// lane (same register slot reflected), except for the self-mirrored threads
+// 0 and TT/2, which lanes 0 and 32 of the group's first wave play.
+template <int TT, bool PAIR>
+__device__ __forceinline__ int fft_thread(int r)
+{
+    if constexpr (!PAIR) {
+        return r;
+    } else {
+        const int wv = r >> 6, lane = r & 63;
+        if (lane < 32) return 32 * wv + lane;
+        const int u = 32 * wv + lane - 32;
+        return u == 0 ? TT / 2 : TT - u;
+    }
+}
+
+template <typename T, int N, int E, int RMAX, int TWMODE, bool WAVE, bool PAIR, bool PP>
 __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold(EvDesc ev0, const EvDesc* __restrict__ evs,
                                                    const int4* __restrict__ units, int n_units,
                                                    int spw, const XBin<T>* __restrict__ X,
@@ -314,12 +332,16 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold(
                                                    const int* __restrict__ xcd_off)
 {
     constexpr int TT = N / E;
-    constexpr int G = groups_per_block<T, N, E>();
+    constexpr int G = groups_per_block<T, N, E, PP ? 2 : 1>();
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sh_u;
     __shared__ int sh_list;
-    const int g = threadIdx.x / TT, t = threadIdx.x % TT;
-    C2<T>* lds = reinterpret_cast<C2<T>*>(smem) + g * lds_elems<N>();
+    static_assert(!PAIR || ((N / E) % 64 == 0 && E % 2 == 0), "paired lanes need whole wavefronts");
+    const int g = threadIdx.x / TT, t = fft_thread<TT, PAIR>(threadIdx.x % TT);
+    // PP: two buffers per group; the staging exchange uses lds, the passes
+    // alternate lds2, lds, ...
+    C2<T>* lds = reinterpret_cast<C2<T>*>(smem) + g * (PP ? 2 : 1) * lds_elems<N>();
+    C2<T>* lds2 = lds + lds_elems<N>();
     C2<T> w[tw_count<N, E, RMAX, TWMODE>()];
     load_twiddles<T, N, E, RMAX, TWMODE, +1>(w, tw, t);
     // XCD-aware placement (xcd_off != nullptr): the unit array holds 8 lists,
@@ -383,33 +405,89 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold(
         for (int base = s0; base < s1; base += G) {
             const int s = base + g;
             const bool active = s < s1;
-            if (active) {
-                const XBin<T>* __restrict__ Xs = X + ev.x_off + (int64_t)s * ev.nb;
-                for (unsigned j = t; j < nb; j += TT) {
-                    const MBin<T> m = Md[j];
-                    const XBin<T> xb = Xs[j];
-                    C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
-                    C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
-                    const unsigned k = k_lo + j;
-                    if (k == 0) {
-                        lds[0] = C2<T>{et.re, ep.re};
-                    } else {
-                        lds[lpad(k)] = C2<T>{et.re - ep.im, et.im + ep.re};
-                        lds[lpad(N - k)] = C2<T>{et.re + ep.im, ep.re - et.im};
+            const XBin<T>* __restrict__ Xs = X + ev.x_off + (int64_t)s * ev.nb;
+            C2<T> x[E];
+            if constexpr (PAIR) {
+                // registers i < E/2 hold bins k = t + TT i < N/2: solve them here;
+                // registers i >= E/2 hold the mirrors of the partner's (or, for
+                // t = 0 and TT/2, the lane's own) lower registers.
+                C2<T> eth[E / 2], eph[E / 2];
+#pragma unroll
+                for (int i = 0; i < E / 2; ++i) {
+                    const unsigned k = t + TT * i;
+                    const unsigned j = k - k_lo;
+                    C2<T> et{0, 0}, ep{0, 0};
+                    if (active && j < nb) {
+                        const MBin<T> m = Md[j];
+                        const XBin<T> xb = Xs[j];
+                        et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
+                        ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
+                        if (k == 0) {
+                            et.im = 0;
+                            ep.im = 0;
+                        }
+                    }
+                    eth[i] = et;
+                    eph[i] = ep;
+                    x[i] = C2<T>{et.re - ep.im, et.im + ep.re};
+                }
+                const bool self0 = (t == 0), selfh = (t == TT / 2);
+#pragma unroll
+                for (int i = E / 2; i < E; ++i) {
+                    const int jp = E - 1 - i;
+                    C2<T> et{__shfl_xor(eth[jp].re, 32), __shfl_xor(eth[jp].im, 32)};
+                    C2<T> ep{__shfl_xor(eph[jp].re, 32), __shfl_xor(eph[jp].im, 32)};
+                    if (selfh) {
+                        et = eth[jp];
+                        ep = eph[jp];
+                    }
+                    if (self0) {
+                        et = (i > E / 2) ? eth[E - i] : C2<T>{0, 0};
+                        ep = (i > E / 2) ? eph[E - i] : C2<T>{0, 0};
+                    }
+                    // Z[N - b] = conj E_th[b] + i conj E_ph[b]
+                    x[i] = C2<T>{et.re + ep.im, ep.re - et.im};
+                }
+            } else {
+                if (active) {
+                    for (unsigned j = t; j < nb; j += TT) {
+                        const MBin<T> m = Md[j];
+                        const XBin<T> xb = Xs[j];
+                        C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
+                        C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
+                        const unsigned k = k_lo + j;
+                        if (k == 0) {
+                            lds[0] = C2<T>{et.re, ep.re};
+                        } else {
+                            lds[lpad(k)] = C2<T>{et.re - ep.im, et.im + ep.re};
+                            lds[lpad(N - k)] = C2<T>{et.re + ep.im, ep.re - et.im};
+                        }
                     }
                 }
-            }
-            lds_sync<WAVE>();
-            C2<T> x[E];
+                lds_sync<WAVE>();
 #pragma unroll
-            for (int i = 0; i < E; ++i) {
-                const unsigned k = t + TT * i;
-                const unsigned kk = (k <= N / 2) ? k : N - k;
-                const bool inb = active && (kk - k_lo) < nb;
-                x[i] = inb ? lds[lpad(k)] : C2<T>{0, 0};
+                for (int i = 0; i < E; ++i) {
+                    const unsigned k = t + TT * i;
+                    const unsigned kk = (k <= N / 2) ? k : N - k;
+                    const bool inb = active && (kk - k_lo) < nb;
+                    x[i] = inb ? lds[lpad(k)] : C2<T>{0, 0};
+                }
+                if constexpr (!PP) lds_sync<WAVE>();
             }
-            lds_sync<WAVE>();
-            fft<T, N, E, +1, TWMODE, RMAX, WAVE>(x, lds, tw, t, w);
+            if constexpr (PP) {
+                fft_pp<T, N, E, +1, TWMODE, RMAX, WAVE>(x, lds2, lds, tw, t, w);
+                // exchanges this station: the staging one (lds, unless PAIR)
+                // plus one per pass boundary, alternating from lds2; make the
+                // next station's first write go to the buffer not gathered last
+                constexpr int ex = num_passes<N, (RMAX < E ? RMAX : E)>() - 1;
+                if constexpr ((ex % 2 == 1) == PAIR) {
+                    C2<T>* tmp = lds;
+                    lds = lds2;
+                    lds2 = tmp;
+                }
+            } else {
+                fft<T, N, E, +1, TWMODE, RMAX, WAVE>(x, lds, tw, t, w);
+            }
             if (active) {
                 T* out = efield + ev.efield_off + ((int64_t)d * ev.S + s) * 2 * N;
 #pragma unroll
@@ -457,12 +535,21 @@ struct UnfoldVariant {
     int rmax;
     int twmode;
     bool wave;
+    bool pair;  // mirror-paired lanes: bins solved once, mirrors by a cross-lane swap
+    bool pp;    // two LDS buffers per transform: one barrier per exchange
 };
 constexpr UnfoldVariant kUnfoldVariants[] = {
-    {16, 16, TW_REG, false}, {16, 16, TW_TABLE, false}, {8, 8, TW_REG, false},    {8, 8, TW_TABLE, false},
-    {32, 32, TW_REG, false}, {32, 32, TW_TABLE, false}, {0, 16, TW_SPLIT, true}, {0, 8, TW_SPLIT, true},
+    {16, 16, TW_REG, false, false, false}, {16, 16, TW_TABLE, false, false, false},
+    {8, 8, TW_REG, false, false, false},   {8, 8, TW_TABLE, false, false, false},
+    {32, 32, TW_REG, false, false, false}, {32, 32, TW_TABLE, false, false, false},
+    {0, 16, TW_SPLIT, true, false, false}, {0, 8, TW_SPLIT, true, false, false},
+    {8, 8, TW_REG, false, true, false},    {16, 16, TW_REG, false, true, false},
+    {8, 8, TW_REG, false, false, true},    {16, 16, TW_REG, false, false, true},
 };
-constexpr int kNumVariants = 8;
+constexpr int kNumVariants = 12;
+
+// LDS one workgroup may allocate.
+constexpr int kMaxLdsPerBlock = 65536;
 
 constexpr int variant_e(int n, int v) { return kUnfoldVariants[v].E == 0 ? n / 64 : kUnfoldVariants[v].E; }
 
@@ -478,6 +565,8 @@ constexpr bool variant_built(int n, int v, int tsize)
     if (e < 8 || e > (tsize == 8 ? 16 : 32)) return false;
     if (kUnfoldVariants[v].wave && e > 16) return false;
     if (kUnfoldVariants[v].rmax > e) return false;
+    if (kUnfoldVariants[v].pair && ((n / e) % 64 != 0 || e % 2 != 0)) return false;
+    if (kUnfoldVariants[v].pp && 2 * (n + n / 16) * 2 * tsize > kMaxLdsPerBlock) return false;
     return true;
 }
 
@@ -488,10 +577,13 @@ struct UShape {
     static constexpr int RMAX = kUnfoldVariants[V].rmax < E ? kUnfoldVariants[V].rmax : E;
     static constexpr int TWMODE = kUnfoldVariants[V].twmode;
     static constexpr bool WAVE = kUnfoldVariants[V].wave;
+    static constexpr bool PAIR = kUnfoldVariants[V].pair;
+    static constexpr bool PP = kUnfoldVariants[V].pp;
+    static constexpr int BUFS = PP ? 2 : 1;
     static constexpr int TT = N / E;
-    static constexpr int G = groups_per_block<T, N, E>();
+    static constexpr int G = groups_per_block<T, N, E, BUFS>();
     static constexpr int BLOCK = G * TT;
-    static constexpr size_t LDS = (size_t)G * lds_elems<N>() * sizeof(C2<T>);
+    static constexpr size_t LDS = (size_t)G * BUFS * lds_elems<N>() * sizeof(C2<T>);
 };
 
 static int ilog2(int n)
@@ -545,7 +637,7 @@ static hipError_t launch_unfold_nv(hipStream_t st, const EvDesc& ev0, const EvDe
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counter, 8);
             grid = std::min(n_units, persistent_blocks);
         }
-        hipLaunchKernelGGL((k_unfold<T, N, S::E, S::RMAX, S::TWMODE, S::WAVE>), dim3(grid), dim3(S::BLOCK), S::LDS, st,
+        hipLaunchKernelGGL((k_unfold<T, N, S::E, S::RMAX, S::TWMODE, S::WAVE, S::PAIR, S::PP>), dim3(grid), dim3(S::BLOCK), S::LDS, st,
                            ev0, evs, units, n_units, spw, X, M, efield, tw, counter, xcd_off);
         return hipGetLastError();
     }
@@ -561,7 +653,7 @@ static hipError_t launch_unfold_n(int v, hipStream_t st, const EvDesc& ev0, cons
     switch (v) {
 #define V_(VV) \
     case VV: return launch_unfold_nv<T, N, VV>(st, ev0, evs, units, n_units, spw, X, M, efield, tw, counter, persistent_blocks, xcd_off, xcd_max_list);
-        V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7)
+        V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11)
 #undef V_
     }
     return hipErrorInvalidValue;
@@ -575,7 +667,7 @@ static int occupancy_nv()
     } else {
         using S = UShape<T, N, V>;
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_unfold<T, N, S::E, S::RMAX, S::TWMODE, S::WAVE>, S::BLOCK,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_unfold<T, N, S::E, S::RMAX, S::TWMODE, S::WAVE, S::PAIR, S::PP>, S::BLOCK,
                                                          S::LDS) != hipSuccess)
             return 0;
         return occ;
@@ -631,6 +723,10 @@ static int persistent_blocks_for(int n, int v, int device)
             case 5: per_cu = occupancy_nv<T, NN, 5>(); break;                                   \
             case 6: per_cu = occupancy_nv<T, NN, 6>(); break;                                   \
             case 7: per_cu = occupancy_nv<T, NN, 7>(); break;                                   \
+            case 8: per_cu = occupancy_nv<T, NN, 8>(); break;                                   \
+            case 9: per_cu = occupancy_nv<T, NN, 9>(); break;                                   \
+            case 10: per_cu = occupancy_nv<T, NN, 10>(); break;                                 \
+            case 11: per_cu = occupancy_nv<T, NN, 11>(); break;                                 \
         }                                                                                       \
         break;
         AU_FOR_EACH_N(X_)
@@ -1477,7 +1573,7 @@ static au_status check_variant_args(int32_t prec, int32_t n)
 }
 
 extern "C" au_status au_unfold_variant_count(int32_t* count, int32_t* e_values, int32_t* rmax,
-                                             int32_t* twmode, int32_t* wave)
+                                             int32_t* twmode, int32_t* wave, int32_t* pair, int32_t* pp)
 {
     if (!count) return fail(AU_EINVAL, "null argument");
     *count = kNumVariants;
@@ -1486,6 +1582,8 @@ extern "C" au_status au_unfold_variant_count(int32_t* count, int32_t* e_values, 
         if (rmax) rmax[v] = kUnfoldVariants[v].rmax;
         if (twmode) twmode[v] = kUnfoldVariants[v].twmode;
         if (wave) wave[v] = kUnfoldVariants[v].wave ? 1 : 0;
+        if (pair) pair[v] = kUnfoldVariants[v].pair ? 1 : 0;
+        if (pp) pp[v] = kUnfoldVariants[v].pp ? 1 : 0;
     }
     return AU_OK;
 }

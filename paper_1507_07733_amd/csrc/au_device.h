@@ -370,6 +370,89 @@ __device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
     }
 }
 
+// Number of passes of an N-point transform with radix at most RMAX.
+template <int N, int RMAX>
+constexpr int num_passes()
+{
+    int p = 0;
+    for (int ns = 1; ns < N; ns *= pass_radix<N, RMAX>(ns)) ++p;
+    return p;
+}
+
+// Ping-pong form of fft_pass: pass p scatters into `la`, one barrier, gathers
+// from `la`, and pass p+1 scatters into `lb`.  A buffer is written again only
+// two exchanges after it was last read, and every thread has passed the
+// barrier in between, so one barrier per exchange suffices (against two with
+// a single buffer).
+template <typename T, int N, int E, int RMAX, int TWMODE, bool WAVE, int NS, int SIGN>
+__device__ __forceinline__ void fft_pass_pp(C2<T> (&x)[E], C2<T>* __restrict__ la, C2<T>* __restrict__ lb,
+                                            const C2<T>* __restrict__ tw, const C2<T>* __restrict__ w, int t)
+{
+    constexpr int R = pass_radix<N, RMAX>(NS);
+    constexpr int TT = N / E;
+    constexpr int B = E / R;
+    constexpr bool LAST = (NS * R == N);
+    static_assert(R >= 2 && E % R == 0, "radix");
+#pragma unroll
+    for (int m = 0; m < B; ++m) {
+        const int j = t + TT * m;
+        const int k = j & (NS - 1);
+        C2<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = x[m + r * B];
+        if constexpr (NS > 1) {
+            constexpr int STRIDE = kTwN / (NS * R);
+            constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                C2<T> wr;
+                if constexpr (TWMODE == TW_TABLE) {
+                    wr = twiddle_tab<SIGN>(tw, r * k * STRIDE);
+                } else if constexpr (TWMODE == TW_REG) {
+                    wr = w[OFF + m * (R - 1) + r - 1];
+                } else {
+                    wr = w[OFF + r - 1];
+                    if constexpr (NS > TT) {
+                        const int p = (r * ((TT * m) % NS)) % (NS * R);
+                        if (p != 0) {
+                            constexpr int Q = NS * R;
+                            const CxRoot cr = cx_root(SIGN > 0 ? p : Q - p, Q);
+                            wr = cmul(wr, C2<T>{(T)cr.c, (T)cr.s});
+                        }
+                    }
+                }
+                v[r] = cmul(v[r], wr);
+            }
+        }
+        Dft<R, SIGN, T>::run(v);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[m + r * B] = v[r];
+        } else {
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) la[lpad(base + r * NS)] = v[r];
+        }
+    }
+    if constexpr (!LAST) {
+        lds_sync<WAVE>();
+#pragma unroll
+        for (int i = 0; i < E; ++i) x[i] = la[lpad(t + TT * i)];
+        fft_pass_pp<T, N, E, RMAX, TWMODE, WAVE, NS * R, SIGN>(x, lb, la, tw, w, t);
+    }
+}
+
+// Full transform with ping-pong buffers; the first exchange writes `la`.
+// The caller must not write `la` or `lb` again until every thread of the
+// group has passed a barrier that follows its last gather.
+template <typename T, int N, int E, int SIGN, int TWMODE, int RMAX, bool WAVE>
+__device__ __forceinline__ void fft_pp(C2<T> (&x)[E], C2<T>* __restrict__ la, C2<T>* __restrict__ lb,
+                                       const C2<T>* __restrict__ tw, int t, const C2<T>* __restrict__ w)
+{
+    static_assert((N & (N - 1)) == 0 && N >= E && (E & (E - 1)) == 0 && RMAX <= 32, "sizes");
+    fft_pass_pp<T, N, E, (RMAX < E ? RMAX : E), TWMODE, WAVE, 1, SIGN>(x, la, lb, tw, w, t);
+}
+
 // Full N-point transform of the group's sequence, exp(SIGN ...) kernel, no
 // scaling.  Every thread of the group must call it; unless WAVE it contains
 // workgroup barriers, so every thread of the workgroup must call it.

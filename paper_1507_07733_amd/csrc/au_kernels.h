@@ -52,12 +52,12 @@ constexpr int kBlock = 256;
 
 // FFT groups per workgroup for an N-point transform with E values per thread:
 // fill kBlock threads, but keep LDS at or under 64 KiB.
-template <typename T, int N, int E>
+template <typename T, int N, int E, int BUFS = 1>
 constexpr int groups_per_block()
 {
     constexpr int tt = N / E;
     int g = tt >= kBlock ? 1 : kBlock / tt;
-    const int cap = 65536 / (lds_elems<N>() * (int)sizeof(C2<T>));
+    const int cap = 65536 / (BUFS * lds_elems<N>() * (int)sizeof(C2<T>));
     if (g > cap) g = cap;
     return g < 1 ? 1 : g;
 }

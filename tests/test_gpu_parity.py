@@ -266,13 +266,13 @@ def test_every_unfold_variant(api, coarse, n, prec):
     keep = api.get_unfold_variant(p, n)
     built = 0
     try:
-        for vi, (e, rmax, twmode, wave) in enumerate(api.unfold_variants()):
+        for vi, (e, rmax, twmode, wave, pair, pp) in enumerate(api.unfold_variants()):
             try:
                 api.set_unfold_variant(p, n, vi)
             except api.AuError:
                 continue                      # not built for this size / precision
             built += 1
-            say("variant", vi, "E", e, "rmax", rmax, "twmode", twmode, "wave", wave, prec, "N", n)
+            say("variant", vi, "E", e, "rmax", rmax, "twmode", twmode, "wave", wave, "pair", pair, "pp", pp, prec, "N", n)
             out = api.unfold_direction_scan(tab, ev, to_dev(v), dirs).cpu().numpy()
             assert_traces_close(out, ref, TOL_FP64 if prec == "fp64" else TOL_FP32, "variant %d" % vi)
     finally:
