@@ -164,6 +164,22 @@ au_status au_unfold_direction_scan(const au_table* table, const au_event* ev, co
                                    uint64_t* d_counts);
 
 /*
+ * Direction scan reduced to station timing: the E-field trace's Hilbert
+ * envelope env = sqrt(e^2 + H(e)^2) (section 4) and its maximum, whose
+ * sample is the updated station time (section 2, Fig. 1).  For every
+ * direction, station and component (theta, phi):
+ *   d_peak [n_dir][S][2] (float or double per ev->prec): max_n env[n];
+ *   d_arg  [n_dir][S][2] int32: the smallest n attaining it.
+ * d_efield ([n_dir][S][2][N], nullable) also receives the traces.  The
+ * Hilbert transform uses -i sgn(k) (sgn 0 at DC and Nyquist); the opposite
+ * sign gives the same envelope.  Workspace as au_unfold_direction_scan.
+ */
+au_status au_unfold_envelope_scan(const au_table* table, const au_event* ev, const void* d_volt,
+                                  int32_t n_dir, const double* h_dirs, void* d_efield, void* d_peak,
+                                  int32_t* d_arg, void* d_work, uint64_t work_bytes, void* stream,
+                                  uint64_t* d_counts);
+
+/*
  * Interpolated pattern H[c][p](f_k; zen, az) at every in-band bin of ev, for
  * n_dir directions (section 3: linear interpolation between nodes).  Output
  * d_resp [n_dir][n_band][2][2] complex (interleaved re, im) of the precision's

@@ -30,6 +30,12 @@
  *   Both are a textbook iterative radix-2 Cooley-Tukey FFT; every twiddle
  *   is cos/sin of its own angle from libm, never a recurrence.
  *
+ * Envelope (section 4: the envelope of a trace x is the magnitude of
+ * x + i H(x), H the Hilbert transform; section 2: its maximum is the updated
+ * timing of the station): H(x) = IDFT(-i sgn(k) DFT(x)), sgn(k) = +1 for
+ * 0 < k < N/2, -1 for N/2 < k < N, 0 at k = 0 and N/2.  The paper's phase
+ * convention is the opposite sign, which leaves the envelope unchanged.
+ *
  * Every pin of this file lives in tests/test_oracle_*.py (brute-force DFT,
  * Parseval, pure tones, exact node interpolation, multilinear
  * reproduction, azimuth wrap, exact rational 2x2 solve, band-pass and
@@ -338,5 +344,61 @@ int orc_unfold_units(const orc_grid* g, const double* tab,
     }
     if (max_imag) *max_imag = worst;
     free(buf);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Hilbert envelope and its peak.                                          */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * env[j] = sqrt(x[j]^2 + H(x)[j]^2) for a real trace x of length n (a power
+ * of two).  Returns 0, -1 on a bad size, -3 on allocation failure.
+ */
+int orc_envelope(int64_t n, const double* x, double* env)
+{
+    if (!is_pow2(n) || n < 2) return -1;
+    double* re = (double*)malloc(sizeof(double) * (size_t)n * 2);
+    if (!re) return -3;
+    double* im = re + n;
+    for (int64_t j = 0; j < n; ++j) { re[j] = x[j]; im[j] = 0.0; }
+    orc_fft(n, re, im, -1);
+    for (int64_t k = 0; k < n; ++k) {
+        double sg = 0.0;
+        if (k > 0 && 2 * k < n) sg = 1.0;
+        if (2 * k > n) sg = -1.0;
+        /* -i sgn(k) (a + ib) = sgn(k) (b - ia) */
+        const double a = re[k], b = im[k];
+        re[k] = sg * b;
+        im[k] = -sg * a;
+    }
+    orc_fft(n, re, im, +1);
+    for (int64_t j = 0; j < n; ++j) {
+        const double h = re[j] / (double)n;
+        env[j] = sqrt(x[j] * x[j] + h * h);
+    }
+    free(re);
+    return 0;
+}
+
+/*
+ * Peak of the envelope of each of `n_tr` traces of length n stored back to
+ * back: peak[t] = max_j env_t[j], arg[t] = the smallest j attaining it.
+ */
+int orc_envelope_peaks(int64_t n_tr, int64_t n, const double* traces, double* peak, int64_t* arg)
+{
+    double* env = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!env) return -3;
+    for (int64_t t = 0; t < n_tr; ++t) {
+        int rc = orc_envelope(n, traces + (size_t)t * (size_t)n, env);
+        if (rc) { free(env); return rc; }
+        double best = -1.0;
+        int64_t bj = 0;
+        for (int64_t j = 0; j < n; ++j)
+            if (env[j] > best) { best = env[j]; bj = j; }
+        peak[t] = best;
+        arg[t] = bj;
+    }
+    free(env);
     return 0;
 }

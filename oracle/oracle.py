@@ -62,6 +62,10 @@ def lib():
                                            C.c_int64, C.c_int64, C.c_double, dp, C.c_int64, dp,
                                            C.c_int64, ip, dp, ip, dp]
             L.orc_unfold_units.restype = C.c_int
+            L.orc_envelope.argtypes = [C.c_int64, dp, dp]
+            L.orc_envelope.restype = C.c_int
+            L.orc_envelope_peaks.argtypes = [C.c_int64, C.c_int64, dp, dp, ip]
+            L.orc_envelope_peaks.restype = C.c_int
             _lib = L
     return _lib
 
@@ -152,3 +156,24 @@ def unfold(grid, table, volt, dirs, fs_hz: int, lo_hz: int, hi_hz: int,
         e = e.reshape(len(d), n_st, 2, n)
         sing = sing.reshape(len(d), n_st)
     return e, sing, float(mi[0])
+
+
+def envelope(x) -> np.ndarray:
+    """Hilbert envelope sqrt(x^2 + H(x)^2) of a real trace (length a power of two)."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    env = np.empty_like(x)
+    if lib().orc_envelope(len(x), _dp(x), _dp(env)) != 0:
+        raise ValueError("length must be a power of two >= 2")
+    return env
+
+
+def envelope_peaks(traces):
+    """(peak value, first index of the peak) of the envelope of every trace along the last axis."""
+    t = np.ascontiguousarray(np.asarray(traces, dtype=np.float64))
+    n = t.shape[-1]
+    flat = t.reshape(-1, n)
+    peak = np.empty(len(flat))
+    arg = np.empty(len(flat), dtype=np.int64)
+    if lib().orc_envelope_peaks(len(flat), n, _dp(flat), _dp(peak), _ip(arg)) != 0:
+        raise ValueError("bad trace length")
+    return peak.reshape(t.shape[:-1]), arg.reshape(t.shape[:-1])

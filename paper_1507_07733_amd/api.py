@@ -107,6 +107,8 @@ _SIG = {
                                     C.c_uint64, _VP, _VP]),
     "au_unfold_direction_scan": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.c_int32, C.POINTER(C.c_double),
                                              _VP, _VP, C.c_uint64, _VP, _VP]),
+    "au_unfold_envelope_scan": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.c_int32, C.POINTER(C.c_double),
+                                            _VP, _VP, _VP, _VP, C.c_uint64, _VP, _VP]),
     "au_pattern_response": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.POINTER(C.c_double), _VP, _VP]),
     "au_plan_create": (C.c_int32, [_VP, C.POINTER(AuBatch), C.POINTER(_VP)]),
     "au_plan_units": (C.c_int32, [_VP, C.POINTER(C.c_uint64)]),
@@ -286,6 +288,31 @@ def unfold_direction_scan(table: Table, ev: AuEvent, volt, dirs, out=None, work=
                                           d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(out), wp, wb,
                                           _stream_handle(stream), _ptr(counts)))
     return out
+
+
+def unfold_envelope_scan(table: Table, ev: AuEvent, volt, dirs, efield=False, work=None, counts=None,
+                         stream=None):
+    """Envelope peaks for every (direction, station, component).
+
+    Returns (peak [D][S][2], arg [D][S][2] int32, E or None) where E
+    [D][S][2][N] is also produced when ``efield`` is True (or a tensor).
+    """
+    import torch
+    _check_traces(volt, ev)
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 2))
+    dt = out_dtype(ev.prec)
+    peak = torch.empty((len(d), ev.n_stations, 2), dtype=dt, device=volt.device)
+    arg = torch.empty((len(d), ev.n_stations, 2), dtype=torch.int32, device=volt.device)
+    out = None
+    if efield is True:
+        out = torch.empty((len(d), ev.n_stations, 2, ev.n_samples), dtype=dt, device=volt.device)
+    elif efield is not False and efield is not None:
+        out = efield
+    wp, wb = _work(work)
+    _check(lib().au_unfold_envelope_scan(table.handle, C.byref(ev), _ptr(volt), len(d),
+                                         d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(out), _ptr(peak),
+                                         _ptr(arg), wp, wb, _stream_handle(stream), _ptr(counts)))
+    return peak, arg, out
 
 
 def pattern_response(table: Table, ev: AuEvent, dirs, device=None, stream=None):

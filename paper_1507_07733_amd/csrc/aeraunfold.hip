@@ -500,6 +500,121 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold(
     }
 }
 
+// Envelope peaks (the timing step after the unfolding: the station time is
+// the maximum of the Hilbert envelope of its E-field trace).  Per (direction,
+// station) the in-band solution (E_th, E_ph) is packed twice:
+//   Z[k]   = E_th + i E_ph,            Z[N-k]   = conj E_th + i conj E_ph
+//   Zh[k]  = -i E_th + E_ph,           Zh[N-k]  = i conj E_th - conj E_ph
+// (Zh is the packed spectrum of the Hilbert transforms H(e_th) + i H(e_ph),
+// with H = IDFT(-i sgn(k) DFT)), both are inverse-transformed, and
+// env = sqrt(e^2 + H(e)^2) is reduced to its maximum and the first sample
+// attaining it, per component.  Optionally the traces are stored too.
+template <typename T, int N, int E>
+__global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_env(
+    EvDesc ev0, int spw, const XBin<T>* __restrict__ X, const MBin<T>* __restrict__ M, T* __restrict__ efield,
+    T* __restrict__ peak, int* __restrict__ arg, const C2<T>* __restrict__ tw)
+{
+    constexpr int TT = N / E;
+    constexpr int G = groups_per_block<T, N, E>();
+    constexpr int NW = (TT + 63) / 64;  // waves per group
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ T red_v[G][NW][2];
+    __shared__ int red_i[G][NW][2];
+    const int g = threadIdx.x / TT, t = threadIdx.x % TT;
+    C2<T>* la = reinterpret_cast<C2<T>*>(smem) + g * lds_elems<N>();
+    const int chunks = (ev0.S + spw - 1) / spw;
+    const int d = blockIdx.x / chunks;
+    const int s0 = (blockIdx.x - d * chunks) * spw, s1 = min(ev0.S, s0 + spw);
+    const unsigned nb = (unsigned)ev0.nb, k_lo = (unsigned)ev0.k_lo;
+    const MBin<T>* __restrict__ Md = M + ev0.m_off + (int64_t)d * ev0.nb;
+    for (int base = s0; base < s1; base += G) {
+        const int s = base + g;
+        const bool active = s < s1;
+        const XBin<T>* __restrict__ Xs = X + ev0.x_off + (int64_t)s * ev0.nb;
+        C2<T> x[E], xh[E];
+        // the two packed spectra go through the same LDS buffer one after the other
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (active) {
+                for (unsigned j = t; j < nb; j += TT) {
+                    const MBin<T> m = Md[j];
+                    const XBin<T> xb = Xs[j];
+                    C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
+                    C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
+                    const unsigned k = k_lo + j;
+                    if (k == 0) {
+                        la[0] = h == 0 ? C2<T>{et.re, ep.re} : C2<T>{0, 0};
+                    } else if (h == 0) {
+                        la[lpad(k)] = C2<T>{et.re - ep.im, et.im + ep.re};
+                        la[lpad(N - k)] = C2<T>{et.re + ep.im, ep.re - et.im};
+                    } else {
+                        la[lpad(k)] = C2<T>{et.im + ep.re, ep.im - et.re};
+                        la[lpad(N - k)] = C2<T>{et.im - ep.re, et.re + ep.im};
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const unsigned k = t + TT * i;
+                const unsigned kk = (k <= N / 2) ? k : N - k;
+                const bool inb = active && (kk - k_lo) < nb;
+                const C2<T> v = inb ? la[lpad(k)] : C2<T>{0, 0};
+                if (h == 0) x[i] = v; else xh[i] = v;
+            }
+            __syncthreads();
+        }
+        fft<T, N, E, +1>(x, la, tw, t);
+        fft<T, N, E, +1>(xh, la, tw, t);
+        // per-thread maxima over its samples n = t + TT i (increasing in i)
+        T bv[2] = {(T)-1, (T)-1};
+        int bi[2] = {0, 0};
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const T e0 = sqrt(x[i].re * x[i].re + xh[i].re * xh[i].re);
+            const T e1 = sqrt(x[i].im * x[i].im + xh[i].im * xh[i].im);
+            if (e0 > bv[0]) { bv[0] = e0; bi[0] = t + TT * i; }
+            if (e1 > bv[1]) { bv[1] = e1; bi[1] = t + TT * i; }
+        }
+        // larger value wins; equal values: smaller sample index
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            for (int off = 32; off >= 1; off >>= 1) {
+                const T ov = __shfl_xor(bv[c], off);
+                const int oi = __shfl_xor(bi[c], off);
+                if (ov > bv[c] || (ov == bv[c] && oi < bi[c])) { bv[c] = ov; bi[c] = oi; }
+            }
+        }
+        const int lane = threadIdx.x & 63, wv = t >> 6;
+        if (lane == 0) {
+            red_v[g][wv][0] = bv[0]; red_i[g][wv][0] = bi[0];
+            red_v[g][wv][1] = bv[1]; red_i[g][wv][1] = bi[1];
+        }
+        __syncthreads();
+        if (active && t < 2) {
+            T v = red_v[g][0][t];
+            int ix = red_i[g][0][t];
+            for (int w2 = 1; w2 < NW; ++w2) {
+                const T ov = red_v[g][w2][t];
+                const int oi = red_i[g][w2][t];
+                if (ov > v || (ov == v && oi < ix)) { v = ov; ix = oi; }
+            }
+            const int64_t o = ((int64_t)d * ev0.S + s) * 2 + t;
+            peak[o] = v;
+            arg[o] = ix;
+        }
+        if (active && efield != nullptr) {
+            T* out = efield + ((int64_t)d * ev0.S + s) * 2 * N;
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                __builtin_nontemporal_store(x[i].re, out + t + TT * i);
+                __builtin_nontemporal_store(x[i].im, out + N + t + TT * i);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_zero_u32(unsigned int* p, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1782,4 +1897,106 @@ extern "C" au_status au_hbm_fill(void* d_dst, uint64_t bytes, uint32_t value, vo
     hipLaunchKernelGGL(k_fill16, dim3(grid), dim3(256), 0, (hipStream_t)stream, (uint4*)d_dst, n16, value);
     HIP_TRY(hipGetLastError());
     return AU_OK;
+}
+
+// ---------------------------------------------------------------------------
+// envelope peaks of a direction scan
+// ---------------------------------------------------------------------------
+
+template <typename T, int N>
+static hipError_t launch_env_n(hipStream_t st, const EvDesc& ev0, int n_units, const XBin<T>* X, const MBin<T>* M,
+                               T* efield, T* peak, int* arg, const C2<T>* tw)
+{
+    constexpr int E = N >= 1024 ? 8 : (N < 16 ? N : 16);
+    constexpr int TT = N / E;
+    constexpr int G = groups_per_block<T, N, E>();
+    constexpr size_t LDS = (size_t)G * lds_elems<N>() * sizeof(C2<T>);
+    hipLaunchKernelGGL((k_unfold_env<T, N, E>), dim3(n_units), dim3(G * TT), LDS, st, ev0, kStationsPerUnit, X, M,
+                       efield, peak, arg, tw);
+    return hipGetLastError();
+}
+
+template <typename T>
+static au_status run_envelope(const au_table* tb, const au_event* ev, const EvParams& p, const void* d_volt,
+                              int n_dir, const double* h_dirs, void* d_efield, void* d_peak, int32_t* d_arg,
+                              void* d_work, hipStream_t st, uint64_t* d_counts)
+{
+    const WsLayout w = ws_layout(p, ev->prec, n_dir);
+    unsigned char* base = (unsigned char*)d_work;
+    XBin<T>* X = (XBin<T>*)base;
+    MBin<T>* M = (MBin<T>*)(base + w.x);
+    double* dirs = (double*)(base + w.x + w.m);
+    HIP_TRY(hipMemcpyAsync(dirs, h_dirs, sizeof(double) * 2 * n_dir, hipMemcpyHostToDevice, st));
+    EvDesc ev0{};
+    ev0.S = p.S;
+    ev0.N = p.N;
+    ev0.D = n_dir;
+    ev0.k_lo = p.k_lo;
+    ev0.nb = p.nb;
+    const C2<T>* tw = twiddles<T>(tb->device);
+    if (tw == nullptr) return fail(AU_EDEVICE, "twiddle tables missing on this device");
+    hipError_t e;
+    if (ev->trace_dtype == AU_F64)
+        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+    else
+        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
+    if (tb->dtype == AU_F64)
+        launch_coef<double, T>(st, tb, ev0, nullptr, nullptr, n_dir, dirs, 0, 0, ev->fs_hz, ev->fallback_rel,
+                               ev->singular_rel, M, (unsigned long long*)d_counts);
+    else
+        launch_coef<float, T>(st, tb, ev0, nullptr, nullptr, n_dir, dirs, 0, 0, ev->fs_hz, ev->fallback_rel,
+                              ev->singular_rel, M, (unsigned long long*)d_counts);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_coef: ") + hipGetErrorString(e));
+    const int chunks = (p.S + kStationsPerUnit - 1) / kStationsPerUnit;
+    const int64_t n_units = (int64_t)n_dir * chunks;
+    if (n_units > (int64_t)0x7fffffff) return fail(AU_EINVAL, "too many work units");
+    switch (p.N) {
+#define X_(NN)                                                                                              \
+    case NN:                                                                                                \
+        e = launch_env_n<T, NN>(st, ev0, (int)n_units, X, M, (T*)d_efield, (T*)d_peak, (int*)d_arg, tw); \
+        break;
+        AU_FOR_EACH_N(X_)
+#undef X_
+        default: e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_unfold_env: ") + hipGetErrorString(e));
+    return AU_OK;
+}
+
+extern "C" au_status au_unfold_envelope_scan(const au_table* tb, const au_event* ev, const void* d_volt,
+                                             int32_t n_dir, const double* h_dirs, void* d_efield, void* d_peak,
+                                             int32_t* d_arg, void* d_work, uint64_t work_bytes, void* stream,
+                                             uint64_t* d_counts)
+{
+    EvParams p;
+    au_status s = check_event(tb, ev, &p);
+    if (s != AU_OK) return s;
+    if (!d_volt || !d_peak || !d_arg || !h_dirs) return fail(AU_EINVAL, "null argument");
+    if (n_dir < 1) return fail(AU_EINVAL, "n_dir must be >= 1");
+    if (!dirs_finite(h_dirs, n_dir)) return fail(AU_EINVAL, "directions must be finite");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != tb->device) return fail(AU_EINVAL, "table lives on another device");
+    const WsLayout w = ws_layout(p, ev->prec, n_dir);
+    hipStream_t st = (hipStream_t)stream;
+    void* work = d_work;
+    bool pooled = false;
+    if (work == nullptr) {
+        hipError_t e = hipMallocAsync(&work, w.total, st);
+        if (e != hipSuccess) return fail(AU_ENOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        pooled = true;
+    } else if (work_bytes < w.total) {
+        return fail(AU_ENOMEM, "workspace smaller than au_workspace_bytes");
+    }
+    s = ev->prec == AU_PREC_FP64
+            ? run_envelope<double>(tb, ev, p, d_volt, n_dir, h_dirs, d_efield, d_peak, d_arg, work, st, d_counts)
+            : run_envelope<float>(tb, ev, p, d_volt, n_dir, h_dirs, d_efield, d_peak, d_arg, work, st, d_counts);
+    if (pooled) {
+        hipError_t e = hipFreeAsync(work, st);
+        if (s == AU_OK && e != hipSuccess)
+            return fail(AU_EDEVICE, std::string("hipFreeAsync: ") + hipGetErrorString(e));
+    }
+    return s;
 }

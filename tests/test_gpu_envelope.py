@@ -1,0 +1,85 @@
+"""GPU parity of the envelope-peak timing step (au_unfold_envelope_scan)
+against the oracle's Hilbert envelope of its own E-field traces.
+
+The peak value is compared to the tolerance of the path; the sample index
+is an argmax decided in floating point, so it must be a valid argmax of the
+oracle's envelope to the same tolerance (and is equal when no near-tie
+exists)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1507_07733_amd import synth as S
+
+from helpers import TOL_FP32, TOL_FP64, assert_traces_close, oracle_unfold
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    from paper_1507_07733_amd import api as A
+    A.lib()
+    torch.cuda.init()
+    return A
+
+
+def check_peaks(peak, arg, e_ref, tol):
+    pk_ref, arg_ref = O.envelope_peaks(e_ref)
+    pk = peak.astype(np.float64)
+    rel = np.abs(pk - pk_ref) / np.where(pk_ref > 0, pk_ref, 1.0)
+    assert np.max(rel) <= tol, np.max(rel)
+    assert np.all((pk_ref > 0) | (pk == 0))
+    flat_e = e_ref.reshape(-1, e_ref.shape[-1])
+    flat_a = arg.reshape(-1)
+    flat_p = pk_ref.reshape(-1)
+    same = 0
+    for i in range(len(flat_a)):
+        if flat_p[i] == 0:
+            assert flat_a[i] == 0
+            continue
+        env = O.envelope(flat_e[i])
+        assert env[flat_a[i]] >= flat_p[i] * (1 - tol)
+        same += int(flat_a[i] == arg_ref.reshape(-1)[i])
+    return same / len(flat_a)
+
+
+@pytest.mark.parametrize("n", [1024, 2048, 4096])
+def test_envelope_peaks_fp64(api, n):
+    import torch
+    g = S.GRID_COARSE
+    t = S.pattern_table(g, cfg=0)
+    tab = api.Table(g, t)
+    s = 6
+    v = S.traces(s, n, cfg=4, event=n)
+    dirs = np.array([[40.0, 120.0], [70.0, 355.0], [90.0, 30.0], [12.0, 200.0]])
+    ev = api.make_event(s, n)
+    say("envelope fp64 N", n)
+    peak, arg, e = api.unfold_envelope_scan(tab, ev, torch.from_numpy(v).cuda(), dirs, efield=True)
+    torch.cuda.synchronize()
+    ref, _, _ = oracle_unfold(g, t, v, dirs)
+    assert_traces_close(e.cpu().numpy(), ref, TOL_FP64, "envelope-scan traces")
+    frac = check_peaks(peak.cpu().numpy(), arg.cpu().numpy(), ref, TOL_FP64)
+    assert frac > 0.95
+    assert np.all(peak.cpu().numpy()[2] == 0)          # horizon: singular, zero field
+
+
+def test_envelope_peaks_fp32(api):
+    import torch
+    g = S.GRID_FINE
+    t32 = S.pattern_table(g, cfg=2).astype(np.complex64)
+    tab = api.Table(g, t32)
+    s, n = 9, 2048
+    v = S.traces(s, n, cfg=4, event=77, dtype=np.float32)
+    dirs = S.direction_grid(3, 3)
+    ev = api.make_event(s, n, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32)
+    say("envelope fp32")
+    peak, arg, _ = api.unfold_envelope_scan(tab, ev, torch.from_numpy(v).cuda(), dirs)
+    ref, _, _ = oracle_unfold(g, t32, v, dirs)
+    frac = check_peaks(peak.cpu().numpy(), arg.cpu().numpy(), ref, TOL_FP32)
+    assert frac > 0.9
