@@ -663,8 +663,8 @@ constexpr UnfoldVariant kUnfoldVariants[] = {
 };
 constexpr int kNumVariants = 12;
 
-// LDS one workgroup may allocate.
-constexpr int kMaxLdsPerBlock = 65536;
+// LDS one workgroup may allocate on gfx950 (the whole 160 KiB of a CU).
+constexpr int kMaxLdsPerBlock = 163840;
 
 constexpr int variant_e(int n, int v) { return kUnfoldVariants[v].E == 0 ? n / 64 : kUnfoldVariants[v].E; }
 
