@@ -135,6 +135,51 @@ def parity_sample(grid, table_c64, specs, plan, volt_host, efield, n_units=8):
     return worst
 
 
+KAPPA_EDGES = (1.0, 3.0, 10.0, 30.0, 100.0, 1e3, float("inf"))
+
+
+def fp32_error_report(api, plan, specs, efield, tab64, volt, dev):
+    """FP32 batched output vs the FP64 path for every output trace.
+
+    Per event the FP64 direction scan (complex128 table, same float32
+    traces) runs on the device; per trace r = max|E32 - E64| / max|E64|.
+    Traces are bucketed by kappa = max over in-band bins of ||H||_F^2/|det|
+    of their direction (from au_pattern_response in FP64)."""
+    import torch
+    buckets = {i: [] for i in range(len(KAPPA_EDGES) - 1)}
+    worst = 0.0
+    n_tr = 0
+    for e, (s, n, dirs) in enumerate(specs):
+        ev64 = api.make_event(s, n, prec=api.AU_PREC_FP64, trace_dtype=api.AU_F32)
+        o = int(plan.volt_offsets[e])
+        v = volt[o:o + s * 2 * n].view(s, 2, n)
+        e64 = api.unfold_direction_scan(tab64, ev64, v, dirs)
+        e32 = plan.event_output(efield, e)
+        ref = e64.abs().amax(dim=-1)
+        err = (e32.double() - e64).abs().amax(dim=-1) / torch.where(ref > 0, ref, torch.ones_like(ref))
+        h = api.pattern_response(tab64, ev64, dirs)              # [D][nb][2][2] complex128
+        det = h[:, :, 0, 0] * h[:, :, 1, 1] - h[:, :, 0, 1] * h[:, :, 1, 0]
+        fro2 = (h.abs() ** 2).sum(dim=(-1, -2))
+        kappa = (fro2 / det.abs()).amax(dim=-1)                  # [D]
+        kb = torch.bucketize(kappa, torch.tensor(KAPPA_EDGES[1:-1], dtype=kappa.dtype, device=kappa.device))
+        err_d = err.reshape(len(dirs), -1).cpu().numpy()
+        kb = kb.cpu().numpy()
+        for di in range(len(dirs)):
+            buckets[int(kb[di])].append(err_d[di])
+        worst = max(worst, float(err.max()))
+        n_tr += err.numel()
+        del e64
+    out = []
+    for i, lst in buckets.items():
+        if not lst:
+            continue
+        a = np.concatenate(lst)
+        out.append({"kappa": [KAPPA_EDGES[i], KAPPA_EDGES[i + 1]], "traces": int(a.size),
+                    "max": float(a.max()), "p99": float(np.percentile(a, 99)), "median": float(np.median(a))})
+    return {"traces": n_tr, "max": worst, "by_kappa": out,
+            "reference": "FP64 direction scan on the same float32 traces (complex128 table)"}
+
+
 def serving_benchmark(api, synth, tab32, tab64, rate_hz=2000.0, duration_s=3.0, warm_s=0.5,
                       plain_s=1.5, pool=48):
     """Open-loop Poisson stream of events (stations U{3..124}, 2048 float32
@@ -242,6 +287,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--flags", type=int, default=6, help="plan flags: 1 graph, 2 persistent, 4 XCD placement")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-fp32-error", action="store_true", help="skip the FP32-vs-FP64 error pass over every output")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library defaults or --variant-*)")
     ap.add_argument("--variant-fp32", default="", help="pin FP32 unfold variants: V (every N >= 1024) or N=V,N=V")
     ap.add_argument("--variant-fp64", default="", help="pin FP64 unfold variants: V (every N >= 1024) or N=V,N=V")
@@ -365,6 +411,14 @@ def main():
     cnt = counts.cpu().tolist()
     log("parity sample max per-trace error %.3e; fallback/singular counters %s" % (err, cnt))
     del gplan
+    precision = None
+    if not args.no_fp32_error:
+        tab64f = api.Table(grid, synth.pattern_table(grid, cfg=2).astype(np.complex64).astype(np.complex128))
+        precision = fp32_error_report(api, plan, specs, efield, tab64f, volt, dev)
+        log("fp32 vs fp64 over %d traces: max %.3e; %s" % (precision["traces"], precision["max"],
+            ", ".join("kappa %g-%g: max %.2e" % (b["kappa"][0], b["kappa"][1], b["max"]) for b in precision["by_kappa"])))
+        del tab64f
+        torch.cuda.empty_cache()
 
     # ---------------- FP64 plain direction scan ----------------------------
     fp64 = None
@@ -441,6 +495,7 @@ def main():
         "serving": serving,
         "cpu_baseline": cpu,
         "parity_sample_max_err": err,
+        "fp32_error_vs_fp64": precision,
         "fallback_singular_bins": cnt,
     }
     print(json.dumps(line), flush=True)
