@@ -167,9 +167,10 @@ au_status au_unfold_direction_scan(const au_table* table, const au_event* ev, co
  * Direction scan reduced to station timing: the E-field trace's Hilbert
  * envelope env = sqrt(e^2 + H(e)^2) (section 4) and its maximum, whose
  * sample is the updated station time (section 2, Fig. 1).  For every
- * direction, station and component (theta, phi):
- *   d_peak [n_dir][S][2] (float or double per ev->prec): max_n env[n];
- *   d_arg  [n_dir][S][2] int32: the smallest n attaining it.
+ * direction and station, for c = 0 (theta), 1 (phi) and 2 (total field,
+ * sqrt(env_theta^2 + env_phi^2)):
+ *   d_peak [n_dir][S][3] (float or double per ev->prec): max_n env_c[n];
+ *   d_arg  [n_dir][S][3] int32: the smallest n attaining it.
  * d_efield ([n_dir][S][2][N], nullable) also receives the traces.  The
  * Hilbert transform uses -i sgn(k) (sgn 0 at DC and Nyquist); the opposite
  * sign gives the same envelope.  Workspace as au_unfold_direction_scan.

@@ -292,17 +292,17 @@ def unfold_direction_scan(table: Table, ev: AuEvent, volt, dirs, out=None, work=
 
 def unfold_envelope_scan(table: Table, ev: AuEvent, volt, dirs, efield=False, work=None, counts=None,
                          stream=None):
-    """Envelope peaks for every (direction, station, component).
+    """Envelope peaks for every (direction, station) of the theta, phi and total-field envelopes.
 
-    Returns (peak [D][S][2], arg [D][S][2] int32, E or None) where E
+    Returns (peak [D][S][3], arg [D][S][3] int32, E or None) where E
     [D][S][2][N] is also produced when ``efield`` is True (or a tensor).
     """
     import torch
     _check_traces(volt, ev)
     d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 2))
     dt = out_dtype(ev.prec)
-    peak = torch.empty((len(d), ev.n_stations, 2), dtype=dt, device=volt.device)
-    arg = torch.empty((len(d), ev.n_stations, 2), dtype=torch.int32, device=volt.device)
+    peak = torch.empty((len(d), ev.n_stations, 3), dtype=dt, device=volt.device)
+    arg = torch.empty((len(d), ev.n_stations, 3), dtype=torch.int32, device=volt.device)
     out = None
     if efield is True:
         out = torch.empty((len(d), ev.n_stations, 2, ev.n_samples), dtype=dt, device=volt.device)

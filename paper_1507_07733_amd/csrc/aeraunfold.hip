@@ -518,8 +518,8 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
     constexpr int G = groups_per_block<T, N, E>();
     constexpr int NW = (TT + 63) / 64;  // waves per group
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ T red_v[G][NW][2];
-    __shared__ int red_i[G][NW][2];
+    __shared__ T red_v[G][NW][3];
+    __shared__ int red_i[G][NW][3];
     const int g = threadIdx.x / TT, t = threadIdx.x % TT;
     C2<T>* la = reinterpret_cast<C2<T>*>(smem) + g * lds_elems<N>();
     const int chunks = (ev0.S + spw - 1) / spw;
@@ -566,40 +566,55 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
         }
         fft<T, N, E, +1>(x, la, tw, t);
         fft<T, N, E, +1>(xh, la, tw, t);
-        // per-thread maxima over its samples n = t + TT i (increasing in i)
-        T bv[2] = {(T)-1, (T)-1};
-        int bi[2] = {0, 0};
+        // per-thread maxima over its samples n = t + TT i (increasing in i) of
+        // the theta, phi and total-field envelopes
+        T bv[3] = {(T)-1, (T)-1, (T)-1};
+        int bi[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            const T e0 = sqrt(x[i].re * x[i].re + xh[i].re * xh[i].re);
-            const T e1 = sqrt(x[i].im * x[i].im + xh[i].im * xh[i].im);
-            if (e0 > bv[0]) { bv[0] = e0; bi[0] = t + TT * i; }
-            if (e1 > bv[1]) { bv[1] = e1; bi[1] = t + TT * i; }
+            const T p0 = x[i].re * x[i].re + xh[i].re * xh[i].re;
+            const T p1 = x[i].im * x[i].im + xh[i].im * xh[i].im;
+            const T e[3] = {sqrt(p0), sqrt(p1), sqrt(p0 + p1)};
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (e[c] > bv[c]) {
+                    bv[c] = e[c];
+                    bi[c] = t + TT * i;
+                }
         }
         // larger value wins; equal values: smaller sample index
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < 3; ++c) {
             for (int off = 32; off >= 1; off >>= 1) {
                 const T ov = __shfl_xor(bv[c], off);
                 const int oi = __shfl_xor(bi[c], off);
-                if (ov > bv[c] || (ov == bv[c] && oi < bi[c])) { bv[c] = ov; bi[c] = oi; }
+                if (ov > bv[c] || (ov == bv[c] && oi < bi[c])) {
+                    bv[c] = ov;
+                    bi[c] = oi;
+                }
             }
         }
         const int lane = threadIdx.x & 63, wv = t >> 6;
         if (lane == 0) {
-            red_v[g][wv][0] = bv[0]; red_i[g][wv][0] = bi[0];
-            red_v[g][wv][1] = bv[1]; red_i[g][wv][1] = bi[1];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                red_v[g][wv][c] = bv[c];
+                red_i[g][wv][c] = bi[c];
+            }
         }
         __syncthreads();
-        if (active && t < 2) {
+        if (active && t < 3) {
             T v = red_v[g][0][t];
             int ix = red_i[g][0][t];
             for (int w2 = 1; w2 < NW; ++w2) {
                 const T ov = red_v[g][w2][t];
                 const int oi = red_i[g][w2][t];
-                if (ov > v || (ov == v && oi < ix)) { v = ov; ix = oi; }
+                if (ov > v || (ov == v && oi < ix)) {
+                    v = ov;
+                    ix = oi;
+                }
             }
-            const int64_t o = ((int64_t)d * ev0.S + s) * 2 + t;
+            const int64_t o = ((int64_t)d * ev0.S + s) * 3 + t;
             peak[o] = v;
             arg[o] = ix;
         }

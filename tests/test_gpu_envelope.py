@@ -29,21 +29,42 @@ def api():
     return A
 
 
+def total_envelope_peaks(e_ref):
+    """peak and first argmax of sqrt(env_theta^2 + env_phi^2) per [D][S] (oracle envelopes)."""
+    d, s, _, n = e_ref.shape
+    pk = np.zeros((d, s))
+    ar = np.zeros((d, s), dtype=np.int64)
+    for i in range(d):
+        for j in range(s):
+            tot = np.sqrt(O.envelope(e_ref[i, j, 0]) ** 2 + O.envelope(e_ref[i, j, 1]) ** 2)
+            pk[i, j] = tot.max()
+            ar[i, j] = tot.argmax()
+    return pk, ar
+
+
 def check_peaks(peak, arg, e_ref, tol):
-    pk_ref, arg_ref = O.envelope_peaks(e_ref)
+    """peak/arg [D][S][3]: theta, phi from the oracle's envelope_peaks, total from both."""
+    pk_c, arg_c = O.envelope_peaks(e_ref)
+    pk_t, arg_t = total_envelope_peaks(e_ref)
+    pk_ref = np.concatenate([pk_c, pk_t[..., None]], axis=-1)
+    arg_ref = np.concatenate([arg_c, arg_t[..., None]], axis=-1)
     pk = peak.astype(np.float64)
     rel = np.abs(pk - pk_ref) / np.where(pk_ref > 0, pk_ref, 1.0)
     assert np.max(rel) <= tol, np.max(rel)
     assert np.all((pk_ref > 0) | (pk == 0))
-    flat_e = e_ref.reshape(-1, e_ref.shape[-1])
     flat_a = arg.reshape(-1)
     flat_p = pk_ref.reshape(-1)
+    d_, s_ = e_ref.shape[:2]
     same = nonzero = 0
     for i in range(len(flat_a)):
         if flat_p[i] == 0:
             assert flat_a[i] == 0
             continue
-        env = O.envelope(flat_e[i])
+        di, si, c = i // (s_ * 3), (i // 3) % s_, i % 3
+        if c < 2:
+            env = O.envelope(e_ref[di, si, c])
+        else:
+            env = np.sqrt(O.envelope(e_ref[di, si, 0]) ** 2 + O.envelope(e_ref[di, si, 1]) ** 2)
         assert env[flat_a[i]] >= flat_p[i] * (1 - tol)
         same += int(flat_a[i] == arg_ref.reshape(-1)[i])
         nonzero += 1
