@@ -36,6 +36,18 @@
  * 0 < k < N/2, -1 for N/2 < k < N, 0 at k = 0 and N/2.  The paper's phase
  * convention is the opposite sign, which leaves the envelope unchanged.
  *
+ * Reconstruction loop (section 2, Fig. 1): the first station times are the
+ * maxima of the voltage traces; the direction follows from the times by
+ * triangulation; the E-field is reconstructed for that direction; the
+ * maximum of its envelope gives new times; repeat until converged.
+ * Readings: a station's voltage maximum is the sample maximising
+ * V_0^2 + V_1^2; the envelope used for timing is the total-field envelope
+ * sqrt(env_theta^2 + env_phi^2); triangulation is a least-squares plane wave
+ * t_s = t0 + p x_s + q y_s over ground positions (x east, y north), giving the
+ * direction n = (-c p, -c q, ...) towards the source; the loop stops when a
+ * set of station times repeats (a fixed point of the iteration) or after
+ * max_iter directions.
+ *
  * Every pin of this file lives in tests/test_oracle_*.py (brute-force DFT,
  * Parseval, pure tones, exact node interpolation, multilinear
  * reproduction, azimuth wrap, exact rational 2x2 solve, band-pass and
@@ -401,4 +413,123 @@ int orc_envelope_peaks(int64_t n_tr, int64_t n, const double* traces, double* pe
     }
     free(env);
     return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Reconstruction loop: timing -> triangulation -> unfold -> envelope.     */
+/* ---------------------------------------------------------------------- */
+
+static const double ORC_C_M_PER_NS = 0.299792458;
+
+/*
+ * Least-squares plane wave through station times t[s] (samples at fs) at
+ * ground positions pos[s] = (x, y) metres: t_ns = t0 + p x + q y.  Writes
+ * (zenith, azimuth) in degrees of the source direction.  Returns 0, or -1
+ * if the normal equations are singular (fewer than 3 non-collinear stations).
+ */
+int orc_plane_fit(int64_t n_st, const double* pos, const int64_t* t, int64_t fs_hz, double* dir)
+{
+    double a[3][4] = {{0}};
+    const double dt = 1e9 / (double)fs_hz;
+    for (int64_t s = 0; s < n_st; ++s) {
+        const double row[3] = {1.0, pos[2 * s], pos[2 * s + 1]};
+        const double ts = (double)t[s] * dt;
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) a[i][j] += row[i] * row[j];
+            a[i][3] += row[i] * ts;
+        }
+    }
+    /* Gaussian elimination with partial pivoting on the 3x4 augmented matrix */
+    for (int c = 0; c < 3; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+        if (fabs(a[piv][c]) < 1e-300) return -1;
+        if (piv != c)
+            for (int j = 0; j < 4; ++j) { double tmp = a[c][j]; a[c][j] = a[piv][j]; a[piv][j] = tmp; }
+        for (int r = c + 1; r < 3; ++r) {
+            const double f = a[r][c] / a[c][c];
+            for (int j = c; j < 4; ++j) a[r][j] -= f * a[c][j];
+        }
+    }
+    double x[3];
+    for (int c = 2; c >= 0; --c) {
+        double v = a[c][3];
+        for (int j = c + 1; j < 3; ++j) v -= a[c][j] * x[j];
+        x[c] = v / a[c][c];
+    }
+    if (fabs(a[2][2]) < 1e-12 * fabs(a[0][0])) return -1;
+    const double nx = -ORC_C_M_PER_NS * x[1], ny = -ORC_C_M_PER_NS * x[2];
+    double sn = sqrt(nx * nx + ny * ny);
+    if (sn > 1.0) sn = 1.0;
+    double az = atan2(ny, nx) * 180.0 / ORC_PI;
+    if (az < 0.0) az += 360.0;
+    dir[0] = asin(sn) * 180.0 / ORC_PI;
+    dir[1] = az;
+    return 0;
+}
+
+/*
+ * volt [S][2][N], pos [S][2] metres.  dirs_out [max_iter][2] receives the
+ * direction of every iteration, times_out [S] the final station times
+ * (samples), *n_dirs the number of directions produced (the last one is the
+ * result; it is the converged direction if *converged).  Returns 0 or a
+ * negative error (bad sizes, singular geometry, allocation).
+ */
+int orc_reconstruct(const orc_grid* g, const double* tab, int64_t n_st, int64_t n, int64_t fs_hz,
+                    int64_t lo_hz, int64_t hi_hz, double singular_rel, const double* volt,
+                    const double* pos, int64_t max_iter, double* dirs_out, int64_t* times_out,
+                    int64_t* n_dirs, int64_t* converged)
+{
+    if (n_st < 3 || max_iter < 1) return -1;
+    int64_t* t = (int64_t*)malloc(sizeof(int64_t) * (size_t)n_st * 3);
+    double* e = (double*)malloc(sizeof(double) * (size_t)n_st * 2 * (size_t)n);
+    double* env0 = (double*)malloc(sizeof(double) * (size_t)n * 2);
+    if (!t || !e || !env0) { free(t); free(e); free(env0); return -3; }
+    int64_t* units = t + n_st;        /* [S][2] (direction 0, station) */
+    double* env1 = env0 + n;
+    for (int64_t s = 0; s < n_st; ++s) {
+        const double* v0 = volt + (size_t)s * 2 * (size_t)n;
+        const double* v1 = v0 + n;
+        double best = -1.0;
+        int64_t bj = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double pw = v0[j] * v0[j] + v1[j] * v1[j];
+            if (pw > best) { best = pw; bj = j; }
+        }
+        t[s] = bj;
+        units[2 * s] = 0;
+        units[2 * s + 1] = s;
+    }
+    int rc = 0;
+    *n_dirs = 0;
+    *converged = 0;
+    for (int64_t it = 0; it < max_iter; ++it) {
+        double* dir = dirs_out + 2 * it;
+        if (orc_plane_fit(n_st, pos, t, fs_hz, dir)) { rc = -4; break; }
+        *n_dirs = it + 1;
+        rc = orc_unfold_units(g, tab, n_st, n, fs_hz, lo_hz, hi_hz, singular_rel, volt, 1, dir,
+                              n_st, units, e, NULL, NULL);
+        if (rc) break;
+        int64_t changed = 0;
+        for (int64_t s = 0; s < n_st; ++s) {
+            const double* es = e + (size_t)s * 2 * (size_t)n;
+            if ((rc = orc_envelope(n, es, env0)) || (rc = orc_envelope(n, es + n, env1))) break;
+            double best = -1.0;
+            int64_t bj = 0;
+            for (int64_t j = 0; j < n; ++j) {
+                const double tot = sqrt(env0[j] * env0[j] + env1[j] * env1[j]);
+                if (tot > best) { best = tot; bj = j; }
+            }
+            changed += bj != t[s];
+            t[s] = bj;
+        }
+        if (rc) break;
+        if (!changed) { *converged = 1; break; }
+    }
+    for (int64_t s = 0; s < n_st; ++s) times_out[s] = t[s];
+    free(t);
+    free(e);
+    free(env0);
+    return rc;
 }

@@ -66,6 +66,11 @@ def lib():
             L.orc_envelope.restype = C.c_int
             L.orc_envelope_peaks.argtypes = [C.c_int64, C.c_int64, dp, dp, ip]
             L.orc_envelope_peaks.restype = C.c_int
+            L.orc_plane_fit.argtypes = [C.c_int64, dp, ip, C.c_int64, dp]
+            L.orc_plane_fit.restype = C.c_int
+            L.orc_reconstruct.argtypes = [C.POINTER(OrcGrid), dp, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
+                                          C.c_int64, C.c_double, dp, dp, C.c_int64, dp, ip, ip, ip]
+            L.orc_reconstruct.restype = C.c_int
             _lib = L
     return _lib
 
@@ -177,3 +182,32 @@ def envelope_peaks(traces):
     if lib().orc_envelope_peaks(len(flat), n, _dp(flat), _dp(peak), _ip(arg)) != 0:
         raise ValueError("bad trace length")
     return peak.reshape(t.shape[:-1]), arg.reshape(t.shape[:-1])
+
+
+def plane_fit(positions, times, fs_hz: int):
+    """(zenith, azimuth) degrees of the least-squares plane wave through station times (samples)."""
+    p = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 2))
+    t = np.ascontiguousarray(np.asarray(times, dtype=np.int64))
+    d = np.zeros(2)
+    if lib().orc_plane_fit(len(p), _dp(p), _ip(t), fs_hz, _dp(d)) != 0:
+        raise ValueError("singular station geometry")
+    return d
+
+
+def reconstruct(grid, table, volt, positions, fs_hz: int, lo_hz: int, hi_hz: int, max_iter: int = 8,
+                singular_rel: float = 1e-12):
+    """The reconstruction loop; returns (directions [K][2], final station times [S], converged)."""
+    tb = _table128(grid, table)
+    v = np.ascontiguousarray(np.asarray(volt), dtype=np.float64)
+    p = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 2))
+    n_st, two, n = v.shape
+    dirs = np.zeros((max_iter, 2))
+    times = np.zeros(n_st, dtype=np.int64)
+    nd = np.zeros(1, dtype=np.int64)
+    conv = np.zeros(1, dtype=np.int64)
+    g = make_grid(grid)
+    rc = lib().orc_reconstruct(C.byref(g), _dp(tb.view(np.float64)), n_st, n, fs_hz, lo_hz, hi_hz, singular_rel,
+                               _dp(v), _dp(p), max_iter, _dp(dirs), _ip(times), _ip(nd), _ip(conv))
+    if rc != 0:
+        raise ValueError("orc_reconstruct failed with %d" % rc)
+    return dirs[:nd[0]], times, bool(conv[0])

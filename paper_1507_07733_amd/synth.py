@@ -233,3 +233,47 @@ def poisson_arrivals(rate_hz: float, duration_s: float, cfg: int = 3) -> np.ndar
     n = int(rate_hz * duration_s * 1.2) + 16
     t = np.cumsum(r.exponential(1.0 / rate_hz, size=n))
     return t[t < duration_s]
+
+
+# ---------------------------------------------------------------------------
+# Station layout and plane-wave events (for the reconstruction loop)
+# ---------------------------------------------------------------------------
+
+C_M_PER_NS = 0.299792458
+
+
+def station_positions(n: int = 124, area_km2: float = 6.0) -> np.ndarray:
+    """[n][2] (east, north) metres of n stations on a hexagonal grid covering
+    about area_km2 (AERA: 124 stations over about 6 km^2), centred on 0."""
+    a = np.sqrt(2.0 * area_km2 * 1e6 / (np.sqrt(3.0) * n))
+    rings = int(np.ceil(np.sqrt(n))) + 2
+    pts = []
+    for i in range(-rings, rings + 1):
+        for j in range(-rings, rings + 1):
+            pts.append((a * (i + 0.5 * j), a * (np.sqrt(3.0) / 2.0) * j))
+    pts = np.array(pts)
+    r = np.hypot(pts[:, 0], pts[:, 1])
+    order = np.lexsort((np.arctan2(pts[:, 1], pts[:, 0]), np.round(r, 6)))
+    return np.ascontiguousarray(pts[order[:n]])
+
+
+def plane_wave_delays(positions: np.ndarray, zen_deg: float, az_deg: float, fs_hz: int = FS_HZ) -> np.ndarray:
+    """Arrival-time offsets in samples of a plane wave from (zen, az) at ground
+    positions: t = -(n . x) / c with n the unit vector towards the source."""
+    th, ph = np.deg2rad(zen_deg), np.deg2rad(az_deg)
+    nx, ny = np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph)
+    t_ns = -(nx * positions[:, 0] + ny * positions[:, 1]) / C_M_PER_NS
+    return t_ns * fs_hz / 1e9
+
+
+def plane_wave_traces(positions: np.ndarray, n: int, zen_deg: float, az_deg: float, cfg: int, event: int = 0,
+                      dtype=np.float64, noise_sigma: float = 1.0, amp_range=(5.0, 20.0)):
+    """Voltage traces [S][2][N] whose in-band pulses arrive as a plane wave from
+    (zen, az), centred on sample N/2, plus Gaussian noise.  Returns (traces,
+    true arrival samples [S])."""
+    r = rng(cfg, STREAM_TRACES, 1000 + event)
+    s = len(positions)
+    t0 = n / 2.0 + plane_wave_delays(positions, zen_deg, az_deg)
+    amp = r.uniform(amp_range[0], amp_range[1], size=(s, 2))
+    v = r.standard_normal((s, 2, n)) * noise_sigma + pulse(n, np.broadcast_to(t0[:, None], (s, 2)), amp)
+    return np.ascontiguousarray(v.astype(dtype)), t0
