@@ -181,6 +181,42 @@ au_status au_unfold_envelope_scan(const au_table* table, const au_event* ev, con
                                   uint64_t* d_counts);
 
 /*
+ * The reconstruction loop of one event (section 2, Fig. 1), run on the device
+ * with no host round trip between its steps:
+ *   1. station times t_s = the smallest sample maximising V_0^2 + V_1^2
+ *      (evaluated in double, no fused multiply-add);
+ *   2. triangulation: least-squares plane wave t = t0 + p x + q y over the
+ *      station positions (times in ns = samples * 1e9 / fs), direction of
+ *      arrival n = (-c p, -c q) on the ground, c = 0.299792458 m/ns,
+ *      zenith = asin(min(1, |n|)), azimuth = atan2(n_y, n_x) in [0, 360);
+ *   3. unfold every station for that direction (as au_unfold_event);
+ *   4. new t_s = the total-field envelope maximum (as au_unfold_envelope_scan,
+ *      component 2);
+ *   5. stop when no station time changed (converged), else repeat from 2,
+ *      at most max_iter directions.
+ * Inputs: d_volt [S][2][N] device traces (ev->trace_dtype), h_pos [S][2] host
+ * ground positions in metres (x east, y north; finite, |x|, |y| <= 1e7),
+ * 1 <= max_iter <= 1024, S >= 3.
+ * Outputs (host, written before return; the call synchronises the stream):
+ *   h_dirs  [max_iter][2] degrees: rows 0..*n_dirs-1 are the directions of
+ *           each pass, the last one the result;
+ *   h_times [max_iter+1][S] int32 samples: row 0 the voltage maxima, row i the
+ *           envelope maxima after direction i-1; rows 0..*n_dirs are defined;
+ *   *n_dirs, *converged (1 when step 5 ended the loop).
+ *   d_efield ([S][2][N] of ev->prec's type, nullable) and d_peak ([S][3],
+ *   nullable): traces and envelope maxima of the final direction.
+ * Workspace: au_reconstruct_workspace_bytes, or NULL to allocate from the
+ * stream's pool.  AU_EINVAL with *n_dirs set when the stations are collinear
+ * or coincident (the plane fit is undetermined).
+ */
+au_status au_reconstruct_workspace_bytes(const au_table* table, const au_event* ev, int32_t max_iter,
+                                         uint64_t* bytes);
+au_status au_reconstruct(const au_table* table, const au_event* ev, const void* d_volt, const double* h_pos,
+                         int32_t max_iter, double* h_dirs, int32_t* h_times, int32_t* n_dirs,
+                         int32_t* converged, void* d_efield, void* d_peak, void* d_work, uint64_t work_bytes,
+                         void* stream);
+
+/*
  * Interpolated pattern H[c][p](f_k; zen, az) at every in-band bin of ev, for
  * n_dir directions (section 3: linear interpolation between nodes).  Output
  * d_resp [n_dir][n_band][2][2] complex (interleaved re, im) of the precision's

@@ -471,10 +471,12 @@ int orc_plane_fit(int64_t n_st, const double* pos, const int64_t* t, int64_t fs_
 
 /*
  * volt [S][2][N], pos [S][2] metres.  dirs_out [max_iter][2] receives the
- * direction of every iteration, times_out [S] the final station times
- * (samples), *n_dirs the number of directions produced (the last one is the
- * result; it is the converged direction if *converged).  Returns 0 or a
- * negative error (bad sizes, singular geometry, allocation).
+ * direction of every iteration, times_out [max_iter+1][S] the station times
+ * (samples) of every pass: row 0 the voltage maxima, row i+1 the envelope
+ * maxima after direction i (rows 0..*n_dirs are written).  *n_dirs is the
+ * number of directions produced (the last one is the result; it is the
+ * converged direction if *converged).  Returns 0 or a negative error (bad
+ * sizes, singular geometry, allocation).
  */
 int orc_reconstruct(const orc_grid* g, const double* tab, int64_t n_st, int64_t n, int64_t fs_hz,
                     int64_t lo_hz, int64_t hi_hz, double singular_rel, const double* volt,
@@ -498,6 +500,7 @@ int orc_reconstruct(const orc_grid* g, const double* tab, int64_t n_st, int64_t 
             if (pw > best) { best = pw; bj = j; }
         }
         t[s] = bj;
+        times_out[s] = bj;
         units[2 * s] = 0;
         units[2 * s + 1] = s;
     }
@@ -525,9 +528,9 @@ int orc_reconstruct(const orc_grid* g, const double* tab, int64_t n_st, int64_t 
             t[s] = bj;
         }
         if (rc) break;
+        for (int64_t s = 0; s < n_st; ++s) times_out[(it + 1) * n_st + s] = t[s];
         if (!changed) { *converged = 1; break; }
     }
-    for (int64_t s = 0; s < n_st; ++s) times_out[s] = t[s];
     free(t);
     free(e);
     free(env0);

@@ -196,13 +196,17 @@ def plane_fit(positions, times, fs_hz: int):
 
 def reconstruct(grid, table, volt, positions, fs_hz: int, lo_hz: int, hi_hz: int, max_iter: int = 8,
                 singular_rel: float = 1e-12):
-    """The reconstruction loop; returns (directions [K][2], final station times [S], converged)."""
+    """The reconstruction loop.
+
+    Returns (directions [K][2], station times [K+1][S] per pass (row 0 the
+    voltage maxima, row i+1 the envelope maxima after direction i), converged).
+    """
     tb = _table128(grid, table)
     v = np.ascontiguousarray(np.asarray(volt), dtype=np.float64)
     p = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 2))
     n_st, two, n = v.shape
     dirs = np.zeros((max_iter, 2))
-    times = np.zeros(n_st, dtype=np.int64)
+    times = np.zeros((max_iter + 1, n_st), dtype=np.int64)
     nd = np.zeros(1, dtype=np.int64)
     conv = np.zeros(1, dtype=np.int64)
     g = make_grid(grid)
@@ -210,4 +214,4 @@ def reconstruct(grid, table, volt, positions, fs_hz: int, lo_hz: int, hi_hz: int
                                _dp(v), _dp(p), max_iter, _dp(dirs), _ip(times), _ip(nd), _ip(conv))
     if rc != 0:
         raise ValueError("orc_reconstruct failed with %d" % rc)
-    return dirs[:nd[0]], times, bool(conv[0])
+    return dirs[:nd[0]], times[:nd[0] + 1], bool(conv[0])

@@ -110,6 +110,10 @@ _SIG = {
     "au_unfold_envelope_scan": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.c_int32, C.POINTER(C.c_double),
                                             _VP, _VP, _VP, _VP, C.c_uint64, _VP, _VP]),
     "au_pattern_response": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.POINTER(C.c_double), _VP, _VP]),
+    "au_reconstruct_workspace_bytes": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.POINTER(C.c_uint64)]),
+    "au_reconstruct": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.POINTER(C.c_double), C.c_int32,
+                                   C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32), _VP, _VP, _VP, C.c_uint64, _VP]),
     "au_plan_create": (C.c_int32, [_VP, C.POINTER(AuBatch), C.POINTER(_VP)]),
     "au_plan_units": (C.c_int32, [_VP, C.POINTER(C.c_uint64)]),
     "au_plan_run": (C.c_int32, [_VP, _VP, _VP, _VP, _VP]),
@@ -313,6 +317,55 @@ def unfold_envelope_scan(table: Table, ev: AuEvent, volt, dirs, efield=False, wo
                                          d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(out), _ptr(peak),
                                          _ptr(arg), wp, wb, _stream_handle(stream), _ptr(counts)))
     return peak, arg, out
+
+
+def reconstruct_workspace_bytes(table: Table, ev: AuEvent, max_iter: int) -> int:
+    n = C.c_uint64()
+    _check(lib().au_reconstruct_workspace_bytes(table.handle, C.byref(ev), int(max_iter), C.byref(n)))
+    return n.value
+
+
+class Reconstruction:
+    """Result of :func:`reconstruct`: directions per pass, station times per pass, final traces."""
+
+    def __init__(self, dirs, times, converged, efield, peak):
+        self.dirs = dirs            # [K][2] degrees, last = result
+        self.times = times          # [K+1][S] samples: voltage maxima, then envelope maxima per pass
+        self.converged = converged
+        self.efield = efield        # [S][2][N] at the final direction, or None
+        self.peak = peak            # [S][3] envelope maxima at the final direction
+
+    @property
+    def direction(self):
+        return self.dirs[-1]
+
+
+def reconstruct(table: Table, ev: AuEvent, volt, positions, max_iter: int = 8, efield=False, work=None,
+                stream=None) -> Reconstruction:
+    """The reconstruction loop of one event on the device; see au_reconstruct."""
+    import torch
+    _check_traces(volt, ev)
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 2))
+    if len(pos) != ev.n_stations:
+        raise ValueError("positions must have shape [S][2]")
+    dt = out_dtype(ev.prec)
+    out = None
+    if efield is True:
+        out = torch.empty((ev.n_stations, 2, ev.n_samples), dtype=dt, device=volt.device)
+    elif efield is not False and efield is not None:
+        out = efield
+    peak = torch.empty((ev.n_stations, 3), dtype=dt, device=volt.device)
+    dirs = np.zeros((max_iter, 2))
+    times = np.zeros((max_iter + 1, ev.n_stations), dtype=np.int32)
+    nd = C.c_int32()
+    conv = C.c_int32()
+    wp, wb = _work(work)
+    _check(lib().au_reconstruct(table.handle, C.byref(ev), _ptr(volt), pos.ctypes.data_as(C.POINTER(C.c_double)),
+                                int(max_iter), dirs.ctypes.data_as(C.POINTER(C.c_double)),
+                                times.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(nd), C.byref(conv),
+                                _ptr(out), _ptr(peak), wp, wb, _stream_handle(stream)))
+    k = nd.value
+    return Reconstruction(dirs[:k], times[:k + 1], bool(conv.value), out, peak)
 
 
 def pattern_response(table: Table, ev: AuEvent, dirs, device=None, stream=None):

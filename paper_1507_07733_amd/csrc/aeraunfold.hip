@@ -508,15 +508,17 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold(
 // (Zh is the packed spectrum of the Hilbert transforms H(e_th) + i H(e_ph),
 // with H = IDFT(-i sgn(k) DFT)), both are inverse-transformed, and
 // env = sqrt(e^2 + H(e)^2) is reduced to its maximum and the first sample
-// attaining it, per component.  Optionally the traces are stored too.
+// attaining it, per component.  Optionally the traces are stored too.  A
+// non-null skip flag that reads nonzero turns the launch into a no-op.
 template <typename T, int N, int E>
 __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_env(
     EvDesc ev0, int spw, const XBin<T>* __restrict__ X, const MBin<T>* __restrict__ M, T* __restrict__ efield,
-    T* __restrict__ peak, int* __restrict__ arg, const C2<T>* __restrict__ tw)
+    T* __restrict__ peak, int* __restrict__ arg, const C2<T>* __restrict__ tw, const int* __restrict__ skip)
 {
     constexpr int TT = N / E;
     constexpr int G = groups_per_block<T, N, E>();
     constexpr int NW = (TT + 63) / 64;  // waves per group
+    if (skip != nullptr && *skip) return;  // set by a converged reconstruction loop
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ T red_v[G][NW][3];
     __shared__ int red_i[G][NW][3];
@@ -1920,14 +1922,14 @@ extern "C" au_status au_hbm_fill(void* d_dst, uint64_t bytes, uint32_t value, vo
 
 template <typename T, int N>
 static hipError_t launch_env_n(hipStream_t st, const EvDesc& ev0, int n_units, const XBin<T>* X, const MBin<T>* M,
-                               T* efield, T* peak, int* arg, const C2<T>* tw)
+                               T* efield, T* peak, int* arg, const C2<T>* tw, const int* skip = nullptr)
 {
     constexpr int E = N >= 1024 ? 8 : (N < 16 ? N : 16);
     constexpr int TT = N / E;
     constexpr int G = groups_per_block<T, N, E>();
     constexpr size_t LDS = (size_t)G * lds_elems<N>() * sizeof(C2<T>);
     hipLaunchKernelGGL((k_unfold_env<T, N, E>), dim3(n_units), dim3(G * TT), LDS, st, ev0, kStationsPerUnit, X, M,
-                       efield, peak, arg, tw);
+                       efield, peak, arg, tw, skip);
     return hipGetLastError();
 }
 
@@ -2014,4 +2016,311 @@ extern "C" au_status au_unfold_envelope_scan(const au_table* tb, const au_event*
             return fail(AU_EDEVICE, std::string("hipFreeAsync: ") + hipGetErrorString(e));
     }
     return s;
+}
+
+// ---------------------------------------------------------------------------
+// reconstruction loop (section 2, Fig. 1): voltage timing -> triangulation ->
+// unfold -> envelope timing, repeated on the device with no host round trip;
+// a device stop flag turns the steps after convergence into no-ops
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr double kCMPerNs = 0.299792458;
+constexpr int kMaxReconIter = 1024;
+
+// larger value wins; equal values: the smaller index
+template <typename V>
+__device__ inline void amax_merge(V& v, int& i, V ov, int oi)
+{
+    if (ov > v || (ov == v && oi < i)) {
+        v = ov;
+        i = oi;
+    }
+}
+
+// block-wide argmax over kBlock threads, result in thread 0
+__device__ void block_argmax(double& v, int& i)
+{
+    __shared__ double sv[kBlock / 64];
+    __shared__ int si[kBlock / 64];
+    for (int off = 32; off >= 1; off >>= 1) amax_merge(v, i, __shfl_xor(v, off), __shfl_xor(i, off));
+    if ((threadIdx.x & 63) == 0) {
+        sv[threadIdx.x >> 6] = v;
+        si[threadIdx.x >> 6] = i;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < kBlock / 64; ++w) amax_merge(v, i, sv[w], si[w]);
+}
+
+// block-wide sums of K doubles over kBlock threads, result in every thread
+template <int K>
+__device__ void block_sum(double (&v)[K])
+{
+    __shared__ double sv[K][kBlock / 64];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        for (int off = 32; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off);
+        if ((threadIdx.x & 63) == 0) sv[k][threadIdx.x >> 6] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        v[k] = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) v[k] += sv[k][w];
+    }
+    __syncthreads();
+}
+
+}  // namespace
+
+// First station times: the smallest sample maximising V_0^2 + V_1^2, in double
+// with every operation rounded on its own (no contraction into fma), so the
+// decision is the one a plain double evaluation takes.  One block per station.
+template <typename Tin>
+__global__ __launch_bounds__(kBlock) void k_volt_timing(const Tin* __restrict__ volt, int N, int* __restrict__ t0)
+{
+#pragma clang fp contract(off)
+    const Tin* __restrict__ v0 = volt + (int64_t)blockIdx.x * 2 * N;
+    const Tin* __restrict__ v1 = v0 + N;
+    double bv = -1.0;
+    int bi = 0;
+    for (int j = threadIdx.x; j < N; j += kBlock) {
+        const double a = (double)v0[j], b = (double)v1[j];
+        const double pw = a * a + b * b;
+        amax_merge(bv, bi, pw, j);
+    }
+    block_argmax(bv, bi);
+    if (threadIdx.x == 0) t0[blockIdx.x] = bi;
+}
+
+// One step of the loop, one block.  state: [0] stop, [1] directions produced,
+// [2] converged, [3] degenerate station geometry.  For it >= 1 the total-field
+// envelope maxima of the previous unfold become times row it; when no station
+// time changed the loop has converged and stops.  Otherwise (and at it = 0,
+// whose row holds the voltage maxima) the plane wave t = t0 + p x + q y is
+// fitted by least squares about the centroid and the direction of arrival,
+// n = (-c p, -c q) on the ground, is written to dirs[it] and cur.  last: the
+// step after the final unfold, convergence check only.
+__global__ __launch_bounds__(kBlock) void k_recon_step(int it, int last, int S, double dt_ns,
+                                                        const double* __restrict__ pos,
+                                                        const int* __restrict__ env_arg, int* __restrict__ hist,
+                                                        double* __restrict__ dirs, double* __restrict__ cur,
+                                                        int* __restrict__ state)
+{
+    if (state[0]) return;
+    int* __restrict__ row = hist + (int64_t)it * S;
+    if (it > 0) {
+        int changed = 0;
+        for (int s = threadIdx.x; s < S; s += kBlock) {
+            const int t = env_arg[3 * s + 2];
+            changed |= t != row[s - S];
+            row[s] = t;
+        }
+        changed = __syncthreads_or(changed);
+        if (!changed || last) {
+            if (threadIdx.x == 0) {
+                state[0] = 1;
+                state[2] = !changed;
+            }
+            return;
+        }
+    }
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int s = threadIdx.x; s < S; s += kBlock) {
+        m[0] += pos[2 * s];
+        m[1] += pos[2 * s + 1];
+        m[2] += (double)row[s] * dt_ns;
+    }
+    block_sum(m);
+    const double inv_s = 1.0 / (double)S;
+    const double mx = m[0] * inv_s, my = m[1] * inv_s, mt = m[2] * inv_s;
+    double c[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // xx, xy, yy, xt, yt about the centroid
+    for (int s = threadIdx.x; s < S; s += kBlock) {
+        const double dx = pos[2 * s] - mx, dy = pos[2 * s + 1] - my, dt = (double)row[s] * dt_ns - mt;
+        c[0] += dx * dx;
+        c[1] += dx * dy;
+        c[2] += dy * dy;
+        c[3] += dx * dt;
+        c[4] += dy * dt;
+    }
+    block_sum(c);
+    if (threadIdx.x != 0) return;
+    const double det = c[0] * c[2] - c[1] * c[1];
+    const double p = (c[2] * c[3] - c[1] * c[4]) / det, q = (c[0] * c[4] - c[1] * c[3]) / det;
+    const double nx = -kCMPerNs * p, ny = -kCMPerNs * q;
+    const double sn = fmin(1.0, sqrt(nx * nx + ny * ny));
+    double az = atan2(ny, nx) * (180.0 / M_PI);
+    if (az < 0.0) az += 360.0;
+    const double zen = asin(sn) * (180.0 / M_PI);
+    if (!(det > 1e-12 * c[0] * c[2]) || !isfinite(zen) || !isfinite(az)) {
+        cur[0] = 0.0;
+        cur[1] = 0.0;
+        state[3] = 1;
+        state[0] = 1;
+        return;
+    }
+    dirs[2 * it] = zen;
+    dirs[2 * it + 1] = az;
+    cur[0] = zen;
+    cur[1] = az;
+    state[1] = it + 1;
+}
+
+namespace {
+
+struct ReconLayout {
+    size_t base, hist, dirs, cur, state, pos, peak, arg, total;
+};
+
+ReconLayout recon_layout(const EvParams& p, int prec, int max_iter)
+{
+    ReconLayout r;
+    r.base = ws_layout(p, prec, 1).total;
+    r.hist = align256((size_t)(max_iter + 1) * p.S * sizeof(int32_t));
+    r.dirs = align256((size_t)max_iter * 2 * sizeof(double));
+    r.cur = 256;
+    r.state = 256;
+    r.pos = align256((size_t)p.S * 2 * sizeof(double));
+    r.peak = align256((size_t)p.S * 3 * (prec == AU_PREC_FP64 ? sizeof(double) : sizeof(float)));
+    r.arg = align256((size_t)p.S * 3 * sizeof(int32_t));
+    r.total = r.base + r.hist + r.dirs + r.cur + r.state + r.pos + r.peak + r.arg;
+    return r;
+}
+
+au_status check_recon(const au_table* tb, const au_event* ev, int32_t max_iter, EvParams* p)
+{
+    au_status s = check_event(tb, ev, p);
+    if (s != AU_OK) return s;
+    if (p->S < 3) return fail(AU_EINVAL, "the reconstruction needs at least 3 stations");
+    if (max_iter < 1 || max_iter > kMaxReconIter) return fail(AU_EINVAL, "max_iter must be in [1, 1024]");
+    return AU_OK;
+}
+
+}  // namespace
+
+template <typename T>
+static au_status run_reconstruct(const au_table* tb, const au_event* ev, const EvParams& p, const void* d_volt,
+                                 const double* h_pos, int max_iter, void* d_efield, void* d_peak, void* d_work,
+                                 hipStream_t st, double* h_dirs, int32_t* h_times, int32_t* h_state)
+{
+    const ReconLayout r = recon_layout(p, ev->prec, max_iter);
+    const WsLayout w = ws_layout(p, ev->prec, 1);
+    unsigned char* base = (unsigned char*)d_work;
+    XBin<T>* X = (XBin<T>*)base;
+    MBin<T>* M = (MBin<T>*)(base + w.x);
+    unsigned char* q = base + r.base;
+    int* hist = (int*)q;
+    double* dirs = (double*)(q += r.hist);
+    double* cur = (double*)(q += r.dirs);
+    int* state = (int*)(q += r.cur);
+    double* pos = (double*)(q += r.state);
+    T* peak = d_peak ? (T*)d_peak : (T*)(q += r.pos);
+    int* arg = (int*)(base + r.total - r.arg);
+    HIP_TRY(hipMemcpyAsync(pos, h_pos, sizeof(double) * 2 * p.S, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (unsigned int*)state, 4);
+    EvDesc ev0{};
+    ev0.S = p.S;
+    ev0.N = p.N;
+    ev0.D = 1;
+    ev0.k_lo = p.k_lo;
+    ev0.nb = p.nb;
+    const C2<T>* tw = twiddles<T>(tb->device);
+    if (tw == nullptr) return fail(AU_EDEVICE, "twiddle tables missing on this device");
+    hipError_t e;
+    if (ev->trace_dtype == AU_F64) {
+        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+        hipLaunchKernelGGL(k_volt_timing<double>, dim3(p.S), dim3(kBlock), 0, st, (const double*)d_volt, p.N, hist);
+    } else {
+        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+        hipLaunchKernelGGL(k_volt_timing<float>, dim3(p.S), dim3(kBlock), 0, st, (const float*)d_volt, p.N, hist);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("spectrum/timing: ") + hipGetErrorString(e));
+    const double dt_ns = 1e9 / (double)ev->fs_hz;
+    for (int it = 0; it <= max_iter; ++it) {
+        const int last = it == max_iter;
+        hipLaunchKernelGGL(k_recon_step, dim3(1), dim3(kBlock), 0, st, it, last, p.S, dt_ns, (const double*)pos,
+                           (const int*)arg, hist, dirs, cur, state);
+        if (last) break;
+        if (tb->dtype == AU_F64)
+            launch_coef<double, T>(st, tb, ev0, nullptr, nullptr, 1, cur, 0, 0, ev->fs_hz, ev->fallback_rel,
+                                   ev->singular_rel, M, nullptr);
+        else
+            launch_coef<float, T>(st, tb, ev0, nullptr, nullptr, 1, cur, 0, 0, ev->fs_hz, ev->fallback_rel,
+                                  ev->singular_rel, M, nullptr);
+        const int chunks = (p.S + kStationsPerUnit - 1) / kStationsPerUnit;
+        switch (p.N) {
+#define X_(NN)                                                                                               \
+    case NN:                                                                                                 \
+        e = launch_env_n<T, NN>(st, ev0, chunks, X, M, (T*)d_efield, peak, arg, tw, (const int*)state); \
+        break;
+            AU_FOR_EACH_N(X_)
+#undef X_
+            default: e = hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return fail(AU_EDEVICE, std::string("reconstruction step: ") + hipGetErrorString(e));
+    }
+    HIP_TRY(hipMemcpyAsync(h_state, state, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h_dirs, dirs, sizeof(double) * 2 * max_iter, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h_times, hist, sizeof(int32_t) * (size_t)(max_iter + 1) * p.S, hipMemcpyDeviceToHost,
+                           st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return AU_OK;
+}
+
+extern "C" au_status au_reconstruct_workspace_bytes(const au_table* tb, const au_event* ev, int32_t max_iter,
+                                                    uint64_t* bytes)
+{
+    if (!bytes) return fail(AU_EINVAL, "null argument");
+    EvParams p;
+    au_status s = check_recon(tb, ev, max_iter, &p);
+    if (s != AU_OK) return s;
+    *bytes = recon_layout(p, ev->prec, max_iter).total;
+    return AU_OK;
+}
+
+extern "C" au_status au_reconstruct(const au_table* tb, const au_event* ev, const void* d_volt,
+                                    const double* h_pos, int32_t max_iter, double* h_dirs, int32_t* h_times,
+                                    int32_t* n_dirs, int32_t* converged, void* d_efield, void* d_peak,
+                                    void* d_work, uint64_t work_bytes, void* stream)
+{
+    EvParams p;
+    au_status s = check_recon(tb, ev, max_iter, &p);
+    if (s != AU_OK) return s;
+    if (!d_volt || !h_pos || !h_dirs || !h_times || !n_dirs || !converged) return fail(AU_EINVAL, "null argument");
+    for (int64_t i = 0; i < 2 * (int64_t)p.S; ++i)
+        if (!std::isfinite(h_pos[i]) || std::fabs(h_pos[i]) > 1e7)
+            return fail(AU_EINVAL, "station positions must be finite and within 1e7 m");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != tb->device) return fail(AU_EINVAL, "table lives on another device");
+    const ReconLayout r = recon_layout(p, ev->prec, max_iter);
+    hipStream_t st = (hipStream_t)stream;
+    void* work = d_work;
+    bool pooled = false;
+    if (work == nullptr) {
+        hipError_t e = hipMallocAsync(&work, r.total, st);
+        if (e != hipSuccess) return fail(AU_ENOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        pooled = true;
+    } else if (work_bytes < r.total) {
+        return fail(AU_ENOMEM, "workspace smaller than au_reconstruct_workspace_bytes");
+    }
+    int32_t state[4] = {0, 0, 0, 0};
+    s = ev->prec == AU_PREC_FP64
+            ? run_reconstruct<double>(tb, ev, p, d_volt, h_pos, max_iter, d_efield, d_peak, work, st, h_dirs,
+                                      h_times, state)
+            : run_reconstruct<float>(tb, ev, p, d_volt, h_pos, max_iter, d_efield, d_peak, work, st, h_dirs,
+                                     h_times, state);
+    if (pooled) {
+        hipError_t e = hipFreeAsync(work, st);
+        if (s == AU_OK && e != hipSuccess)
+            return fail(AU_EDEVICE, std::string("hipFreeAsync: ") + hipGetErrorString(e));
+    }
+    if (s != AU_OK) return s;
+    *n_dirs = state[1];
+    *converged = state[2];
+    if (state[3]) return fail(AU_EINVAL, "degenerate station geometry (collinear or coincident stations)");
+    return AU_OK;
 }

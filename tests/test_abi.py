@@ -51,6 +51,9 @@ def test_validation_without_device(lib):
     assert b"table" in lib.au_last_error()
     assert lib.au_plan_create(None, None, None) == api.AU_EINVAL
     assert lib.au_unfold_event(None, C.byref(ev), None, 0.0, 0.0, None, None, 0, None, None) == api.AU_EINVAL
+    assert lib.au_reconstruct_workspace_bytes(None, C.byref(ev), 4, C.byref(n)) == api.AU_EINVAL
+    assert lib.au_reconstruct(None, C.byref(ev), None, None, 4, None, None, None, None, None, None, None, 0,
+                              None) == api.AU_EINVAL
     assert lib.au_free_pattern_table(None) == api.AU_OK
 
 

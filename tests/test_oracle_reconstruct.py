@@ -33,6 +33,19 @@ def test_reconstruction_converges_near_truth(zen, az):
     v, t_true = S.plane_wave_traces(pos, 2048, zen, az, cfg=6, event=int(zen))
     dirs, times, conv = O.reconstruct(g, t, v, pos, S.FS_HZ, S.BAND_LO_HZ, S.BAND_HI_HZ, max_iter=6)
     assert conv
+    assert len(times) == len(dirs) + 1
+    assert np.array_equal(times[-1], times[-2])          # converged: the last pass repeated its times
+    pw = (v.astype(np.float64) ** 2).sum(axis=1)
+    assert np.array_equal(times[0], pw.argmax(axis=1))    # first times: voltage maxima
+    # every direction is the plane fit of the times before it
+    for i, d in enumerate(dirs):
+        assert np.allclose(O.plane_fit(pos, times[i], S.FS_HZ), d, rtol=0, atol=1e-12)
+    # the final times are the total-field envelope maxima of the unfold at the final direction
+    e, _, _ = O.unfold(g, t, v, dirs[-1:], S.FS_HZ, S.BAND_LO_HZ, S.BAND_HI_HZ)
+    for s in range(len(pos)):
+        tot = np.sqrt(O.envelope(e[0, s, 0]) ** 2 + O.envelope(e[0, s, 1]) ** 2)
+        assert tot.argmax() == times[-1][s]
+    times = times[-1]
     zf, af = dirs[-1]
     assert abs(zf - zen) < 1.0
     assert min(abs(af - az), 360 - abs(af - az)) < 2.0
