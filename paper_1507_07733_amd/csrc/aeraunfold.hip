@@ -584,10 +584,13 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                     bi[c] = t + TT * i;
                 }
         }
-        // larger value wins; equal values: smaller sample index
+        // larger value wins; equal values: smaller sample index.  A group of
+        // TT < 64 threads shares its wave with other groups, so the butterfly
+        // stays within the group's TT lanes.
+        constexpr int kShfl = TT < 64 ? TT / 2 : 32;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            for (int off = 32; off >= 1; off >>= 1) {
+            for (int off = kShfl; off >= 1; off >>= 1) {
                 const T ov = __shfl_xor(bv[c], off);
                 const int oi = __shfl_xor(bi[c], off);
                 if (ov > bv[c] || (ov == bv[c] && oi < bi[c])) {
@@ -596,8 +599,8 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                 }
             }
         }
-        const int lane = threadIdx.x & 63, wv = t >> 6;
-        if (lane == 0) {
+        const int wv = t >> 6;
+        if ((t & 63) == 0) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 red_v[g][wv][c] = bv[c];

@@ -71,7 +71,7 @@ def check_peaks(peak, arg, e_ref, tol):
     return same / max(nonzero, 1)
 
 
-@pytest.mark.parametrize("n", [1024, 2048, 4096])
+@pytest.mark.parametrize("n", [16, 64, 256, 1024, 2048, 4096])
 def test_envelope_peaks_fp64(api, n):
     import torch
     g = S.GRID_COARSE
