@@ -608,18 +608,19 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
             }
         }
         __syncthreads();
-        if (active && t < 3) {
-            T v = red_v[g][0][t];
-            int ix = red_i[g][0][t];
+        // components c = t, t + TT, ... (a group of N = 16 or 32 has fewer than 3 threads)
+        for (int c = t; active && c < 3; c += TT) {
+            T v = red_v[g][0][c];
+            int ix = red_i[g][0][c];
             for (int w2 = 1; w2 < NW; ++w2) {
-                const T ov = red_v[g][w2][t];
-                const int oi = red_i[g][w2][t];
+                const T ov = red_v[g][w2][c];
+                const int oi = red_i[g][w2][c];
                 if (ov > v || (ov == v && oi < ix)) {
                     v = ov;
                     ix = oi;
                 }
             }
-            const int64_t o = ((int64_t)d * ev0.S + s) * 3 + t;
+            const int64_t o = ((int64_t)d * ev0.S + s) * 3 + c;
             peak[o] = v;
             arg[o] = ix;
         }
