@@ -341,11 +341,6 @@ def main():
     tab = api.Table(grid, table)
     specs = build_batched_workload(args.events)
     tuned = {}
-    for n in sorted(set(sp[1] for sp in specs)) if not args.no_tune else []:
-        best, ms = api.autotune(tab, api.make_event(124, n, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32),
-                                n_dir=256, reps=5)
-        tuned["fp32_N%d" % n] = {"variant": best, "shape": api.unfold_variants()[best], "ms": ms}
-        log("autotune fp32 N=%d: variant %d %s" % (n, best, api.unfold_variants()[best]))
     flags = args.flags & ~api.AU_PLAN_GRAPH      # stage timing needs eager launches
     plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=flags)
     volt_host = gen_traces(specs, plan.volt_offsets, plan.volt_elems)
@@ -354,6 +349,13 @@ def main():
     counts = torch.zeros(2, dtype=torch.int64, device=dev)
     log("batched workload ready: %d events, %d station-unfolds, %.1f GB out, setup %.1f s"
         % (len(specs), plan.station_unfolds, plan.efield_elems * 4 / 1e9, time.perf_counter() - t0))
+    if not args.no_tune and not args.variant_fp32:
+        # every unfold variant timed inside this plan; the graph plan below takes the same choice
+        for n, best, ms in plan.autotune(volt, efield, reps=3):
+            api.set_unfold_variant(api.AU_PREC_FP32, n, best)
+            tuned["fp32_N%d" % n] = {"variant": best, "shape": api.unfold_variants()[best],
+                                     "unfold_ms": [round(m, 4) for m in ms]}
+            log("in-plan autotune fp32 N=%d: variant %d %s" % (n, best, api.unfold_variants()[best]))
 
     for _ in range(args.warmup):
         plan.run(volt, efield, counts)
@@ -429,7 +431,7 @@ def main():
         dirs1 = synth.direction_grid(32, 64)
         v1 = torch.from_numpy(synth.traces(s1, n1, cfg=1, event=0)).to(dev)
         ev = api.make_event(s1, n1, prec=api.AU_PREC_FP64, trace_dtype=api.AU_F64)
-        if not args.no_tune:
+        if not args.no_tune and not args.variant_fp64:
             best, ms = api.autotune(t1, ev, n_dir=256, reps=5)
             tuned["fp64_N%d" % n1] = {"variant": best, "shape": api.unfold_variants()[best], "ms": ms}
             log("autotune fp64 N=%d: variant %d" % (n1, best))

@@ -272,6 +272,20 @@ au_status au_plan_run(au_plan* plan, const void* d_volt, void* d_efield, void* s
                       uint64_t* d_counts);
 
 /*
+ * Tune the plan's unfold kernel per trace-length class: every built variant
+ * (au_unfold_variant_count) is run inside this plan (its work lists,
+ * placement and persistent grid) on d_volt / d_efield, reps timed runs after
+ * one warm-up, timed by HIP events around the class's unfold launch; the
+ * fastest is kept for later runs (a captured graph is re-captured).  ms
+ * ([n_classes][variant count], nullable) receives the average ms per launch
+ * (-1 for a variant not built for that length), best ([n_classes], nullable)
+ * the chosen variant.  Synchronises the stream.  The global per-length
+ * choice (au_set_unfold_variant) is left unchanged.
+ */
+au_status au_plan_autotune(au_plan* plan, const void* d_volt, void* d_efield, int32_t reps, void* stream,
+                           double* ms, int32_t* best);
+
+/*
  * Stage timing for measurement: with timing enabled (plans without
  * AU_PLAN_GRAPH only), au_plan_run records a HIP event on the run's stream
  * before the first launch and after each launch, waits for the last one and

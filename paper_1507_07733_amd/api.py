@@ -118,6 +118,7 @@ _SIG = {
     "au_plan_units": (C.c_int32, [_VP, C.POINTER(C.c_uint64)]),
     "au_plan_run": (C.c_int32, [_VP, _VP, _VP, _VP, _VP]),
     "au_plan_free": (C.c_int32, [_VP]),
+    "au_plan_autotune": (C.c_int32, [_VP, _VP, _VP, C.c_int32, _VP, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "au_plan_timing": (C.c_int32, [_VP, C.c_int32]),
     "au_plan_classes": (C.c_int32, [_VP, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_uint64),
                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -480,6 +481,22 @@ class Plan:
         if trace_code(volt) != self.trace_dtype or efield.dtype != out_dtype(self.prec):
             raise ValueError("buffer dtypes do not match the plan")
         _check(lib().au_plan_run(self.handle, _ptr(volt), _ptr(efield), _stream_handle(stream), _ptr(counts)))
+
+    def autotune(self, volt, efield, reps: int = 3, stream=None):
+        """Pick the fastest unfold variant per class inside this plan.
+
+        Returns [(n_samples, best variant, [ms per variant, -1 if not built])].
+        """
+        if volt.numel() < self.volt_elems or efield.numel() < self.efield_elems:
+            raise ValueError("buffers smaller than the plan's offsets require")
+        nc = len(self.classes())
+        nv = len(unfold_variants())
+        ms = (C.c_double * (nc * nv))()
+        best = (C.c_int32 * nc)()
+        _check(lib().au_plan_autotune(self.handle, _ptr(volt), _ptr(efield), int(reps), _stream_handle(stream),
+                                      ms, best))
+        cls = self.classes()
+        return [(cls[i][0], best[i], list(ms[i * nv:(i + 1) * nv])) for i in range(nc)]
 
     def set_timing(self, enable: bool):
         _check(lib().au_plan_timing(self.handle, 1 if enable else 0))

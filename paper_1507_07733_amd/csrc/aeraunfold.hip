@@ -1697,6 +1697,69 @@ extern "C" au_status au_plan_run(au_plan* pl, const void* d_volt, void* d_efield
     return AU_OK;
 }
 
+
+// Per trace-length class, time every built unfold variant inside the plan
+// itself (its own work lists, placement and persistent grid), with HIP events
+// around the class's unfold launch, and keep the fastest.
+extern "C" au_status au_plan_autotune(au_plan* pl, const void* d_volt, void* d_efield, int32_t reps, void* stream,
+                                      double* ms, int32_t* best)
+{
+    if (!pl || !d_volt || !d_efield) return fail(AU_EINVAL, "null argument");
+    if (reps < 1) return fail(AU_EINVAL, "reps must be >= 1");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != pl->device) return fail(AU_EINVAL, "plan lives on another device");
+    hipStream_t st = (hipStream_t)stream;
+    const bool was_timing = pl->timing;
+    const std::vector<double> saved_ms = pl->stage_ms;
+    const uint64_t saved_runs = pl->timed_runs;
+    if (pl->ev.empty()) {
+        pl->ev.resize(3 * pl->classes.size() + 1);
+        for (auto& e : pl->ev) HIP_TRY(hipEventCreate(&e));
+    }
+    const int tsize = pl->prec == AU_PREC_FP64 ? 8 : 4;
+    au_status rc = AU_OK;
+    for (size_t i = 0; i < pl->classes.size() && rc == AU_OK; ++i) {
+        ClassPlan& cp = pl->classes[i];
+        double best_ms = 1e300;
+        int best_v = cp.variant;
+        for (int v = 0; v < kNumVariants && rc == AU_OK; ++v) {
+            if (ms) ms[i * kNumVariants + v] = -1.0;
+            if (!variant_built(cp.N, v, tsize)) continue;
+            cp.variant = v;
+            cp.persistent_blocks = au::persistent_blocks(pl->prec, cp.N, v, pl->device);
+            pl->timing = false;
+            rc = plan_enqueue(pl, d_volt, d_efield, st, nullptr);  // warm-up
+            pl->timing = true;
+            pl->stage_ms.assign(3 * pl->classes.size(), 0.0);
+            pl->timed_runs = 0;
+            for (int r = 0; r < reps && rc == AU_OK; ++r) rc = plan_enqueue(pl, d_volt, d_efield, st, nullptr);
+            if (rc != AU_OK) break;
+            const double t = pl->stage_ms[3 * i + 2] / reps;
+            if (ms) ms[i * kNumVariants + v] = t;
+            if (t < best_ms) {
+                best_ms = t;
+                best_v = v;
+            }
+        }
+        cp.variant = best_v;
+        cp.persistent_blocks = au::persistent_blocks(pl->prec, cp.N, best_v, pl->device);
+        if (best) best[i] = best_v;
+    }
+    pl->timing = was_timing;
+    pl->stage_ms = saved_ms;
+    pl->timed_runs = saved_runs;
+    if (pl->exec) {  // the captured graph holds the old launch shapes
+        (void)hipGraphExecDestroy(pl->exec);
+        pl->exec = nullptr;
+    }
+    if (pl->graph) {
+        (void)hipGraphDestroy(pl->graph);
+        pl->graph = nullptr;
+    }
+    return rc;
+}
+
 // ---------------------------------------------------------------------------
 // unfold-kernel variants and the autotuner
 // ---------------------------------------------------------------------------

@@ -287,3 +287,38 @@ def test_autotune_selects_a_built_variant(api, coarse):
     best, ms = api.autotune(tab, ev, n_dir=4, reps=1)
     assert ms[best] > 0 and ms[best] == min(m for m in ms if m > 0)
     assert api.get_unfold_variant(api.AU_PREC_FP64, 2048) == best
+
+
+@pytest.mark.parametrize("flags", [3, 6])
+def test_plan_autotune_keeps_results(api, flags):
+    """In-plan tuning picks a built variant per class, leaves the global choice alone, and the
+    tuned plan (graph re-captured when flags has AU_PLAN_GRAPH) still meets the FP32 bar."""
+    import torch
+    t32 = S.pattern_table(GF, cfg=2).astype(np.complex64)
+    tab = api.Table(GF, t32)
+    specs = [(13, 4096, S.direction_grid(2, 2)), (7, 2048, S.direction_grid(3, 1)), (3, 1024, [[30.0, 30.0]])]
+    say("plan autotune flags", flags)
+    plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=flags)
+    volt = np.zeros(plan.volt_elems, dtype=np.float32)
+    vs = []
+    for e, (s, n, _) in enumerate(specs):
+        v = S.traces(s, n, cfg=2, event=90 + e, dtype=np.float32)
+        vs.append(v)
+        volt[plan.volt_offsets[e]:plan.volt_offsets[e] + v.size] = v.ravel()
+    dv = to_dev(volt)
+    out = torch.zeros(plan.efield_elems, dtype=torch.float32, device="cuda")
+    plan.run(dv, out)                                   # captures the graph with the default variants
+    before = {n: api.get_unfold_variant(api.AU_PREC_FP32, n) for n in (1024, 2048, 4096)}
+    res = plan.autotune(dv, out, reps=1)
+    assert [r[0] for r in res] == [4096, 2048, 1024]
+    for (n, best, ms), (n2, _, var) in zip(res, plan.classes()):
+        assert n == n2 and var == best
+        assert ms[best] > 0 and ms[best] == min(m for m in ms if m > 0)
+    assert before == {n: api.get_unfold_variant(api.AU_PREC_FP32, n) for n in (1024, 2048, 4096)}
+    out.fill_(float("nan"))
+    plan.run(dv, out)
+    plan.run(dv, out)
+    torch.cuda.synchronize()
+    for e, (s, n, d) in enumerate(specs):
+        ref, _, _ = oracle_unfold(GF, t32, vs[e], d)
+        assert_traces_close(plan.event_output(out, e).cpu().numpy(), ref, TOL_FP32, "tuned plan event %d" % e)
