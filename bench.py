@@ -180,6 +180,61 @@ def fp32_error_report(api, plan, specs, efield, tab64, volt, dev):
             "reference": "FP64 direction scan on the same float32 traces (complex128 table)"}
 
 
+def envelope_scan_rate(api, tab, ev, volt, dirs, work, reps, stream):
+    """Station-unfolds/s of au_unfold_envelope_scan (peaks and their samples only, no traces)."""
+    import torch
+    api.unfold_envelope_scan(tab, ev, volt, dirs, work=work)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        api.unfold_envelope_scan(tab, ev, volt, dirs, work=work)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    su = len(dirs) * ev.n_stations
+    n = ev.n_samples
+    # 2 complex inverse FFTs per station-unfold at the 5 N log2 N convention
+    flops = su * 2 * 5 * n * int(np.log2(n))
+    return {"value": su / (ms / 1e3), "unit": "station-unfolds/s", "ms_per_call": ms, "station_unfolds": su,
+            "fft_GFLOPs_5NlogN": flops / (ms / 1e3) / 1e9}
+
+
+def reconstruction_latency(api, synth, tab64, tab32, dev, n_events=8, n_st=124, n=4096, max_iter=8):
+    """Wall time per event of the device reconstruction loop on plane-wave events
+    (124 stations on the 6 km^2 hexagonal layout, directions spread over the sky)."""
+    import torch
+    pos = synth.station_positions(n_st)
+    r = synth.rng(5, synth.STREAM_EVENTS)
+    truth = np.stack([r.uniform(5.0, 65.0, n_events), r.uniform(0.0, 360.0, n_events)], 1)
+    out = {}
+    for name, tab, prec, tin, dt in (("fp64", tab64, api.AU_PREC_FP64, api.AU_F64, np.float64),
+                                     ("fp32", tab32, api.AU_PREC_FP32, api.AU_F32, np.float32)):
+        ev = api.make_event(n_st, n, prec=prec, trace_dtype=tin)
+        work = torch.empty(api.reconstruct_workspace_bytes(tab, ev, max_iter), dtype=torch.uint8, device=dev)
+        vols = [torch.from_numpy(synth.plane_wave_traces(pos, n, z, a, cfg=5, event=i, dtype=dt)[0]).to(dev)
+                for i, (z, a) in enumerate(truth)]
+        api.reconstruct(tab, ev, vols[0], pos, max_iter=max_iter, work=work)
+        torch.cuda.synchronize()
+        passes, conv, err = [], 0, []
+        t0 = time.perf_counter()
+        for i, v in enumerate(vols):
+            rec = api.reconstruct(tab, ev, v, pos, max_iter=max_iter, work=work)
+            passes.append(len(rec.dirs))
+            conv += rec.converged
+            z, a = np.radians(rec.direction)
+            zt, at = np.radians(truth[i])
+            cosang = np.sin(z) * np.sin(zt) * np.cos(a - at) + np.cos(z) * np.cos(zt)
+            err.append(np.degrees(np.arccos(min(1.0, cosang))))
+        ms = (time.perf_counter() - t0) * 1e3 / n_events
+        out[name] = {"ms_per_event": ms, "mean_passes": float(np.mean(passes)), "converged": int(conv),
+                     "events": n_events, "max_angle_err_deg": float(np.max(err))}
+        del vols, work
+    out["workload"] = "%d plane-wave events, %d stations (hexagonal, 6 km^2) x %d samples, max %d passes" % (
+        n_events, n_st, n, max_iter)
+    return out
+
+
 def serving_benchmark(api, synth, tab32, tab64, rate_hz=2000.0, duration_s=3.0, warm_s=0.5,
                       plain_s=1.5, pool=48):
     """Open-loop Poisson stream of events (stations U{3..124}, 2048 float32
@@ -455,7 +510,20 @@ def main():
                 "station_unfolds": su1,
                 "output_GBs": su1 * 2 * n1 * 8 / (ms1 / 1e3) / 1e9}
         log("fp64 plain scan: %.3f ms/call, %.1f M station-unfolds/s" % (ms1, fp64["value"] / 1e6))
-        del out1, work
+        del out1
+        torch.cuda.empty_cache()
+        # envelope-peak timing over the same scan (two inverse FFTs per station-unfold, 6 values out)
+        fp64["envelope_scan"] = envelope_scan_rate(api, t1, ev, v1, dirs1, work, k1, stream)
+        v1f = v1.float().contiguous()
+        evf = api.make_event(s1, n1, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32)
+        workf = torch.empty(api.workspace_bytes(tab, evf, len(dirs1)), dtype=torch.uint8, device=dev)
+        fp64["envelope_scan_fp32"] = envelope_scan_rate(api, tab, evf, v1f, dirs1, workf, k1, stream)
+        log("envelope scan: fp64 %.1f M, fp32 %.1f M station-unfolds/s"
+            % (fp64["envelope_scan"]["value"] / 1e6, fp64["envelope_scan_fp32"]["value"] / 1e6))
+        del work, workf, v1f
+        fp64["reconstruction"] = reconstruction_latency(api, synth, t1, tab, dev)
+        log("reconstruction loop (124 stations x 4096): fp64 %.3f ms/event, fp32 %.3f ms/event"
+            % (fp64["reconstruction"]["fp64"]["ms_per_event"], fp64["reconstruction"]["fp32"]["ms_per_event"]))
         torch.cuda.empty_cache()
 
     # ---------------- serving -------------------------------------------

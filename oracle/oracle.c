@@ -48,6 +48,16 @@
  * set of station times repeats (a fixed point of the iteration) or after
  * max_iter directions.
  *
+ * Direction fit (the reconstruction repeats the E-field step for candidate
+ * directions; the paper states no objective).  Reading: for a candidate
+ * direction d, every station is unfolded for d and timed at its total-field
+ * envelope maximum t_s(d); the score is the timing inconsistency with a plane
+ * wave from d, chi2(d) = min over t0 of sum_s (t_s(d) dt - t0 - tau_s(d))^2
+ * with tau_s(d) = -(n(d) . x_s) / c in ns (the same plane-wave model as the
+ * triangulation); the best candidate minimises chi2 (the first on ties).
+ * Local refinement: a K x K grid around the best candidate at half the
+ * previous spacing, zenith clamped to [0, 90], azimuth wrapped to [0, 360).
+ *
  * Every pin of this file lives in tests/test_oracle_*.py (brute-force DFT,
  * Parseval, pure tones, exact node interpolation, multilinear
  * reproduction, azimuth wrap, exact rational 2x2 solve, band-pass and
@@ -534,5 +544,125 @@ int orc_reconstruct(const orc_grid* g, const double* tab, int64_t n_st, int64_t 
     free(t);
     free(e);
     free(env0);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Direction fit: timing-consistency score over candidate directions.     */
+/* ---------------------------------------------------------------------- */
+
+/* chi2[d] for station times t [n_dir][n_st] (samples at fs), dirs [n_dir][2]
+ * degrees, pos [n_st][2] metres; also power[d] = sum_s peak[d][s]^2 when
+ * peak (nullable) is given.  Two plain passes: the best t0 is the mean of
+ * the residuals, then the sum of squared deviations from it. */
+void orc_direction_objective(int64_t n_st, const double* pos, int64_t n_dir, const double* dirs,
+                             const int64_t* t, int64_t fs_hz, const double* peak, double* chi2, double* power)
+{
+    const double dt = 1e9 / (double)fs_hz;
+    for (int64_t d = 0; d < n_dir; ++d) {
+        const double zr = dirs[2 * d] * ORC_PI / 180.0, ar = dirs[2 * d + 1] * ORC_PI / 180.0;
+        const double nx = sin(zr) * cos(ar), ny = sin(zr) * sin(ar);
+        double mean = 0.0;
+        for (int64_t s = 0; s < n_st; ++s) {
+            const double tau = -(nx * pos[2 * s] + ny * pos[2 * s + 1]) / ORC_C_M_PER_NS;
+            mean += (double)t[d * n_st + s] * dt - tau;
+        }
+        mean /= (double)n_st;
+        double acc = 0.0, pw = 0.0;
+        for (int64_t s = 0; s < n_st; ++s) {
+            const double tau = -(nx * pos[2 * s] + ny * pos[2 * s + 1]) / ORC_C_M_PER_NS;
+            const double r = (double)t[d * n_st + s] * dt - tau - mean;
+            acc += r * r;
+            if (peak) pw += peak[d * n_st + s] * peak[d * n_st + s];
+        }
+        chi2[d] = acc;
+        if (power) power[d] = pw;
+    }
+}
+
+/* K x K directions around (zc, ac): zenith zc + (i - (K-1)/2) hz clamped to
+ * [0, 90] (row i), azimuth ac + (j - (K-1)/2) ha wrapped to [0, 360)
+ * (column j); dirs [K*K][2] row-major. */
+void orc_local_grid(double zc, double ac, double hz, double ha, int64_t k, double* dirs)
+{
+    const double m = 0.5 * (double)(k - 1);
+    for (int64_t i = 0; i < k; ++i) {
+        for (int64_t j = 0; j < k; ++j) {
+            double z = zc + ((double)i - m) * hz;
+            if (z < 0.0) z = 0.0;
+            if (z > 90.0) z = 90.0;
+            double a = ac + ((double)j - m) * ha;
+            a = a - 360.0 * floor(a / 360.0);
+            if (a >= 360.0) a -= 360.0;
+            dirs[2 * (i * k + j)] = z;
+            dirs[2 * (i * k + j) + 1] = a;
+        }
+    }
+}
+
+/* The fit: score the n_dir candidates, then `levels` refinements, each a
+ * k x k grid around the best so far at spacing (step_z, step_a) / 2^level.
+ * Outputs: level_dirs [levels][k*k][2]; chi2 and power [n_dir + levels*k*k]
+ * (candidates in order, coarse first); best [levels + 1] (index within its
+ * level); result [2] the best direction of the last level.  Returns 0 or a
+ * negative error. */
+int orc_direction_fit(const orc_grid* g, const double* tab, int64_t n_st, int64_t n, int64_t fs_hz,
+                      int64_t lo_hz, int64_t hi_hz, double singular_rel, const double* volt, const double* pos,
+                      int64_t n_dir, const double* dirs, int64_t levels, int64_t k, double step_z,
+                      double step_a, double* level_dirs, double* chi2, double* power, int64_t* best,
+                      double* result)
+{
+    if (n_st < 3 || n_dir < 1 || levels < 0 || k < 1) return -1;
+    const int64_t dmax = n_dir > k * k ? n_dir : k * k;
+    int64_t* units = (int64_t*)malloc(sizeof(int64_t) * 2 * (size_t)(dmax * n_st));
+    int64_t* t = (int64_t*)malloc(sizeof(int64_t) * (size_t)(dmax * n_st));
+    double* pk = (double*)malloc(sizeof(double) * (size_t)(dmax * n_st));
+    double* e = (double*)malloc(sizeof(double) * 2 * (size_t)n * (size_t)(dmax * n_st));
+    double* env = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    if (!units || !t || !pk || !e || !env) {
+        free(units); free(t); free(pk); free(e); free(env);
+        return -3;
+    }
+    int rc = 0;
+    const double* cand = dirs;
+    int64_t nc = n_dir, off = 0;
+    for (int64_t lv = 0; lv <= levels && rc == 0; ++lv) {
+        if (lv > 0) {
+            double* nd = level_dirs + 2 * (lv - 1) * k * k;
+            const double sc = ldexp(1.0, (int)-lv);
+            orc_local_grid(result[0], result[1], step_z * sc, step_a * sc, k, nd);
+            cand = nd;
+            nc = k * k;
+        }
+        for (int64_t d = 0; d < nc; ++d)
+            for (int64_t s = 0; s < n_st; ++s) {
+                units[2 * (d * n_st + s)] = d;
+                units[2 * (d * n_st + s) + 1] = s;
+            }
+        rc = orc_unfold_units(g, tab, n_st, n, fs_hz, lo_hz, hi_hz, singular_rel, volt, nc, cand, nc * n_st,
+                              units, e, NULL, NULL);
+        for (int64_t u = 0; rc == 0 && u < nc * n_st; ++u) {
+            const double* eu = e + (size_t)u * 2 * (size_t)n;
+            if ((rc = orc_envelope(n, eu, env)) || (rc = orc_envelope(n, eu + n, env + n))) break;
+            double bv = -1.0;
+            int64_t bj = 0;
+            for (int64_t j = 0; j < n; ++j) {
+                const double tot = sqrt(env[j] * env[j] + env[n + j] * env[n + j]);
+                if (tot > bv) { bv = tot; bj = j; }
+            }
+            t[u] = bj;
+            pk[u] = bv;
+        }
+        if (rc) break;
+        orc_direction_objective(n_st, pos, nc, cand, t, fs_hz, pk, chi2 + off, power + off);
+        int64_t b = 0;
+        for (int64_t d = 1; d < nc; ++d)
+            if (chi2[off + d] < chi2[off + b]) b = d;
+        best[lv] = b;
+        result[0] = cand[2 * b];
+        result[1] = cand[2 * b + 1];
+        off += nc;
+    }
+    free(units); free(t); free(pk); free(e); free(env);
     return rc;
 }

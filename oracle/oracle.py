@@ -71,6 +71,14 @@ def lib():
             L.orc_reconstruct.argtypes = [C.POINTER(OrcGrid), dp, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
                                           C.c_int64, C.c_double, dp, dp, C.c_int64, dp, ip, ip, ip]
             L.orc_reconstruct.restype = C.c_int
+            L.orc_direction_objective.argtypes = [C.c_int64, dp, C.c_int64, dp, ip, C.c_int64, dp, dp, dp]
+            L.orc_direction_objective.restype = None
+            L.orc_local_grid.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int64, dp]
+            L.orc_local_grid.restype = None
+            L.orc_direction_fit.argtypes = [C.POINTER(OrcGrid), dp, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
+                                            C.c_int64, C.c_double, dp, dp, C.c_int64, dp, C.c_int64, C.c_int64,
+                                            C.c_double, C.c_double, dp, dp, dp, ip, dp]
+            L.orc_direction_fit.restype = C.c_int
             _lib = L
     return _lib
 
@@ -215,3 +223,50 @@ def reconstruct(grid, table, volt, positions, fs_hz: int, lo_hz: int, hi_hz: int
     if rc != 0:
         raise ValueError("orc_reconstruct failed with %d" % rc)
     return dirs[:nd[0]], times[:nd[0] + 1], bool(conv[0])
+
+
+def direction_objective(positions, dirs, times, fs_hz: int, peaks=None):
+    """(chi2 [D], power [D] or None): plane-wave timing inconsistency of station times [D][S] per direction."""
+    p = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 2))
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 2))
+    t = np.ascontiguousarray(np.asarray(times, dtype=np.int64).reshape(len(d), len(p)))
+    chi2 = np.zeros(len(d))
+    pw = None
+    pk = None
+    if peaks is not None:
+        pk = np.ascontiguousarray(np.asarray(peaks, dtype=np.float64).reshape(len(d), len(p)))
+        pw = np.zeros(len(d))
+    lib().orc_direction_objective(len(p), _dp(p), len(d), _dp(d), _ip(t), fs_hz,
+                                  _dp(pk) if pk is not None else None, _dp(chi2),
+                                  _dp(pw) if pw is not None else None)
+    return chi2, pw
+
+
+def local_grid(zc: float, ac: float, hz: float, ha: float, k: int):
+    """k x k refinement directions [k*k][2] around (zc, ac)."""
+    d = np.zeros((k * k, 2))
+    lib().orc_local_grid(zc, ac, hz, ha, k, _dp(d))
+    return d
+
+
+def direction_fit(grid, table, volt, positions, dirs, fs_hz: int, lo_hz: int, hi_hz: int, levels: int = 2,
+                  k: int = 5, step=(5.0, 5.0), singular_rel: float = 1e-12):
+    """Coarse scan + local refinements; returns dict(level_dirs, chi2, power, best, result)."""
+    tb = _table128(grid, table)
+    v = np.ascontiguousarray(np.asarray(volt), dtype=np.float64)
+    p = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 2))
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 2))
+    n_st, _, n = v.shape
+    tot = len(d) + levels * k * k
+    ld = np.zeros((max(levels, 1), k * k, 2))
+    chi2 = np.zeros(tot)
+    pw = np.zeros(tot)
+    best = np.zeros(levels + 1, dtype=np.int64)
+    res = np.zeros(2)
+    g = make_grid(grid)
+    rc = lib().orc_direction_fit(C.byref(g), _dp(tb.view(np.float64)), n_st, n, fs_hz, lo_hz, hi_hz, singular_rel,
+                                 _dp(v), _dp(p), len(d), _dp(d), levels, k, float(step[0]), float(step[1]),
+                                 _dp(ld), _dp(chi2), _dp(pw), _ip(best), _dp(res))
+    if rc != 0:
+        raise ValueError("orc_direction_fit failed with %d" % rc)
+    return {"level_dirs": ld[:levels], "chi2": chi2, "power": pw, "best": best, "result": res}
