@@ -217,6 +217,37 @@ au_status au_reconstruct(const au_table* table, const au_event* ev, const void* 
                          void* stream);
 
 /*
+ * Direction fit of one event over candidate directions (the reconstruction
+ * repeats the E-field step per candidate, section 2; the paper names no
+ * objective).  Per candidate d every station is unfolded for d and timed at
+ * its total-field envelope maximum t_s(d) (as au_unfold_envelope_scan); the
+ * score is the inconsistency of those times with a plane wave from d,
+ *   chi2(d) = min over t0 of sum_s (t_s(d) dt - t0 - tau_s(d))^2   [ns^2],
+ *   tau_s(d) = -(n(d) . x_s) / c,  n(d) = (sin z cos a, sin z sin a),
+ * with dt = 1e9 / fs ns, c = 0.299792458 m/ns; also power(d) = sum_s peak_s^2.
+ * The best candidate minimises chi2 (the first on ties).  Then `levels`
+ * refinements, all on the device with no host round trip: level l scores the
+ * k x k grid around the previous best at spacing (step_zen, step_az) / 2^l,
+ * zenith zc + (i - (k-1)/2) h_z clamped to [0, 90] (row i), azimuth
+ * ac + (j - (k-1)/2) h_a wrapped to [0, 360) (column j).
+ * Inputs: d_volt [S][2][N] device; h_pos [S][2] host metres (x east, y north;
+ * finite, |x|, |y| <= 1e7); h_dirs [n_dir][2] host degrees; S >= 3,
+ * 0 <= levels <= 16, 1 <= k <= 15, steps in (0, 90] and (0, 360] when
+ * levels > 0.  Outputs (host, written before return; the call synchronises
+ * the stream; each nullable except h_result): h_level_dirs
+ * [levels][k*k][2]; h_chi2, h_power [n_dir + levels*k*k] (coarse candidates
+ * first, then each level); h_best [levels+1] (index within its level);
+ * h_result [2] the best direction of the last level.
+ * Workspace: au_direction_fit_workspace_bytes, or NULL for the stream's pool.
+ */
+au_status au_direction_fit_workspace_bytes(const au_table* table, const au_event* ev, int32_t n_dir,
+                                           int32_t levels, int32_t k, uint64_t* bytes);
+au_status au_direction_fit(const au_table* table, const au_event* ev, const void* d_volt, const double* h_pos,
+                           int32_t n_dir, const double* h_dirs, int32_t levels, int32_t k, double step_zen,
+                           double step_az, double* h_level_dirs, double* h_chi2, double* h_power,
+                           int32_t* h_best, double* h_result, void* d_work, uint64_t work_bytes, void* stream);
+
+/*
  * Interpolated pattern H[c][p](f_k; zen, az) at every in-band bin of ev, for
  * n_dir directions (section 3: linear interpolation between nodes).  Output
  * d_resp [n_dir][n_band][2][2] complex (interleaved re, im) of the precision's

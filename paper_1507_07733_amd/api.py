@@ -110,6 +110,12 @@ _SIG = {
     "au_unfold_envelope_scan": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.c_int32, C.POINTER(C.c_double),
                                             _VP, _VP, _VP, _VP, C.c_uint64, _VP, _VP]),
     "au_pattern_response": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.POINTER(C.c_double), _VP, _VP]),
+    "au_direction_fit_workspace_bytes": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.c_int32, C.c_int32,
+                                                     C.POINTER(C.c_uint64)]),
+    "au_direction_fit": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.POINTER(C.c_double), C.c_int32,
+                                     C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_double), _VP, C.c_uint64, _VP]),
     "au_reconstruct_workspace_bytes": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.POINTER(C.c_uint64)]),
     "au_reconstruct": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.POINTER(C.c_double), C.c_int32,
                                    C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -367,6 +373,40 @@ def reconstruct(table: Table, ev: AuEvent, volt, positions, max_iter: int = 8, e
                                 _ptr(out), _ptr(peak), wp, wb, _stream_handle(stream)))
     k = nd.value
     return Reconstruction(dirs[:k], times[:k + 1], bool(conv.value), out, peak)
+
+
+def direction_fit_workspace_bytes(table: Table, ev: AuEvent, n_dir: int, levels: int, k: int) -> int:
+    n = C.c_uint64()
+    _check(lib().au_direction_fit_workspace_bytes(table.handle, C.byref(ev), int(n_dir), int(levels), int(k),
+                                                  C.byref(n)))
+    return n.value
+
+
+def direction_fit(table: Table, ev: AuEvent, volt, positions, dirs, levels: int = 3, k: int = 5,
+                  step=(5.0, 5.0), work=None, stream=None):
+    """Coarse scan + device refinements; see au_direction_fit.
+
+    Returns dict(result [2], best [levels+1], chi2, power [n_dir + levels*k*k], level_dirs [levels][k*k][2]).
+    """
+    _check_traces(volt, ev)
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 2))
+    if len(pos) != ev.n_stations:
+        raise ValueError("positions must have shape [S][2]")
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 2))
+    tot = len(d) + levels * k * k
+    ld = np.zeros((max(levels, 1), k * k, 2))
+    chi2 = np.zeros(tot)
+    pw = np.zeros(tot)
+    best = np.zeros(levels + 1, dtype=np.int32)
+    res = np.zeros(2)
+    dp = C.POINTER(C.c_double)
+    wp, wb = _work(work)
+    _check(lib().au_direction_fit(table.handle, C.byref(ev), _ptr(volt), pos.ctypes.data_as(dp), len(d),
+                                  d.ctypes.data_as(dp), int(levels), int(k), float(step[0]), float(step[1]),
+                                  ld.ctypes.data_as(dp), chi2.ctypes.data_as(dp), pw.ctypes.data_as(dp),
+                                  best.ctypes.data_as(C.POINTER(C.c_int32)), res.ctypes.data_as(dp), wp, wb,
+                                  _stream_handle(stream)))
+    return {"result": res, "best": best, "chi2": chi2, "power": pw, "level_dirs": ld[:levels]}
 
 
 def pattern_response(table: Table, ev: AuEvent, dirs, device=None, stream=None):

@@ -2399,3 +2399,255 @@ extern "C" au_status au_reconstruct(const au_table* tb, const au_event* ev, cons
     if (state[3]) return fail(AU_EINVAL, "degenerate station geometry (collinear or coincident stations)");
     return AU_OK;
 }
+
+// ---------------------------------------------------------------------------
+// direction fit: plane-wave timing-consistency score over candidate
+// directions, device argmin and local refinement grids, no host round trip
+// between levels
+// ---------------------------------------------------------------------------
+
+// Score of every candidate (one block each): r_s = t_s dt - tau_s with
+// tau_s = -(n . x_s) / c, chi2 = sum_s (r_s - mean r)^2 (ns^2), and the summed
+// squared total-field envelope peaks.  t_s and the peaks are component 2 of
+// the envelope scan's [D][S][3] outputs.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dir_score(int S, const double* __restrict__ pos,
+                                                       const double* __restrict__ dirs, const int* __restrict__ arg,
+                                                       const T* __restrict__ peak, double dt_ns,
+                                                       double* __restrict__ chi2, double* __restrict__ power)
+{
+    const int d = blockIdx.x;
+    const double zr = dirs[2 * d] * (M_PI / 180.0), ar = dirs[2 * d + 1] * (M_PI / 180.0);
+    const double nx = sin(zr) * cos(ar), ny = sin(zr) * sin(ar);
+    const int* __restrict__ t = arg + (int64_t)d * S * 3;
+    double m[1] = {0.0};
+    for (int s = threadIdx.x; s < S; s += kBlock)
+        m[0] += (double)t[3 * s + 2] * dt_ns + (nx * pos[2 * s] + ny * pos[2 * s + 1]) / kCMPerNs;
+    block_sum(m);
+    const double mean = m[0] / (double)S;
+    double acc[2] = {0.0, 0.0};
+    for (int s = threadIdx.x; s < S; s += kBlock) {
+        const double r = (double)t[3 * s + 2] * dt_ns + (nx * pos[2 * s] + ny * pos[2 * s + 1]) / kCMPerNs - mean;
+        const double p = (double)peak[((int64_t)d * S + s) * 3 + 2];
+        acc[0] += r * r;
+        acc[1] += p * p;
+    }
+    block_sum(acc);
+    if (threadIdx.x == 0) {
+        chi2[d] = acc[0];
+        power[d] = acc[1];
+    }
+}
+
+// Best candidate of a level (smallest chi2, the first on ties) into best and
+// result; then, if next is non-null, the k x k grid of the next level around
+// it: zenith zc + (i - (k-1)/2) hz clamped to [0, 90], azimuth
+// ac + (j - (k-1)/2) ha wrapped to [0, 360), every operation rounded on its
+// own so the grid is exactly the plain double evaluation.
+__global__ __launch_bounds__(kBlock) void k_dir_best(int nc, const double* __restrict__ chi2,
+                                                      const double* __restrict__ cand, int* __restrict__ best,
+                                                      double* __restrict__ result, double hz, double ha, int k,
+                                                      double* __restrict__ next)
+{
+#pragma clang fp contract(off)
+    __shared__ double centre[2];
+    double v = -INFINITY;
+    int bi = 0;
+    for (int d = threadIdx.x; d < nc; d += kBlock) amax_merge(v, bi, -chi2[d], d);
+    block_argmax(v, bi);
+    if (threadIdx.x == 0) {
+        *best = bi;
+        centre[0] = result[0] = cand[2 * bi];
+        centre[1] = result[1] = cand[2 * bi + 1];
+    }
+    __syncthreads();
+    if (next == nullptr) return;
+    const double m = 0.5 * (double)(k - 1);
+    for (int q = threadIdx.x; q < k * k; q += kBlock) {
+        const int i = q / k, j = q - (q / k) * k;
+        double z = centre[0] + ((double)i - m) * hz;
+        z = z < 0.0 ? 0.0 : (z > 90.0 ? 90.0 : z);
+        double a = centre[1] + ((double)j - m) * ha;
+        a = a - 360.0 * floor(a / 360.0);
+        if (a >= 360.0) a -= 360.0;
+        next[2 * q] = z;
+        next[2 * q + 1] = a;
+    }
+}
+
+namespace {
+
+constexpr int kMaxFitLevels = 16;
+constexpr int kMaxFitK = 15;
+
+struct FitLayout {
+    size_t x, m, dirs, chi2, power, best, result, pos, peak, arg, total;
+    int64_t n_cand, d_max;
+};
+
+FitLayout fit_layout(const EvParams& p, int prec, int n_dir, int levels, int k)
+{
+    FitLayout f;
+    f.n_cand = (int64_t)n_dir + (int64_t)levels * k * k;
+    f.d_max = std::max<int64_t>(n_dir, (int64_t)k * k);
+    const size_t tsz = prec == AU_PREC_FP64 ? sizeof(double) : sizeof(float);
+    const WsLayout w = ws_layout(p, prec, (int)f.d_max);
+    f.x = w.x;
+    f.m = w.m;
+    f.dirs = align256((size_t)f.n_cand * 2 * sizeof(double));
+    f.chi2 = align256((size_t)f.n_cand * sizeof(double));
+    f.power = f.chi2;
+    f.best = align256((size_t)(levels + 1) * sizeof(int32_t));
+    f.result = 256;
+    f.pos = align256((size_t)p.S * 2 * sizeof(double));
+    f.peak = align256((size_t)f.d_max * p.S * 3 * tsz);
+    f.arg = align256((size_t)f.d_max * p.S * 3 * sizeof(int32_t));
+    f.total = f.x + f.m + f.dirs + f.chi2 + f.power + f.best + f.result + f.pos + f.peak + f.arg;
+    return f;
+}
+
+au_status check_fit(const au_table* tb, const au_event* ev, int32_t n_dir, int32_t levels, int32_t k,
+                    double step_zen, double step_az, EvParams* p)
+{
+    au_status s = check_event(tb, ev, p);
+    if (s != AU_OK) return s;
+    if (p->S < 3) return fail(AU_EINVAL, "the direction fit needs at least 3 stations");
+    if (n_dir < 1) return fail(AU_EINVAL, "n_dir must be >= 1");
+    if (levels < 0 || levels > kMaxFitLevels) return fail(AU_EINVAL, "levels must be in [0, 16]");
+    if (k < 1 || k > kMaxFitK) return fail(AU_EINVAL, "k must be in [1, 15]");
+    if (levels > 0 && (!(step_zen > 0.0) || !(step_az > 0.0) || !std::isfinite(step_zen) ||
+                       !std::isfinite(step_az) || step_zen > 90.0 || step_az > 360.0))
+        return fail(AU_EINVAL, "steps must be in (0, 90] and (0, 360]");
+    const int64_t units = std::max<int64_t>(n_dir, (int64_t)k * k) * ((p->S + kStationsPerUnit - 1) / kStationsPerUnit);
+    if (units > (int64_t)0x7fffffff) return fail(AU_EINVAL, "too many work units");
+    return AU_OK;
+}
+
+}  // namespace
+
+template <typename T>
+static au_status run_fit(const au_table* tb, const au_event* ev, const EvParams& p, const void* d_volt,
+                         const double* h_pos, int n_dir, const double* h_dirs, int levels, int k, double step_zen,
+                         double step_az, void* d_work, hipStream_t st, double* h_level_dirs, double* h_chi2,
+                         double* h_power, int32_t* h_best, double* h_result)
+{
+    const FitLayout f = fit_layout(p, ev->prec, n_dir, levels, k);
+    unsigned char* q = (unsigned char*)d_work;
+    XBin<T>* X = (XBin<T>*)q;
+    MBin<T>* M = (MBin<T>*)(q += f.x);
+    double* dirs = (double*)(q += f.m);
+    double* chi2 = (double*)(q += f.dirs);
+    double* power = (double*)(q += f.chi2);
+    int* best = (int*)(q += f.power);
+    double* result = (double*)(q += f.best);
+    double* pos = (double*)(q += f.result);
+    T* peak = (T*)(q += f.pos);
+    int* arg = (int*)(q += f.peak);
+    HIP_TRY(hipMemcpyAsync(dirs, h_dirs, sizeof(double) * 2 * n_dir, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(pos, h_pos, sizeof(double) * 2 * p.S, hipMemcpyHostToDevice, st));
+    EvDesc ev0{};
+    ev0.S = p.S;
+    ev0.N = p.N;
+    ev0.k_lo = p.k_lo;
+    ev0.nb = p.nb;
+    const C2<T>* tw = twiddles<T>(tb->device);
+    if (tw == nullptr) return fail(AU_EDEVICE, "twiddle tables missing on this device");
+    hipError_t e = ev->trace_dtype == AU_F64
+                       ? launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, X, tw)
+                       : launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
+    const double dt_ns = 1e9 / (double)ev->fs_hz;
+    const int chunks = (p.S + kStationsPerUnit - 1) / kStationsPerUnit;
+    int64_t off = 0;
+    for (int lv = 0; lv <= levels; ++lv) {
+        const int nc = lv == 0 ? n_dir : k * k;
+        double* cand = dirs + 2 * off;
+        ev0.D = nc;
+        if (tb->dtype == AU_F64)
+            launch_coef<double, T>(st, tb, ev0, nullptr, nullptr, nc, cand, 0, 0, ev->fs_hz, ev->fallback_rel,
+                                   ev->singular_rel, M, nullptr);
+        else
+            launch_coef<float, T>(st, tb, ev0, nullptr, nullptr, nc, cand, 0, 0, ev->fs_hz, ev->fallback_rel,
+                                  ev->singular_rel, M, nullptr);
+        switch (p.N) {
+#define X_(NN)                                                                                       \
+    case NN:                                                                                         \
+        e = launch_env_n<T, NN>(st, ev0, nc * chunks, X, M, (T*)nullptr, peak, arg, tw, nullptr); \
+        break;
+            AU_FOR_EACH_N(X_)
+#undef X_
+            default: e = hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return fail(AU_EDEVICE, std::string("direction fit scan: ") + hipGetErrorString(e));
+        hipLaunchKernelGGL(k_dir_score<T>, dim3(nc), dim3(kBlock), 0, st, p.S, (const double*)pos,
+                           (const double*)cand, (const int*)arg, (const T*)peak, dt_ns, chi2 + off, power + off);
+        const double sc = std::ldexp(1.0, -(lv + 1));
+        hipLaunchKernelGGL(k_dir_best, dim3(1), dim3(kBlock), 0, st, nc, (const double*)(chi2 + off),
+                           (const double*)cand, best + lv, result, step_zen * sc, step_az * sc, k,
+                           lv < levels ? dirs + 2 * (off + nc) : nullptr);
+        e = hipGetLastError();
+        if (e != hipSuccess) return fail(AU_EDEVICE, std::string("direction fit score: ") + hipGetErrorString(e));
+        off += nc;
+    }
+    if (levels > 0 && h_level_dirs)
+        HIP_TRY(hipMemcpyAsync(h_level_dirs, dirs + 2 * n_dir, sizeof(double) * 2 * (size_t)levels * k * k,
+                               hipMemcpyDeviceToHost, st));
+    if (h_chi2) HIP_TRY(hipMemcpyAsync(h_chi2, chi2, sizeof(double) * f.n_cand, hipMemcpyDeviceToHost, st));
+    if (h_power) HIP_TRY(hipMemcpyAsync(h_power, power, sizeof(double) * f.n_cand, hipMemcpyDeviceToHost, st));
+    if (h_best) HIP_TRY(hipMemcpyAsync(h_best, best, sizeof(int32_t) * (levels + 1), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h_result, result, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return AU_OK;
+}
+
+extern "C" au_status au_direction_fit_workspace_bytes(const au_table* tb, const au_event* ev, int32_t n_dir,
+                                                      int32_t levels, int32_t k, uint64_t* bytes)
+{
+    if (!bytes) return fail(AU_EINVAL, "null argument");
+    EvParams p;
+    au_status s = check_fit(tb, ev, n_dir, levels, k, 1.0, 1.0, &p);
+    if (s != AU_OK) return s;
+    *bytes = fit_layout(p, ev->prec, n_dir, levels, k).total;
+    return AU_OK;
+}
+
+extern "C" au_status au_direction_fit(const au_table* tb, const au_event* ev, const void* d_volt, const double* h_pos,
+                                      int32_t n_dir, const double* h_dirs, int32_t levels, int32_t k,
+                                      double step_zen, double step_az, double* h_level_dirs, double* h_chi2,
+                                      double* h_power, int32_t* h_best, double* h_result, void* d_work,
+                                      uint64_t work_bytes, void* stream)
+{
+    EvParams p;
+    au_status s = check_fit(tb, ev, n_dir, levels, k, step_zen, step_az, &p);
+    if (s != AU_OK) return s;
+    if (!d_volt || !h_pos || !h_dirs || !h_result) return fail(AU_EINVAL, "null argument");
+    if (!dirs_finite(h_dirs, n_dir)) return fail(AU_EINVAL, "directions must be finite");
+    for (int64_t i = 0; i < 2 * (int64_t)p.S; ++i)
+        if (!std::isfinite(h_pos[i]) || std::fabs(h_pos[i]) > 1e7)
+            return fail(AU_EINVAL, "station positions must be finite and within 1e7 m");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != tb->device) return fail(AU_EINVAL, "table lives on another device");
+    const FitLayout f = fit_layout(p, ev->prec, n_dir, levels, k);
+    hipStream_t st = (hipStream_t)stream;
+    void* work = d_work;
+    bool pooled = false;
+    if (work == nullptr) {
+        hipError_t e = hipMallocAsync(&work, f.total, st);
+        if (e != hipSuccess) return fail(AU_ENOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        pooled = true;
+    } else if (work_bytes < f.total) {
+        return fail(AU_ENOMEM, "workspace smaller than au_direction_fit_workspace_bytes");
+    }
+    s = ev->prec == AU_PREC_FP64
+            ? run_fit<double>(tb, ev, p, d_volt, h_pos, n_dir, h_dirs, levels, k, step_zen, step_az, work, st,
+                              h_level_dirs, h_chi2, h_power, h_best, h_result)
+            : run_fit<float>(tb, ev, p, d_volt, h_pos, n_dir, h_dirs, levels, k, step_zen, step_az, work, st,
+                             h_level_dirs, h_chi2, h_power, h_best, h_result);
+    if (pooled) {
+        hipError_t e = hipFreeAsync(work, st);
+        if (s == AU_OK && e != hipSuccess)
+            return fail(AU_EDEVICE, std::string("hipFreeAsync: ") + hipGetErrorString(e));
+    }
+    return s;
+}
