@@ -257,6 +257,18 @@ au_status au_pattern_response(const au_table* table, const au_event* ev, int32_t
                               const double* h_dirs, void* d_resp, void* stream);
 
 /*
+ * As au_pattern_response, with each of the three interpolation weights
+ * (fractional node positions in frequency, zenith and azimuth) rounded to the
+ * nearest multiple of 2^-weight_bits (ties to even) before interpolating:
+ * the fixed-point weights of a hardware texture filter (section 3 interpolates
+ * with texture hardware; NVIDIA documents 8 fractional bits, weight_bits = 8).
+ * gfx950 has no texture sampler, so this models its weights in software to
+ * measure the precision cost.  1 <= weight_bits <= 30.
+ */
+au_status au_pattern_response_quantized(const au_table* table, const au_event* ev, int32_t n_dir,
+                                        const double* h_dirs, int32_t weight_bits, void* d_resp, void* stream);
+
+/*
  * Batched unfolding of many events of uneven size (stations x directions x
  * events) in one launch per trace length, optionally replayed from a captured
  * HIP graph.  Motivation: the paper's GPU time was dominated by host<->device

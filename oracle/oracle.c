@@ -231,6 +231,29 @@ int orc_pattern_at_bin(const orc_grid* g, const double* tab, int64_t k, int64_t 
     return 0;
 }
 
+/*
+ * As orc_pattern_at_bin, with the three interpolation weights rounded to the
+ * nearest multiple of 2^-weight_bits (ties to even): the fixed-point weights
+ * of a texture filter (section 3 interpolates with texture hardware).
+ */
+int orc_pattern_at_bin_quantized(const orc_grid* g, const double* tab, int64_t k, int64_t n, int64_t fs_hz,
+                                 double zen, double az, int weight_bits, double* h)
+{
+    int64_t ifr, iz, ia, ja;
+    double tf, tz, ta;
+    if (freq_cell(g, k, n, fs_hz, &ifr, &tf)) return -1;
+    zen_cell(g, zen, &iz, &tz);
+    az_cell(g, az, &ia, &ja, &ta);
+    const double q = ldexp(1.0, weight_bits);
+    tf = nearbyint(tf * q) / q;
+    tz = nearbyint(tz * q) / q;
+    ta = nearbyint(ta * q) / q;
+    for (int c = 0; c < 2; ++c)
+        for (int p = 0; p < 2; ++p)
+            trilinear(g, tab, c, p, ifr, tf, iz, tz, ia, ja, ta, h + 2 * (c * 2 + p));
+    return 0;
+}
+
 /* ---------------------------------------------------------------------- */
 /* 2x2 complex solve by Cramer's rule.                                     */
 /* ---------------------------------------------------------------------- */

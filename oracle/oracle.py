@@ -56,6 +56,9 @@ def lib():
             L.orc_pattern_at_bin.argtypes = [C.POINTER(OrcGrid), dp, C.c_int64, C.c_int64, C.c_int64,
                                              C.c_double, C.c_double, dp]
             L.orc_pattern_at_bin.restype = C.c_int
+            L.orc_pattern_at_bin_quantized.argtypes = [C.POINTER(OrcGrid), dp, C.c_int64, C.c_int64, C.c_int64,
+                                                       C.c_double, C.c_double, C.c_int, dp]
+            L.orc_pattern_at_bin_quantized.restype = C.c_int
             L.orc_solve2.argtypes = [dp, dp, C.c_double, dp]
             L.orc_solve2.restype = C.c_int
             L.orc_unfold_units.argtypes = [C.POINTER(OrcGrid), dp, C.c_int64, C.c_int64, C.c_int64,
@@ -123,6 +126,17 @@ def pattern_at_bin(grid, table, k: int, n: int, fs_hz: int, zen: float, az: floa
     g = make_grid(grid)
     h = np.zeros(8)
     if lib().orc_pattern_at_bin(C.byref(g), _dp(t.view(np.float64)), k, n, fs_hz, zen, az, _dp(h)) != 0:
+        raise ValueError("bin outside the table's frequency range")
+    return (h[0::2] + 1j * h[1::2]).reshape(2, 2)
+
+
+def pattern_at_bin_quantized(grid, table, k: int, n: int, fs_hz: int, zen: float, az: float, weight_bits: int):
+    """pattern_at_bin with interpolation weights rounded to weight_bits fractional bits."""
+    t = _table128(grid, table)
+    g = make_grid(grid)
+    h = np.zeros(8)
+    if lib().orc_pattern_at_bin_quantized(C.byref(g), _dp(t.view(np.float64)), k, n, fs_hz, zen, az,
+                                          int(weight_bits), _dp(h)) != 0:
         raise ValueError("bin outside the table's frequency range")
     return (h[0::2] + 1j * h[1::2]).reshape(2, 2)
 

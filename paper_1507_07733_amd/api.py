@@ -110,6 +110,8 @@ _SIG = {
     "au_unfold_envelope_scan": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.c_int32, C.POINTER(C.c_double),
                                             _VP, _VP, _VP, _VP, C.c_uint64, _VP, _VP]),
     "au_pattern_response": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.POINTER(C.c_double), _VP, _VP]),
+    "au_pattern_response_quantized": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.POINTER(C.c_double),
+                                                  C.c_int32, _VP, _VP]),
     "au_direction_fit_workspace_bytes": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.c_int32, C.c_int32,
                                                      C.POINTER(C.c_uint64)]),
     "au_direction_fit": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.POINTER(C.c_double), C.c_int32,
@@ -409,16 +411,22 @@ def direction_fit(table: Table, ev: AuEvent, volt, positions, dirs, levels: int 
     return {"result": res, "best": best, "chi2": chi2, "power": pw, "level_dirs": ld[:levels]}
 
 
-def pattern_response(table: Table, ev: AuEvent, dirs, device=None, stream=None):
-    """Interpolated H at every in-band bin: complex tensor [D][n_band][2][2]."""
+def pattern_response(table: Table, ev: AuEvent, dirs, device=None, stream=None, weight_bits: int = 0):
+    """Interpolated H at every in-band bin: complex tensor [D][n_band][2][2].
+
+    weight_bits > 0 rounds the interpolation weights to that many fractional
+    bits (au_pattern_response_quantized)."""
     import torch
     d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 2))
     _, nb = band_bins(ev)
     rd = out_dtype(ev.prec)
     out = torch.zeros((len(d), nb, 2, 2, 2), dtype=rd, device=device or "cuda")
-    _check(lib().au_pattern_response(table.handle, C.byref(ev), len(d),
-                                     d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(out),
-                                     _stream_handle(stream)))
+    dp = d.ctypes.data_as(C.POINTER(C.c_double))
+    if weight_bits:
+        _check(lib().au_pattern_response_quantized(table.handle, C.byref(ev), len(d), dp, int(weight_bits),
+                                                   _ptr(out), _stream_handle(stream)))
+    else:
+        _check(lib().au_pattern_response(table.handle, C.byref(ev), len(d), dp, _ptr(out), _stream_handle(stream)))
     return torch.view_as_complex(out)
 
 

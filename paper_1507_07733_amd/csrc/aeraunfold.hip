@@ -221,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
                                                  const double* __restrict__ dirs, double zen1,
                                                  double az1, int64_t fs, double fallback_rel,
                                                  double singular_rel, MBin<T>* __restrict__ M,
-                                                 unsigned long long* __restrict__ counts)
+                                                 unsigned long long* __restrict__ counts, double wq)
 {
     __shared__ unsigned int cnt[2];
     if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
@@ -241,6 +241,12 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
     int iz, ia, ja;
     double tz, ta;
     angle_cells(gd, zen, az, iz, tz, ia, ja, ta);
+    if constexpr (RESP) {
+        if (wq > 0.0) {  // interpolation weights rounded to multiples of 1 / wq
+            tz = rint(tz * wq) / wq;
+            ta = rint(ta * wq) / wq;
+        }
+    }
     const T inv_n = (T)(1.0 / (double)ev.N);
     unsigned int n_fb = 0, n_sg = 0;
     MBin<T>* out = M + ev.m_off + (int64_t)d * ev.nb;
@@ -248,6 +254,9 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
         int ifr;
         double tf;
         freq_cell(gd, (int64_t)(ev.k_lo + j), ev.N, fs, ifr, tf);
+        if constexpr (RESP) {
+            if (wq > 0.0) tf = rint(tf * wq) / wq;
+        }
         C2<T> h[4];
         interp4<Tt, T>(nodes, gd, ifr, (T)tf, iz, (T)tz, ia, ja, (T)ta, h);
         MBin<T> m;
@@ -1146,7 +1155,7 @@ static void launch_coef(hipStream_t st, const au_table* tb, const EvDesc& ev0, c
 {
     hipLaunchKernelGGL((k_coef<Tt, T, false>), dim3(n_units), dim3(kBlock), 0, st,
                        (const C2<Tt>*)tb->d_nodes, tb->g, ev0, evs, units, dirs, zen, az, fs, fb, sg,
-                       M, counts);
+                       M, counts, 0.0);
 }
 
 template <typename T>
@@ -1254,8 +1263,8 @@ extern "C" au_status au_unfold_direction_scan(const au_table* tb, const au_event
                          stream, d_counts);
 }
 
-extern "C" au_status au_pattern_response(const au_table* tb, const au_event* ev, int32_t n_dir,
-                                         const double* h_dirs, void* d_resp, void* stream)
+static au_status pattern_response(const au_table* tb, const au_event* ev, int32_t n_dir, const double* h_dirs,
+                                  void* d_resp, void* stream, double wq)
 {
     EvParams p;
     au_status s = check_event(tb, ev, &p);
@@ -1278,7 +1287,7 @@ extern "C" au_status au_pattern_response(const au_table* tb, const au_event* ev,
 #define RESP_(TT, T)                                                                        \
     hipLaunchKernelGGL((k_coef<TT, T, true>), dim3(n_dir), dim3(kBlock), 0, st,            \
                        (const C2<TT>*)tb->d_nodes, tb->g, ev0, nullptr, nullptr, dirs, 0.0, 0.0, \
-                       ev->fs_hz, 0.0, 0.0, (MBin<T>*)d_resp, nullptr)
+                       ev->fs_hz, 0.0, 0.0, (MBin<T>*)d_resp, nullptr, wq)
     if (f64)
         RESP_(double, double);
     else if (tb->dtype == AU_F64)
@@ -1290,6 +1299,20 @@ extern "C" au_status au_pattern_response(const au_table* tb, const au_event* ev,
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_coef(resp): ") + hipGetErrorString(e));
     HIP_TRY(hipFreeAsync(dirs, st));
     return AU_OK;
+}
+
+extern "C" au_status au_pattern_response(const au_table* tb, const au_event* ev, int32_t n_dir,
+                                         const double* h_dirs, void* d_resp, void* stream)
+{
+    return pattern_response(tb, ev, n_dir, h_dirs, d_resp, stream, 0.0);
+}
+
+extern "C" au_status au_pattern_response_quantized(const au_table* tb, const au_event* ev, int32_t n_dir,
+                                                   const double* h_dirs, int32_t weight_bits, void* d_resp,
+                                                   void* stream)
+{
+    if (weight_bits < 1 || weight_bits > 30) return fail(AU_EINVAL, "weight_bits must be in [1, 30]");
+    return pattern_response(tb, ev, n_dir, h_dirs, d_resp, stream, std::ldexp(1.0, weight_bits));
 }
 
 // ---------------------------------------------------------------------------

@@ -57,6 +57,7 @@ def test_validation_without_device(lib):
     assert lib.au_direction_fit_workspace_bytes(None, C.byref(ev), 4, 1, 3, C.byref(n)) == api.AU_EINVAL
     assert lib.au_direction_fit(None, C.byref(ev), None, None, 4, None, 1, 3, 1.0, 1.0, None, None, None, None,
                                 None, None, 0, None) == api.AU_EINVAL
+    assert lib.au_pattern_response_quantized(None, C.byref(ev), 1, None, 8, None, None) == api.AU_EINVAL
     assert lib.au_free_pattern_table(None) == api.AU_OK
 
 

@@ -173,6 +173,39 @@ def test_pattern_response_fp64_and_fp32_bound(api, coarse, coarse_c64):
         print("fp32 interp: worst err / bound = %.3f" % worst)
 
 
+def test_pattern_response_texture_weights(api, coarse, coarse_c64):
+    """Interpolation with weights rounded to 8 fractional bits (a texture filter's fixed point): GPU
+    equals the oracle's quantized interpolation (FP64 to rounding, FP32 within the FP32 bound), and
+    the precision cost against exact weights is reported."""
+    r = np.random.default_rng(11)
+    dirs = np.stack([r.uniform(0, 89.9, 24), r.uniform(0, 360, 24)], 1)
+    n = 2048
+    rel_cost = []
+    for prec, (t, tab) in ((api.AU_PREC_FP64, coarse), (api.AU_PREC_FP32, coarse_c64)):
+        ev = api.make_event(4, n, prec=prec)
+        say("pattern_response_quantized prec", prec)
+        hq = api.pattern_response(tab, ev, dirs, weight_bits=8).cpu().numpy()
+        k_lo, nb = api.band_bins(ev)
+        t128 = t.astype(np.complex128)
+        for di, (z, a) in enumerate(dirs):
+            for j in range(0, nb, 5):
+                k = k_lo + j
+                ref = O.pattern_at_bin_quantized(G, t128, k, n, S.FS_HZ, z, a, 8)
+                err = np.max(np.abs(hq[di, j] - ref))
+                cm = corner_max(G, t, k, n, z, a)
+                if prec == api.AU_PREC_FP64:
+                    assert err <= 8e-16 * cm
+                    exact = O.pattern_at_bin(G, t128, k, n, S.FS_HZ, z, a)
+                    big = np.abs(exact) > 0.1 * cm
+                    rel_cost.extend((np.abs(ref - exact)[big] / np.abs(exact)[big]).tolist())
+                else:
+                    assert err <= 42 * 2.0 ** -24 * cm, (di, j, err)
+    rel_cost = np.array(rel_cost)
+    print("8-bit weights vs exact: median %.2e, p99 %.2e, max %.2e relative (entries above 10%% of the corner max)"
+          % (np.median(rel_cost), np.percentile(rel_cost, 99), rel_cost.max()))
+    assert rel_cost.max() < 0.05
+
+
 @pytest.mark.parametrize("flags", [0, 1, 2, 3, 4, 6, 7])
 def test_batch_plan_uneven_events(api, coarse, flags):
     import torch

@@ -101,3 +101,49 @@ def test_bin_outside_table_rejected(table):
     small = S.Grid(40, 19, 72, 0, 1_000_000, 0.0, 5.0, 0.0, 5.0)      # 0..39 MHz only
     with pytest.raises(ValueError):
         O.pattern_at_bin(small, np.zeros(small.shape, complex), 800, 2048, FS, 10.0, 10.0)
+
+
+# ---- texture-filter weights (interpolation weights rounded to fixed point) ----
+
+def test_quantized_fine_limit_and_nodes(table):
+    """30 fractional bits reproduce the exact interpolation; nodes stay exact at any precision."""
+    r = np.random.default_rng(3)
+    for _ in range(20):
+        k = int(r.integers(300, 900))
+        z, a = r.uniform(0, 90), r.uniform(0, 360)
+        h = O.pattern_at_bin(G, table, k, 2048, S.FS_HZ, z, a)
+        hq = O.pattern_at_bin_quantized(G, table, k, 2048, S.FS_HZ, z, a, 30)
+        assert np.max(np.abs(hq - h)) <= 1e-8 * np.max(np.abs(table))
+    # bin 512 of 2048 at 200 MHz is 50 MHz, a frequency node; zenith and azimuth on nodes
+    for b in (1, 4, 8):
+        hq = O.pattern_at_bin_quantized(G, table, 512, 2048, S.FS_HZ, 35.0, 120.0, b)
+        assert np.array_equal(hq, table[:, :, 50, 7, 24])
+
+
+def test_quantized_one_bit_is_midpoint(table):
+    """1 fractional bit: weight 0.3 becomes 0.5, weight 0.2 becomes 0; the value is a two-node mean."""
+    # frequency and zenith on nodes (50 MHz, 35 deg); azimuth 120 + 0.3 * 5 deg lies between nodes 24 and 25
+    hq = O.pattern_at_bin_quantized(G, table, 512, 2048, S.FS_HZ, 35.0, 121.5, 1)
+    assert np.allclose(hq, 0.5 * (table[:, :, 50, 7, 24] + table[:, :, 50, 7, 25]), rtol=1e-15, atol=0)
+    hq = O.pattern_at_bin_quantized(G, table, 512, 2048, S.FS_HZ, 35.0, 121.0, 1)
+    assert np.array_equal(hq, table[:, :, 50, 7, 24])
+
+
+def test_quantized_error_bound(table):
+    """Moving one weight by d moves a trilinear value by at most d times the largest node difference
+    along that axis in the cell; 8 bits give d <= 2^-9 per axis."""
+    r = np.random.default_rng(4)
+    n, fs = 2048, S.FS_HZ
+    for _ in range(60):
+        k = int(r.integers(300, 900))
+        z, a = r.uniform(0, 89.9), r.uniform(0, 360)
+        h = O.pattern_at_bin(G, table, k, n, fs, z, a)
+        hq = O.pattern_at_bin_quantized(G, table, k, n, fs, z, a, 8)
+        fpos = k * fs / n / G.df_hz
+        i_f, i_z, i_a = int(fpos), int(z // G.dzen_deg), int(a // G.daz_deg)
+        cell = table[:, :, i_f:i_f + 2, i_z:i_z + 2][..., [i_a, (i_a + 1) % G.n_az]]   # [2][2][2f][2z][2a]
+        bound = 0.0
+        for ax in (2, 3, 4):
+            diff = np.abs(np.diff(cell, axis=ax))
+            bound += 2.0 ** -9 * diff.max()
+        assert np.max(np.abs(hq - h)) <= bound * (1 + 1e-9) + 1e-15
