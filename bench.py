@@ -147,7 +147,8 @@ def fp32_error_report(api, plan, specs, efield, tab64, volt, dev):
     of their direction (from au_pattern_response in FP64)."""
     import torch
     buckets = {i: [] for i in range(len(KAPPA_EDGES) - 1)}
-    worst = 0.0
+    sbuckets = {i: [] for i in range(len(KAPPA_EDGES) - 1)}
+    worst = worst_s = 0.0
     n_tr = 0
     for e, (s, n, dirs) in enumerate(specs):
         ev64 = api.make_event(s, n, prec=api.AU_PREC_FP64, trace_dtype=api.AU_F32)
@@ -155,18 +156,24 @@ def fp32_error_report(api, plan, specs, efield, tab64, volt, dev):
         v = volt[o:o + s * 2 * n].view(s, 2, n)
         e64 = api.unfold_direction_scan(tab64, ev64, v, dirs)
         e32 = plan.event_output(efield, e)
-        ref = e64.abs().amax(dim=-1)
-        err = (e32.double() - e64).abs().amax(dim=-1) / torch.where(ref > 0, ref, torch.ones_like(ref))
+        ref = e64.abs().amax(dim=-1)                                   # [D][S][2]
+        dif = (e32.double() - e64).abs().amax(dim=-1)
+        err = dif / torch.where(ref > 0, ref, torch.ones_like(ref))
+        ref_s = ref.amax(dim=-1)                                       # the station's E-field trace
+        err_s = dif.amax(dim=-1) / torch.where(ref_s > 0, ref_s, torch.ones_like(ref_s))
         h = api.pattern_response(tab64, ev64, dirs)              # [D][nb][2][2] complex128
         det = h[:, :, 0, 0] * h[:, :, 1, 1] - h[:, :, 0, 1] * h[:, :, 1, 0]
         fro2 = (h.abs() ** 2).sum(dim=(-1, -2))
         kappa = (fro2 / det.abs()).amax(dim=-1)                  # [D]
         kb = torch.bucketize(kappa, torch.tensor(KAPPA_EDGES[1:-1], dtype=kappa.dtype, device=kappa.device))
         err_d = err.reshape(len(dirs), -1).cpu().numpy()
+        err_sd = err_s.reshape(len(dirs), -1).cpu().numpy()
         kb = kb.cpu().numpy()
         for di in range(len(dirs)):
             buckets[int(kb[di])].append(err_d[di])
+            sbuckets[int(kb[di])].append(err_sd[di])
         worst = max(worst, float(err.max()))
+        worst_s = max(worst_s, float(err_s.max()))
         n_tr += err.numel()
         del e64
     out = []
@@ -174,10 +181,14 @@ def fp32_error_report(api, plan, specs, efield, tab64, volt, dev):
         if not lst:
             continue
         a = np.concatenate(lst)
+        b = np.concatenate(sbuckets[i])
         out.append({"kappa": [KAPPA_EDGES[i], KAPPA_EDGES[i + 1]], "traces": int(a.size),
-                    "max": float(a.max()), "p99": float(np.percentile(a, 99)), "median": float(np.median(a))})
-    return {"traces": n_tr, "max": worst, "by_kappa": out,
-            "reference": "FP64 direction scan on the same float32 traces (complex128 table)"}
+                    "max": float(a.max()), "p99": float(np.percentile(a, 99)), "median": float(np.median(a)),
+                    "max_station": float(b.max())})
+    return {"traces": n_tr, "max": worst, "max_station": worst_s, "by_kappa": out,
+            "reference": "FP64 direction scan on the same float32 traces (complex128 table)",
+            "normalisation": "max/p99/median: per component trace, max|E32-E64| / max|E64| of that component; "
+                             "max_station: per station, over both components, divided by the larger peak"}
 
 
 def envelope_scan_rate(api, tab, ev, volt, dirs, work, reps, stream):
@@ -504,7 +515,8 @@ def main():
     if not args.no_fp32_error:
         tab64f = api.Table(grid, synth.pattern_table(grid, cfg=2).astype(np.complex64).astype(np.complex128))
         precision = fp32_error_report(api, plan, specs, efield, tab64f, volt, dev)
-        log("fp32 vs fp64 over %d traces: max %.3e; %s" % (precision["traces"], precision["max"],
+        log("fp32 vs fp64 over %d traces: max %.3e per component, %.3e per station; %s"
+            % (precision["traces"], precision["max"], precision["max_station"],
             ", ".join("kappa %g-%g: max %.2e" % (b["kappa"][0], b["kappa"][1], b["max"]) for b in precision["by_kappa"])))
         del tab64f
         torch.cuda.empty_cache()
