@@ -28,6 +28,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# HBM bytes per launch of the dominant kernel on this workload: rocprofv3 FETCH_SIZE x 2.000 +
+# WRITE_SIZE x 1.000 (copy-probe calibration), keyed by kernel and launch size.
+PROFILED_TRAFFIC_SOURCE = "profiles/k_unfold_fp32_batched_256events.md"
+PROFILED_TRAFFIC_BYTES = {
+    ("k_unfold<float, 4096, 8, 8, 1, false, false, true>", 2047488): (2049259 + 65528336) * 1024,
+}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -486,9 +492,12 @@ def main():
                           "unfold_algorithmic_GBs": bytes_launch / (unfold_ms / 1e3) / 1e9})
     dom = max(per_class, key=lambda c: c["unfold_ms"])
     achieved = dom["unfold_algorithmic_GBs"]
+    traffic = PROFILED_TRAFFIC_BYTES.get((dom["kernel"], dom["station_unfolds"]))
     roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
+                "traffic": traffic,
+                "traffic_ratio": None if traffic is None else round(traffic / (dom["station_unfolds"] * 2 * dom["n_samples"] * 4), 4),
+                "traffic_source": None if traffic is None else PROFILED_TRAFFIC_SOURCE,
                 "bytes_per_unit": "2*N*4 B written per station-unfold",
                 "launch_ms": dom["unfold_ms"], "station_unfolds_per_launch": dom["station_unfolds"],
                 "measured_copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
