@@ -527,20 +527,36 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, PAIR, PP>()))) void k_
 // env = sqrt(e^2 + H(e)^2) is reduced to its maximum and the first sample
 // attaining it, per component.  Optionally the traces are stored too.  A
 // non-null skip flag that reads nonzero turns the launch into a no-op.
+// Shape of the envelope kernel.  FP32: the two transforms run in lockstep
+// (fft2) through two LDS buffers with twiddles in registers.  FP64: the
+// registers do not hold two 8-value transforms, so they run one after the
+// other through one buffer with table twiddles.
+template <typename T>
+constexpr bool env_dual() { return sizeof(T) == 4; }
+template <typename T, int E>
+constexpr int env_twmode() { return env_dual<T>() && E <= 8 ? TW_REG : TW_TABLE; }
+template <typename T>
+constexpr int env_bufs() { return env_dual<T>() ? 2 : 1; }
+
 template <typename T, int N, int E>
 __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_env(
     EvDesc ev0, int spw, const XBin<T>* __restrict__ X, const MBin<T>* __restrict__ M, T* __restrict__ efield,
     T* __restrict__ peak, int* __restrict__ arg, const C2<T>* __restrict__ tw, const int* __restrict__ skip)
 {
     constexpr int TT = N / E;
-    constexpr int G = groups_per_block<T, N, E>();
+    constexpr int G = groups_per_block<T, N, E, env_bufs<T>()>();
     constexpr int NW = (TT + 63) / 64;  // waves per group
+    constexpr int TWM = env_twmode<T, E>();
+    constexpr bool DUAL = env_dual<T>();
     if (skip != nullptr && *skip) return;  // set by a converged reconstruction loop
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ T red_v[G][NW][3];
     __shared__ int red_i[G][NW][3];
     const int g = threadIdx.x / TT, t = threadIdx.x % TT;
-    C2<T>* la = reinterpret_cast<C2<T>*>(smem) + g * lds_elems<N>();
+    C2<T>* la = reinterpret_cast<C2<T>*>(smem) + g * env_bufs<T>() * lds_elems<N>();
+    C2<T>* lb = DUAL ? la + lds_elems<N>() : la;
+    C2<T> w[tw_count<N, E, E, TWM>()];
+    load_twiddles<T, N, E, E, TWM, +1>(w, tw, t);
     const int chunks = (ev0.S + spw - 1) / spw;
     const int d = blockIdx.x / chunks;
     const int s0 = (blockIdx.x - d * chunks) * spw, s1 = min(ev0.S, s0 + spw);
@@ -550,25 +566,30 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
         const int s = base + g;
         const bool active = s < s1;
         const XBin<T>* __restrict__ Xs = X + ev0.x_off + (int64_t)s * ev0.nb;
+        // the packed spectra: Z into la and Zh into lb at once (DUAL), or Z
+        // then Zh through the one buffer
         C2<T> x[E], xh[E];
-        // the two packed spectra go through the same LDS buffer one after the other
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < (DUAL ? 1 : 2); ++h) {
             if (active) {
                 for (unsigned j = t; j < nb; j += TT) {
                     const MBin<T> m = Md[j];
                     const XBin<T> xb = Xs[j];
-                    C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
-                    C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
+                    const C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
+                    const C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
                     const unsigned k = k_lo + j;
                     if (k == 0) {
-                        la[0] = h == 0 ? C2<T>{et.re, ep.re} : C2<T>{0, 0};
-                    } else if (h == 0) {
-                        la[lpad(k)] = C2<T>{et.re - ep.im, et.im + ep.re};
-                        la[lpad(N - k)] = C2<T>{et.re + ep.im, ep.re - et.im};
+                        if (DUAL || h == 0) la[0] = C2<T>{et.re, ep.re};
+                        if (DUAL || h == 1) lb[0] = C2<T>{0, 0};
                     } else {
-                        la[lpad(k)] = C2<T>{et.im + ep.re, ep.im - et.re};
-                        la[lpad(N - k)] = C2<T>{et.im - ep.re, et.re + ep.im};
+                        if (DUAL || h == 0) {
+                            la[lpad(k)] = C2<T>{et.re - ep.im, et.im + ep.re};
+                            la[lpad(N - k)] = C2<T>{et.re + ep.im, ep.re - et.im};
+                        }
+                        if (DUAL || h == 1) {
+                            lb[lpad(k)] = C2<T>{et.im + ep.re, ep.im - et.re};
+                            lb[lpad(N - k)] = C2<T>{et.im - ep.re, et.re + ep.im};
+                        }
                     }
                 }
             }
@@ -578,13 +599,17 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                 const unsigned k = t + TT * i;
                 const unsigned kk = (k <= N / 2) ? k : N - k;
                 const bool inb = active && (kk - k_lo) < nb;
-                const C2<T> v = inb ? la[lpad(k)] : C2<T>{0, 0};
-                if (h == 0) x[i] = v; else xh[i] = v;
+                if (DUAL || h == 0) x[i] = inb ? la[lpad(k)] : C2<T>{0, 0};
+                if (DUAL || h == 1) xh[i] = inb ? lb[lpad(k)] : C2<T>{0, 0};
             }
             __syncthreads();
         }
-        fft<T, N, E, +1>(x, la, tw, t);
-        fft<T, N, E, +1>(xh, la, tw, t);
+        if constexpr (DUAL) {
+            fft2<T, N, E, +1, TWM, E>(x, xh, la, lb, tw, t, w);
+        } else {
+            fft<T, N, E, +1>(x, la, tw, t);
+            fft<T, N, E, +1>(xh, la, tw, t);
+        }
         // per-thread maxima over its samples n = t + TT i (increasing in i) of
         // the theta, phi and total-field envelopes
         T bv[3] = {(T)-1, (T)-1, (T)-1};
@@ -2024,8 +2049,8 @@ static hipError_t launch_env_n(hipStream_t st, const EvDesc& ev0, int n_units, c
 {
     constexpr int E = N >= 1024 ? 8 : (N < 16 ? N : 16);
     constexpr int TT = N / E;
-    constexpr int G = groups_per_block<T, N, E>();
-    constexpr size_t LDS = (size_t)G * lds_elems<N>() * sizeof(C2<T>);
+    constexpr int G = groups_per_block<T, N, E, env_bufs<T>()>();
+    constexpr size_t LDS = (size_t)G * env_bufs<T>() * lds_elems<N>() * sizeof(C2<T>);
     hipLaunchKernelGGL((k_unfold_env<T, N, E>), dim3(n_units), dim3(G * TT), LDS, st, ev0, kStationsPerUnit, X, M,
                        efield, peak, arg, tw, skip);
     return hipGetLastError();

@@ -442,6 +442,82 @@ __device__ __forceinline__ void fft_pass_pp(C2<T> (&x)[E], C2<T>* __restrict__ l
     }
 }
 
+// Two transforms of the same length and direction run in lockstep: every
+// pass applies the same twiddles to both, scatters x into `la` and y into
+// `lb`, and one barrier pair per exchange serves both (the per-transform
+// barrier count of the ping-pong form, with twice the independent work
+// between barriers).
+template <typename T, int N, int E, int RMAX, int TWMODE, int NS, int SIGN>
+__device__ __forceinline__ void fft_pass2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* __restrict__ la,
+                                          C2<T>* __restrict__ lb, const C2<T>* __restrict__ tw,
+                                          const C2<T>* __restrict__ w, int t)
+{
+    constexpr int R = pass_radix<N, RMAX>(NS);
+    constexpr int TT = N / E;
+    constexpr int B = E / R;
+    constexpr bool LAST = (NS * R == N);
+    static_assert(R >= 2 && E % R == 0 && TWMODE != TW_SPLIT, "radix");
+#pragma unroll
+    for (int m = 0; m < B; ++m) {
+        const int j = t + TT * m;
+        const int k = j & (NS - 1);
+        C2<T> u[R], v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            u[r] = x[m + r * B];
+            v[r] = y[m + r * B];
+        }
+        if constexpr (NS > 1) {
+            constexpr int STRIDE = kTwN / (NS * R);
+            constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                C2<T> wr;
+                if constexpr (TWMODE == TW_TABLE)
+                    wr = twiddle_tab<SIGN>(tw, r * k * STRIDE);
+                else
+                    wr = w[OFF + m * (R - 1) + r - 1];
+                u[r] = cmul(u[r], wr);
+                v[r] = cmul(v[r], wr);
+            }
+        }
+        Dft<R, SIGN, T>::run(u);
+        Dft<R, SIGN, T>::run(v);
+        if constexpr (LAST) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                x[m + r * B] = u[r];
+                y[m + r * B] = v[r];
+            }
+        } else {
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                la[lpad(base + r * NS)] = u[r];
+                lb[lpad(base + r * NS)] = v[r];
+            }
+        }
+    }
+    if constexpr (!LAST) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            x[i] = la[lpad(t + TT * i)];
+            y[i] = lb[lpad(t + TT * i)];
+        }
+        __syncthreads();
+        fft_pass2<T, N, E, RMAX, TWMODE, NS * R, SIGN>(x, y, la, lb, tw, w, t);
+    }
+}
+
+template <typename T, int N, int E, int SIGN, int TWMODE, int RMAX>
+__device__ __forceinline__ void fft2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* __restrict__ la, C2<T>* __restrict__ lb,
+                                     const C2<T>* __restrict__ tw, int t, const C2<T>* __restrict__ w)
+{
+    static_assert((N & (N - 1)) == 0 && N >= E && (E & (E - 1)) == 0 && RMAX <= 32, "sizes");
+    fft_pass2<T, N, E, (RMAX < E ? RMAX : E), TWMODE, 1, SIGN>(x, y, la, lb, tw, w, t);
+}
+
 // Full transform with ping-pong buffers; the first exchange writes `la`.
 // The caller must not write `la` or `lb` again until every thread of the
 // group has passed a barrier that follows its last gather.
