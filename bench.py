@@ -197,6 +197,22 @@ def fp32_error_report(api, plan, specs, efield, tab64, volt, dev):
                              "max_station: per station, over both components, divided by the larger peak"}
 
 
+# FP32 vector FMA rate without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
+FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def alu_view(cls):
+    """The dominant launch against the vector ALU: algorithmic flops per station-unfold (inverse
+    complex FFT at 5 N log2 N, plus 4 complex multiply-adds per in-band bin) over the launch time."""
+    n = cls["n_samples"]
+    nb = n // 4                                   # 30-80 MHz of 0-100 MHz at 200 MHz: a quarter of the bins
+    flops = 5 * n * int(np.log2(n)) + nb * 28
+    achieved = cls["station_unfolds"] * flops / (cls["unfold_ms"] / 1e3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(FP32_VALU_PEAK_TFLOPS, 1),
+            "unit": "TFLOP/s", "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
+            "flops_per_unit": flops, "convention": "5 N log2 N per complex FFT + 28 flops per in-band bin"}
+
+
 def envelope_scan_rate(api, tab, ev, volt, dirs, work, reps, stream):
     """Station-unfolds/s of au_unfold_envelope_scan (peaks and their samples only, no traces)."""
     import torch
@@ -501,7 +517,8 @@ def main():
                 "bytes_per_unit": "2*N*4 B written per station-unfold",
                 "launch_ms": dom["unfold_ms"], "station_unfolds_per_launch": dom["station_unfolds"],
                 "measured_copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
-                "per_class": per_class}
+                "per_class": per_class,
+                "alu": alu_view(dom)}
 
     # graph replay of the same plan, for reference
     gplan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=args.flags | api.AU_PLAN_GRAPH)
