@@ -330,6 +330,40 @@ __device__ __forceinline__ int fft_thread(int r)
     }
 }
 
+// An empty use of a value held in registers: the compiler must have it
+// (and so wait for the load that produces it) at this point.
+template <typename T>
+__device__ __forceinline__ void touch(const C2<T>& v)
+{
+    asm volatile("" ::"v"(v.re), "v"(v.im));
+}
+
+// An LDS slot no pass ever reads: lpad() skips index 16 (i = 15 -> 15,
+// i = 16 -> 17).
+constexpr int kLdsPadSlot = 16;
+
+// One in-band bin of the packed spectrum: (E_theta, E_phi) = C X, stored as
+// Z[k] = E_theta + i E_phi and Z[N-k] = conj E_theta + i conj E_phi (only the
+// real parts at k = 0).
+template <typename T, int N>
+__device__ __forceinline__ void stage_bin(C2<T>* __restrict__ lds, unsigned k, const MBin<T>& m, const XBin<T>& xb,
+                                          bool write = true)
+{
+    const C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
+    const C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
+    if (!write) return;
+    if (k == 0) {
+        lds[0] = C2<T>{et.re, ep.re};
+    } else {
+        lds[lpad(k)] = C2<T>{et.re - ep.im, et.im + ep.re};
+        lds[lpad(N - k)] = C2<T>{et.re + ep.im, ep.re - et.im};
+    }
+}
+
+#ifndef AU_UNFOLD_PF
+#define AU_UNFOLD_PF 2
+#endif
+
 // Minimum waves per SIMD the register allocator must leave room for: the
 // FP32 shapes with 8 values per thread and two LDS buffers or paired lanes
 // fit in 128 VGPRs (four waves per SIMD, the same as the plain 8-value shape)
@@ -350,6 +384,9 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, PAIR, PP>()))) void k_
 {
     constexpr int TT = N / E;
     constexpr int G = groups_per_block<T, N, E, PP ? 2 : 1>();
+    // bins per thread prefetched for the next station: the FP32 shapes whose
+    // early twiddles live in LDS have the registers for it
+    constexpr int PF = (sizeof(T) == 4 && TWMODE == TW_HYB && E <= 8 && !PAIR && !WAVE) ? AU_UNFOLD_PF : 0;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sh_u;
     __shared__ int sh_list;
@@ -359,8 +396,16 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, PAIR, PP>()))) void k_
     // alternate lds2, lds, ...
     C2<T>* lds = reinterpret_cast<C2<T>*>(smem) + g * (PP ? 2 : 1) * lds_elems<N>();
     C2<T>* lds2 = lds + lds_elems<N>();
+    C2<T>* ltw = reinterpret_cast<C2<T>*>(smem) + G * (PP ? 2 : 1) * lds_elems<N>();
     C2<T> w[tw_count<N, E, RMAX, TWMODE>()];
     load_twiddles<T, N, E, RMAX, TWMODE, +1>(w, tw, t);
+    if constexpr (TWMODE == TW_HYB) fill_lds_twiddles<T, N, E, RMAX, +1>(ltw, tw, threadIdx.x, blockDim.x);
+    // Wait for the twiddle loads here, once.  Left to the compiler, the wait
+    // lands at their first use inside the station loop, where vector-memory
+    // completions are counted in issue order: every station would then wait
+    // for all stores of the station before it.
+    vmem_wait_all();
+    if constexpr (TWMODE == TW_HYB) lds_barrier();
     // XCD-aware placement (xcd_off != nullptr): the unit array holds 8 lists,
     // list x = [xcd_off[x], xcd_off[x+1]), built so that all station chunks of
     // one (event, direction) -- which share a coefficient row -- sit in one
@@ -391,9 +436,9 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, PAIR, PP>()))) void k_
                 }
                 sh_u = got;
             }
-            __syncthreads();
+            lds_barrier();
             u = sh_u;
-            __syncthreads();
+            lds_barrier();
         } else {
             if (iter > 0) break;
             u = blockIdx.x;
@@ -419,6 +464,38 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, PAIR, PP>()))) void k_
         const EvDesc ev = evs ? evs[e] : ev0;
         const MBin<T>* __restrict__ Md = M + ev.m_off + (int64_t)d * ev.nb;
         const unsigned nb = (unsigned)ev.nb, k_lo = (unsigned)ev.k_lo;
+        MBin<T> pm[PF > 0 ? PF : 1];
+        XBin<T> px[PF > 0 ? PF : 1];
+        // loads of PF bins of station s (clamped: a valid station, bin nb-1 for
+        // bins past the band, the twiddle table when the band is empty)
+        auto prefetch_bins = [&](const MBin<T>* md, const XBin<T>* xe, int sv, unsigned nbv, const C2<T>* safe,
+                                 int tv) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const unsigned j = min(tv + TT * q, nbv > 0 ? (int)nbv - 1 : 0);
+                const MBin<T>* pmq = nbv > 0 ? md + j : reinterpret_cast<const MBin<T>*>(safe);
+                const XBin<T>* pxq = nbv > 0 ? xe + (int64_t)sv * nbv + j : reinterpret_cast<const XBin<T>*>(safe);
+                pm[q] = *pmq;
+                px[q] = *pxq;
+            }
+        };
+        if constexpr (PF > 0) {
+            prefetch_bins(Md, X + ev.x_off, min(s0 + g, s1 - 1), nb, tw, t);
+            // Once per unit, take these loads in here (an empty use of every
+            // loaded register): then the only loads outstanding at the top of
+            // the station loop are the prefetch issued ahead of the previous
+            // station's stores, and the wait for them leaves those stores in
+            // flight.
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                touch(pm[q].m00);
+                touch(pm[q].m01);
+                touch(pm[q].m10);
+                touch(pm[q].m11);
+                touch(px[q].x0);
+                touch(px[q].x1);
+            }
+        }
         for (int base = s0; base < s1; base += G) {
             const int s = base + g;
             const bool active = s < s1;
@@ -466,20 +543,34 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, PAIR, PP>()))) void k_
                     x[i] = C2<T>{et.re + ep.im, ep.re - et.im};
                 }
             } else {
-                if (active) {
-                    for (unsigned j = t; j < nb; j += TT) {
-                        const MBin<T> m = Md[j];
-                        const XBin<T> xb = Xs[j];
-                        C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
-                        C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
+                if constexpr (PF > 0) {
+                    // Bins past the prefetched ones (a band wider than PF TT
+                    // bins) are loaded here; the loop is skipped uniformly
+                    // otherwise.
+                    if (nb > (unsigned)(PF * TT) && (G == 1 || active))
+                        for (unsigned j = t + TT * PF; j < nb; j += TT) stage_bin<T, N>(lds, k_lo + j, Md[j], Xs[j]);
+                    // The first PF bins of this thread were loaded ahead (at
+                    // the unit's start, or before the previous station's
+                    // stores).  Branch-free: every lane computes them, and a
+                    // lane with nothing to write writes pad slot 16 (never
+                    // read), so that the only wait for these loads is the one
+                    // before their use.
+#pragma unroll
+                    for (int q = 0; q < PF; ++q) {
+                        const unsigned j = t + TT * q;
                         const unsigned k = k_lo + j;
-                        if (k == 0) {
-                            lds[0] = C2<T>{et.re, ep.re};
-                        } else {
-                            lds[lpad(k)] = C2<T>{et.re - ep.im, et.im + ep.re};
-                            lds[lpad(N - k)] = C2<T>{et.re + ep.im, ep.re - et.im};
-                        }
+                        const bool ok = (G == 1 || active) && j < nb;
+                        const MBin<T>& m = pm[q];
+                        const XBin<T>& xb = px[q];
+                        const C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
+                        const C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
+                        const C2<T> zk = k == 0 ? C2<T>{et.re, ep.re} : C2<T>{et.re - ep.im, et.im + ep.re};
+                        const C2<T> zn{et.re + ep.im, ep.re - et.im};
+                        lds[ok ? lpad(k) : kLdsPadSlot] = zk;
+                        lds[(ok && k != 0) ? lpad(N - k) : kLdsPadSlot] = zn;
                     }
+                } else if (active) {
+                    for (unsigned j = t; j < nb; j += TT) stage_bin<T, N>(lds, k_lo + j, Md[j], Xs[j]);
                 }
                 lds_sync<WAVE>();
 #pragma unroll
@@ -492,7 +583,7 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, PAIR, PP>()))) void k_
                 if constexpr (!PP) lds_sync<WAVE>();
             }
             if constexpr (PP) {
-                fft_pp<T, N, E, +1, TWMODE, RMAX, WAVE>(x, lds2, lds, tw, t, w);
+                fft_pp<T, N, E, +1, TWMODE, RMAX, WAVE>(x, lds2, lds, tw, t, w, ltw);
                 // exchanges this station: the staging one (lds, unless PAIR)
                 // plus one per pass boundary, alternating from lds2; make the
                 // next station's first write go to the buffer not gathered last
@@ -503,9 +594,14 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, PAIR, PP>()))) void k_
                     lds2 = tmp;
                 }
             } else {
-                fft<T, N, E, +1, TWMODE, RMAX, WAVE>(x, lds, tw, t, w);
+                fft<T, N, E, +1, TWMODE, RMAX, WAVE>(x, lds, tw, t, w, ltw);
             }
-            if (active) {
+            // Prefetch the next station's bins before this station's stores:
+            // vector-memory completions are counted in issue order, so loads
+            // issued after the stores would wait for every store to land.
+            // Branch-free, clamped to a valid station and bin.
+            if constexpr (PF > 0) prefetch_bins(Md, X + ev.x_off, min(s + G, s1 - 1), nb, tw, t);
+            if (G == 1 || active) {  // one group per block: its station is always active
                 T* out = efield + ev.efield_off + ((int64_t)d * ev.S + s) * 2 * N;
 #pragma unroll
                 for (int i = 0; i < E; ++i) {
@@ -593,7 +689,7 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 const unsigned k = t + TT * i;
@@ -602,7 +698,7 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                 if (DUAL || h == 0) x[i] = inb ? la[lpad(k)] : C2<T>{0, 0};
                 if (DUAL || h == 1) xh[i] = inb ? lb[lpad(k)] : C2<T>{0, 0};
             }
-            __syncthreads();
+            lds_barrier();
         }
         if constexpr (DUAL) {
             fft2<T, N, E, +1, TWM, E>(x, xh, la, lb, tw, t, w);
@@ -649,7 +745,7 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                 red_i[g][wv][c] = bi[c];
             }
         }
-        __syncthreads();
+        lds_barrier();
         // components c = t, t + TT, ... (a group of N = 16 or 32 has fewer than 3 threads)
         for (int c = t; active && c < 3; c += TT) {
             T v = red_v[g][0][c];
@@ -674,7 +770,7 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                 __builtin_nontemporal_store(x[i].im, out + N + t + TT * i);
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -723,8 +819,9 @@ constexpr UnfoldVariant kUnfoldVariants[] = {
     {0, 16, TW_SPLIT, true, false, false}, {0, 8, TW_SPLIT, true, false, false},
     {8, 8, TW_REG, false, true, false},    {16, 16, TW_REG, false, true, false},
     {8, 8, TW_REG, false, false, true},    {16, 16, TW_REG, false, false, true},
+    {8, 8, TW_HYB, false, false, true},    {8, 8, TW_HYB, false, false, false},
 };
-constexpr int kNumVariants = 12;
+constexpr int kNumVariants = 14;
 
 // LDS one workgroup may allocate on gfx950 (the whole 160 KiB of a CU).
 constexpr int kMaxLdsPerBlock = 163840;
@@ -761,7 +858,8 @@ struct UShape {
     static constexpr int TT = N / E;
     static constexpr int G = groups_per_block<T, N, E, BUFS>();
     static constexpr int BLOCK = G * TT;
-    static constexpr size_t LDS = (size_t)G * BUFS * lds_elems<N>() * sizeof(C2<T>);
+    static constexpr size_t LDS =
+        ((size_t)G * BUFS * lds_elems<N>() + (TWMODE == TW_HYB ? ltw_count<N, E, RMAX>() : 0)) * sizeof(C2<T>);
 };
 
 static int ilog2(int n)
@@ -772,12 +870,13 @@ static int ilog2(int n)
 }
 
 // Selected variant per [precision][log2 N]; the defaults are the shapes
-// that measured fastest on MI355X (E=8 with register twiddles from 1024
-// samples up; below, E=16 with register twiddles for float and table
-// twiddles for double).
+// that measured fastest on MI355X (from 1024 samples up: E=8 with register
+// twiddles for double, and for float E=8 with early twiddles in LDS, two
+// LDS buffers and the next station's bins prefetched; below, E=16 with
+// register twiddles for float and table twiddles for double).
 static std::mutex g_var_mu;
 static int g_variant[2][13] = {{1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2},
-                               {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 2, 2, 2}};
+                               {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 12, 12, 12}};
 
 static int unfold_variant(int prec, int n)
 {
@@ -831,7 +930,7 @@ static hipError_t launch_unfold_n(int v, hipStream_t st, const EvDesc& ev0, cons
     switch (v) {
 #define V_(VV) \
     case VV: return launch_unfold_nv<T, N, VV>(st, ev0, evs, units, n_units, spw, X, M, efield, tw, counter, persistent_blocks, xcd_off, xcd_max_list);
-        V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11)
+        V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11) V_(12) V_(13)
 #undef V_
     }
     return hipErrorInvalidValue;
@@ -905,6 +1004,8 @@ static int persistent_blocks_for(int n, int v, int device)
             case 9: per_cu = occupancy_nv<T, NN, 9>(); break;                                   \
             case 10: per_cu = occupancy_nv<T, NN, 10>(); break;                                 \
             case 11: per_cu = occupancy_nv<T, NN, 11>(); break;                                 \
+            case 12: per_cu = occupancy_nv<T, NN, 12>(); break;                                 \
+            case 13: per_cu = occupancy_nv<T, NN, 13>(); break;                                 \
         }                                                                                       \
         break;
         AU_FOR_EACH_N(X_)

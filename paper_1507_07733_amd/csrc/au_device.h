@@ -209,6 +209,10 @@ constexpr CxRoot cx_root(long long p, long long q)
     }
 }
 
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left alone): every vector-memory
+// operation issued so far has completed.
+__device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // LDS index with one pad slot every 16 elements: the radix-R scatter of a
 // pass (stride R or NS between lanes) no longer lands every lane of a wave in
 // the same bank.
@@ -234,7 +238,12 @@ constexpr int lds_elems() { return N + N / 16; }
 //             exp(SIGN 2 pi i r (TT m mod NS) / (NS R)) (compile-time
 //             constant).
 // ---------------------------------------------------------------------------
-enum { TW_TABLE = 0, TW_REG = 1, TW_SPLIT = 2 };
+//   TW_HYB:   passes with NS < TT (k = t mod NS for every m: only NS
+//             distinct factors sets) read them from a per-workgroup LDS
+//             table of NS (R-1) entries per pass; the passes with NS >= TT
+//             keep theirs in registers as TW_REG.  Saves the registers of
+//             the early passes for one LDS read per factor.
+enum { TW_TABLE = 0, TW_REG = 1, TW_SPLIT = 2, TW_HYB = 3 };
 
 template <int N, int RMAX>
 constexpr int pass_radix(int ns) { return (N / ns < RMAX) ? N / ns : RMAX; }
@@ -246,9 +255,28 @@ constexpr int tw_offset(int ns_target)
     for (int ns = 1; ns < ns_target && ns < N; ns *= pass_radix<N, RMAX>(ns)) {
         if (ns == 1) continue;
         const int r = pass_radix<N, RMAX>(ns);
-        off += TWMODE == TW_REG ? (E / r) * (r - 1) : (r - 1);
+        if (TWMODE == TW_HYB && ns < N / E) continue;
+        off += (TWMODE == TW_REG || TWMODE == TW_HYB) ? (E / r) * (r - 1) : (r - 1);
     }
     return off;
+}
+
+// Offset of pass NS in the TW_HYB LDS table, and the table's length.
+template <int N, int E, int RMAX>
+constexpr int ltw_offset(int ns_target)
+{
+    int off = 0;
+    for (int ns = 1; ns < ns_target && ns < N; ns *= pass_radix<N, RMAX>(ns)) {
+        if (ns == 1) continue;
+        if (ns >= N / E) break;
+        off += ns * (pass_radix<N, RMAX>(ns) - 1);
+    }
+    return off;
+}
+template <int N, int E, int RMAX>
+constexpr int ltw_count()
+{
+    return ltw_offset<N, E, RMAX>(N);
 }
 
 template <int N, int E, int RMAX, int TWMODE>
@@ -265,7 +293,9 @@ __device__ __forceinline__ void load_twiddles_from(C2<T>* __restrict__ w, const 
         if constexpr (NS > 1) {
             constexpr int TT = N / E, B = E / R, STRIDE = kTwN / (NS * R);
             constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
-            if constexpr (TWMODE == TW_REG) {
+            if constexpr (TWMODE == TW_HYB && NS < TT) {
+                // in the LDS table (fill_lds_twiddles)
+            } else if constexpr (TWMODE == TW_REG || TWMODE == TW_HYB) {
 #pragma unroll
                 for (int m = 0; m < B; ++m) {
                     const int k = (t + TT * m) & (NS - 1);
@@ -289,9 +319,50 @@ __device__ __forceinline__ void load_twiddles(C2<T>* __restrict__ w, const C2<T>
     if constexpr (TWMODE != TW_TABLE) load_twiddles_from<T, N, E, RMAX, TWMODE, 1, SIGN>(w, tw, t);
 }
 
+// The TW_HYB LDS table: entry LOFF(NS) + k (R-1) + r - 1 = exp(SIGN 2 pi i r k / (NS R))
+// for every pass with 1 < NS < TT; filled cooperatively by nthr threads.
+template <typename T, int N, int E, int RMAX, int NS, int SIGN>
+__device__ __forceinline__ void fill_lds_twiddles_from(C2<T>* __restrict__ ltw, const C2<T>* __restrict__ tw,
+                                                       int tid, int nthr)
+{
+    if constexpr (NS < N && NS < N / E) {
+        constexpr int R = pass_radix<N, RMAX>(NS);
+        if constexpr (NS > 1) {
+            constexpr int STRIDE = kTwN / (NS * R);
+            constexpr int LOFF = ltw_offset<N, E, RMAX>(NS);
+            for (int i = tid; i < NS * (R - 1); i += nthr) {
+                const int k = i / (R - 1), r = i - k * (R - 1) + 1;
+                ltw[LOFF + i] = twiddle_tab<SIGN>(tw, r * k * STRIDE);
+            }
+        }
+        fill_lds_twiddles_from<T, N, E, RMAX, NS * R, SIGN>(ltw, tw, tid, nthr);
+    }
+}
+
+template <typename T, int N, int E, int RMAX, int SIGN>
+__device__ __forceinline__ void fill_lds_twiddles(C2<T>* __restrict__ ltw, const C2<T>* __restrict__ tw, int tid,
+                                                  int nthr)
+{
+    fill_lds_twiddles_from<T, N, E, (RMAX < E ? RMAX : E), 1, SIGN>(ltw, tw, tid, nthr);
+}
+
+// Workgroup barrier that orders LDS only.  The exchanges between FFT passes
+// (and the small LDS reductions) need every LDS write before the barrier
+// visible after it; no thread reads another thread's global writes.  The
+// full barrier's fence also covers global memory and so waits (vmcnt 0) for
+// every store the wave still has in flight -- the previous station's output
+// -- at each exchange.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Synchronisation between the LDS scatter of one pass and the gather of the
-// next: a workgroup barrier, or -- when one wavefront owns the transform --
-// only a wave-level fence (LDS operations of one wave complete in order).
+// next: an LDS workgroup barrier, or -- when one wavefront owns the
+// transform -- only a wave-level fence (LDS operations of one wave complete
+// in order).
 template <bool WAVE>
 __device__ __forceinline__ void lds_sync()
 {
@@ -300,7 +371,7 @@ __device__ __forceinline__ void lds_sync()
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     } else {
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -313,7 +384,8 @@ __device__ __forceinline__ void lds_sync()
 // pass, which therefore stays in registers).  LDS positions use lpad().
 template <typename T, int N, int E, int RMAX, int TWMODE, bool WAVE, int NS, int SIGN>
 __device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
-                                         const C2<T>* __restrict__ tw, const C2<T>* __restrict__ w, int t)
+                                         const C2<T>* __restrict__ tw, const C2<T>* __restrict__ w, int t,
+                                         const C2<T>* __restrict__ ltw)
 {
     constexpr int R = pass_radix<N, RMAX>(NS);
     constexpr int TT = N / E;
@@ -335,8 +407,10 @@ __device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
                 C2<T> wr;
                 if constexpr (TWMODE == TW_TABLE) {
                     wr = twiddle_tab<SIGN>(tw, r * k * STRIDE);
-                } else if constexpr (TWMODE == TW_REG) {
+                } else if constexpr (TWMODE == TW_REG || (TWMODE == TW_HYB && NS >= TT)) {
                     wr = w[OFF + m * (R - 1) + r - 1];
+                } else if constexpr (TWMODE == TW_HYB) {
+                    wr = ltw[ltw_offset<N, E, RMAX>(NS) + k * (R - 1) + r - 1];
                 } else {
                     wr = w[OFF + r - 1];
                     if constexpr (NS > TT) {
@@ -366,7 +440,7 @@ __device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
 #pragma unroll
         for (int i = 0; i < E; ++i) x[i] = lds[lpad(t + TT * i)];
         lds_sync<WAVE>();
-        fft_pass<T, N, E, RMAX, TWMODE, WAVE, NS * R, SIGN>(x, lds, tw, w, t);
+        fft_pass<T, N, E, RMAX, TWMODE, WAVE, NS * R, SIGN>(x, lds, tw, w, t, ltw);
     }
 }
 
@@ -386,7 +460,8 @@ constexpr int num_passes()
 // a single buffer).
 template <typename T, int N, int E, int RMAX, int TWMODE, bool WAVE, int NS, int SIGN>
 __device__ __forceinline__ void fft_pass_pp(C2<T> (&x)[E], C2<T>* __restrict__ la, C2<T>* __restrict__ lb,
-                                            const C2<T>* __restrict__ tw, const C2<T>* __restrict__ w, int t)
+                                            const C2<T>* __restrict__ tw, const C2<T>* __restrict__ w, int t,
+                                            const C2<T>* __restrict__ ltw)
 {
     constexpr int R = pass_radix<N, RMAX>(NS);
     constexpr int TT = N / E;
@@ -408,8 +483,10 @@ __device__ __forceinline__ void fft_pass_pp(C2<T> (&x)[E], C2<T>* __restrict__ l
                 C2<T> wr;
                 if constexpr (TWMODE == TW_TABLE) {
                     wr = twiddle_tab<SIGN>(tw, r * k * STRIDE);
-                } else if constexpr (TWMODE == TW_REG) {
+                } else if constexpr (TWMODE == TW_REG || (TWMODE == TW_HYB && NS >= TT)) {
                     wr = w[OFF + m * (R - 1) + r - 1];
+                } else if constexpr (TWMODE == TW_HYB) {
+                    wr = ltw[ltw_offset<N, E, RMAX>(NS) + k * (R - 1) + r - 1];
                 } else {
                     wr = w[OFF + r - 1];
                     if constexpr (NS > TT) {
@@ -438,7 +515,7 @@ __device__ __forceinline__ void fft_pass_pp(C2<T> (&x)[E], C2<T>* __restrict__ l
         lds_sync<WAVE>();
 #pragma unroll
         for (int i = 0; i < E; ++i) x[i] = la[lpad(t + TT * i)];
-        fft_pass_pp<T, N, E, RMAX, TWMODE, WAVE, NS * R, SIGN>(x, lb, la, tw, w, t);
+        fft_pass_pp<T, N, E, RMAX, TWMODE, WAVE, NS * R, SIGN>(x, lb, la, tw, w, t, ltw);
     }
 }
 
@@ -499,13 +576,13 @@ __device__ __forceinline__ void fft_pass2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* _
         }
     }
     if constexpr (!LAST) {
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             x[i] = la[lpad(t + TT * i)];
             y[i] = lb[lpad(t + TT * i)];
         }
-        __syncthreads();
+        lds_barrier();
         fft_pass2<T, N, E, RMAX, TWMODE, NS * R, SIGN>(x, y, la, lb, tw, w, t);
     }
 }
@@ -523,10 +600,11 @@ __device__ __forceinline__ void fft2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* __rest
 // group has passed a barrier that follows its last gather.
 template <typename T, int N, int E, int SIGN, int TWMODE, int RMAX, bool WAVE>
 __device__ __forceinline__ void fft_pp(C2<T> (&x)[E], C2<T>* __restrict__ la, C2<T>* __restrict__ lb,
-                                       const C2<T>* __restrict__ tw, int t, const C2<T>* __restrict__ w)
+                                       const C2<T>* __restrict__ tw, int t, const C2<T>* __restrict__ w,
+                                       const C2<T>* __restrict__ ltw = nullptr)
 {
     static_assert((N & (N - 1)) == 0 && N >= E && (E & (E - 1)) == 0 && RMAX <= 32, "sizes");
-    fft_pass_pp<T, N, E, (RMAX < E ? RMAX : E), TWMODE, WAVE, 1, SIGN>(x, la, lb, tw, w, t);
+    fft_pass_pp<T, N, E, (RMAX < E ? RMAX : E), TWMODE, WAVE, 1, SIGN>(x, la, lb, tw, w, t, ltw);
 }
 
 // Full N-point transform of the group's sequence, exp(SIGN ...) kernel, no
@@ -536,10 +614,11 @@ __device__ __forceinline__ void fft_pp(C2<T> (&x)[E], C2<T>* __restrict__ la, C2
 template <typename T, int N, int E, int SIGN, int TWMODE = TW_TABLE, int RMAX = E, bool WAVE = false>
 __device__ __forceinline__ void fft(C2<T> (&x)[E], C2<T>* __restrict__ lds,
                                     const C2<T>* __restrict__ tw, int t,
-                                    const C2<T>* __restrict__ w = nullptr)
+                                    const C2<T>* __restrict__ w = nullptr,
+                                    const C2<T>* __restrict__ ltw = nullptr)
 {
     static_assert((N & (N - 1)) == 0 && N >= E && (E & (E - 1)) == 0 && RMAX <= 32, "sizes");
-    fft_pass<T, N, E, (RMAX < E ? RMAX : E), TWMODE, WAVE, 1, SIGN>(x, lds, tw, w, t);
+    fft_pass<T, N, E, (RMAX < E ? RMAX : E), TWMODE, WAVE, 1, SIGN>(x, lds, tw, w, t, ltw);
 }
 
 }  // namespace au
