@@ -480,20 +480,22 @@ def main():
     for _ in range(args.warmup):
         plan.run(volt, efield, counts)
     torch.cuda.synchronize()
-    plan.set_timing(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    # eager launches, back to back
     ev0.record(stream)
     for _ in range(args.steps):
         plan.run(volt, efield, counts)
     ev1.record(stream)
     torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
+    eager_ms = ev0.elapsed_time(ev1) / args.steps
+    log("batched fp32 eager: %.3f ms/step" % eager_ms)
+    # stage timing (HIP events between the launches, one host wait per run) for the roofline
+    plan.set_timing(True)
+    for _ in range(max(3, args.steps // 3)):
+        plan.run(volt, efield, counts)
+    torch.cuda.synchronize()
     stage_ms, runs = plan.stage_ms()
     plan.set_timing(False)
-    ms_per_step = total_ms / args.steps
-    value = plan.station_unfolds * args.steps / (total_ms / 1e3)
-    log("batched fp32: %.3f ms/step, %.1f M station-unfolds/s" % (ms_per_step, value / 1e6))
 
     classes = plan.classes()
     per_class = []
@@ -520,9 +522,9 @@ def main():
                 "per_class": per_class,
                 "alu": alu_view(dom)}
 
-    # graph replay of the same plan, for reference
+    # the timed step: the same plan captured in a hipGraph and replayed back to back
     gplan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=args.flags | api.AU_PLAN_GRAPH)
-    for _ in range(2):
+    for _ in range(max(2, args.warmup)):
         gplan.run(volt, efield, counts)
     torch.cuda.synchronize()
     ev0.record(stream)
@@ -531,7 +533,9 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     graph_ms = ev0.elapsed_time(ev1) / args.steps
-    log("graph replay: %.3f ms/step" % graph_ms)
+    ms_per_step = graph_ms
+    value = plan.station_unfolds / (graph_ms / 1e3)
+    log("batched fp32 graph replay: %.3f ms/step, %.1f M station-unfolds/s" % (graph_ms, value / 1e6))
 
     err = parity_sample(grid, table, specs, plan, volt_host, efield)
     cnt = counts.cpu().tolist()
@@ -632,7 +636,8 @@ def main():
                                "16x16 directions/event, complex64 table 0.5 MHz/1 deg, FP64 det fallback"
                                % len(specs),
                    "events": len(specs), "station_unfolds": int(plan.station_unfolds),
-                   "plan_flags": flags, "graph_ms_per_step": graph_ms, "autotuned": tuned},
+                   "plan_flags": args.flags | api.AU_PLAN_GRAPH, "timed": "hipGraph replay of the plan",
+                   "eager_ms_per_step": eager_ms, "autotuned": tuned},
         "roofline": roofline,
         "fp64_plain": fp64,
         "serving": serving,

@@ -870,12 +870,12 @@ static int ilog2(int n)
 }
 
 // Selected variant per [precision][log2 N]; the defaults are the shapes
-// that measured fastest on MI355X (from 1024 samples up: E=8 with register
-// twiddles for double, and for float E=8 with early twiddles in LDS, two
-// LDS buffers and the next station's bins prefetched; below, E=16 with
-// register twiddles for float and table twiddles for double).
+// that measured fastest on MI355X (from 1024 samples up: E=8 with the early
+// twiddles in LDS -- for double with one LDS buffer, for float with two and
+// the next station's bins prefetched; below, E=16 with register twiddles for
+// float and table twiddles for double).
 static std::mutex g_var_mu;
-static int g_variant[2][13] = {{1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2},
+static int g_variant[2][13] = {{1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 13, 13, 13},
                                {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 12, 12, 12}};
 
 static int unfold_variant(int prec, int n)
