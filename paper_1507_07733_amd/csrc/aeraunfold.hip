@@ -2144,15 +2144,27 @@ extern "C" au_status au_hbm_fill(void* d_dst, uint64_t bytes, uint32_t value, vo
 // envelope peaks of a direction scan
 // ---------------------------------------------------------------------------
 
+// Stations per envelope workgroup: up to 8 for large scans, fewer when
+// directions x stations would leave the GPU short of workgroups (the
+// reconstruction loop's one-direction launches).
+static int env_spw(int S, int64_t n_dir)
+{
+    const int64_t want = 4 * 256;  // workgroups: a few per CU
+    int spw = 8;
+    while (spw > 1 && n_dir * ((S + spw - 1) / spw) < want) spw /= 2;
+    return spw;
+}
+
 template <typename T, int N>
-static hipError_t launch_env_n(hipStream_t st, const EvDesc& ev0, int n_units, const XBin<T>* X, const MBin<T>* M,
-                               T* efield, T* peak, int* arg, const C2<T>* tw, const int* skip = nullptr)
+static hipError_t launch_env_n(hipStream_t st, const EvDesc& ev0, int spw, int n_units, const XBin<T>* X,
+                               const MBin<T>* M, T* efield, T* peak, int* arg, const C2<T>* tw,
+                               const int* skip = nullptr)
 {
     constexpr int E = N >= 1024 ? 8 : (N < 16 ? N : 16);
     constexpr int TT = N / E;
     constexpr int G = groups_per_block<T, N, E, env_bufs<T>()>();
     constexpr size_t LDS = (size_t)G * env_bufs<T>() * lds_elems<N>() * sizeof(C2<T>);
-    hipLaunchKernelGGL((k_unfold_env<T, N, E>), dim3(n_units), dim3(G * TT), LDS, st, ev0, kStationsPerUnit, X, M,
+    hipLaunchKernelGGL((k_unfold_env<T, N, E>), dim3(n_units), dim3(G * TT), LDS, st, ev0, spw, X, M,
                        efield, peak, arg, tw, skip);
     return hipGetLastError();
 }
@@ -2190,13 +2202,14 @@ static au_status run_envelope(const au_table* tb, const au_event* ev, const EvPa
                               ev->singular_rel, M, (unsigned long long*)d_counts);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_coef: ") + hipGetErrorString(e));
-    const int chunks = (p.S + kStationsPerUnit - 1) / kStationsPerUnit;
+    const int spw = env_spw(p.S, n_dir);
+    const int chunks = (p.S + spw - 1) / spw;
     const int64_t n_units = (int64_t)n_dir * chunks;
     if (n_units > (int64_t)0x7fffffff) return fail(AU_EINVAL, "too many work units");
     switch (p.N) {
 #define X_(NN)                                                                                              \
     case NN:                                                                                                \
-        e = launch_env_n<T, NN>(st, ev0, (int)n_units, X, M, (T*)d_efield, (T*)d_peak, (int*)d_arg, tw); \
+        e = launch_env_n<T, NN>(st, ev0, spw, (int)n_units, X, M, (T*)d_efield, (T*)d_peak, (int*)d_arg, tw); \
         break;
         AU_FOR_EACH_N(X_)
 #undef X_
@@ -2474,11 +2487,12 @@ static au_status run_reconstruct(const au_table* tb, const au_event* ev, const E
         else
             launch_coef<float, T>(st, tb, ev0, nullptr, nullptr, 1, cur, 0, 0, ev->fs_hz, ev->fallback_rel,
                                   ev->singular_rel, M, nullptr);
-        const int chunks = (p.S + kStationsPerUnit - 1) / kStationsPerUnit;
+        const int spw = env_spw(p.S, 1);
+        const int chunks = (p.S + spw - 1) / spw;
         switch (p.N) {
 #define X_(NN)                                                                                               \
     case NN:                                                                                                 \
-        e = launch_env_n<T, NN>(st, ev0, chunks, X, M, (T*)d_efield, peak, arg, tw, (const int*)state); \
+        e = launch_env_n<T, NN>(st, ev0, spw, chunks, X, M, (T*)d_efield, peak, arg, tw, (const int*)state); \
         break;
             AU_FOR_EACH_N(X_)
 #undef X_
@@ -2667,7 +2681,7 @@ au_status check_fit(const au_table* tb, const au_event* ev, int32_t n_dir, int32
     if (levels > 0 && (!(step_zen > 0.0) || !(step_az > 0.0) || !std::isfinite(step_zen) ||
                        !std::isfinite(step_az) || step_zen > 90.0 || step_az > 360.0))
         return fail(AU_EINVAL, "steps must be in (0, 90] and (0, 360]");
-    const int64_t units = std::max<int64_t>(n_dir, (int64_t)k * k) * ((p->S + kStationsPerUnit - 1) / kStationsPerUnit);
+    const int64_t units = std::max<int64_t>(n_dir, (int64_t)k * k) * p->S;  // at one station per workgroup
     if (units > (int64_t)0x7fffffff) return fail(AU_EINVAL, "too many work units");
     return AU_OK;
 }
@@ -2706,10 +2720,11 @@ static au_status run_fit(const au_table* tb, const au_event* ev, const EvParams&
                        : launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
     const double dt_ns = 1e9 / (double)ev->fs_hz;
-    const int chunks = (p.S + kStationsPerUnit - 1) / kStationsPerUnit;
     int64_t off = 0;
     for (int lv = 0; lv <= levels; ++lv) {
         const int nc = lv == 0 ? n_dir : k * k;
+        const int spw = env_spw(p.S, nc);
+        const int chunks = (p.S + spw - 1) / spw;
         double* cand = dirs + 2 * off;
         ev0.D = nc;
         if (tb->dtype == AU_F64)
@@ -2721,7 +2736,7 @@ static au_status run_fit(const au_table* tb, const au_event* ev, const EvParams&
         switch (p.N) {
 #define X_(NN)                                                                                       \
     case NN:                                                                                         \
-        e = launch_env_n<T, NN>(st, ev0, nc * chunks, X, M, (T*)nullptr, peak, arg, tw, nullptr); \
+        e = launch_env_n<T, NN>(st, ev0, spw, nc * chunks, X, M, (T*)nullptr, peak, arg, tw, nullptr); \
         break;
             AU_FOR_EACH_N(X_)
 #undef X_

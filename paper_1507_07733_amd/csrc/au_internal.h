@@ -25,7 +25,7 @@ namespace au {
 au_status set_error(au_status s, const std::string& msg);
 const std::string& error_string();
 
-constexpr int kStationsPerUnit = 8;
+constexpr int kStationsPerUnit = 16;
 
 struct EvParams {
     int S, N, k_lo, nb;
