@@ -630,7 +630,9 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, PAIR, PP>()))) void k_
 template <typename T>
 constexpr bool env_dual() { return sizeof(T) == 4; }
 template <typename T, int E>
-constexpr int env_twmode() { return env_dual<T>() && E <= 8 ? TW_REG : TW_TABLE; }
+constexpr int env_twmode() { return env_dual<T>() && E <= 8 ? TW_HYB : TW_TABLE; }
+template <typename T, int N, int E>
+constexpr int env_ltw() { return env_twmode<T, E>() == TW_HYB ? ltw_count<N, E, E>() : 0; }
 template <typename T>
 constexpr int env_bufs() { return env_dual<T>() ? 2 : 1; }
 
@@ -651,8 +653,13 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
     const int g = threadIdx.x / TT, t = threadIdx.x % TT;
     C2<T>* la = reinterpret_cast<C2<T>*>(smem) + g * env_bufs<T>() * lds_elems<N>();
     C2<T>* lb = DUAL ? la + lds_elems<N>() : la;
+    C2<T>* ltw = reinterpret_cast<C2<T>*>(smem) + G * env_bufs<T>() * lds_elems<N>();
     C2<T> w[tw_count<N, E, E, TWM>()];
     load_twiddles<T, N, E, E, TWM, +1>(w, tw, t);
+    if constexpr (TWM == TW_HYB) {
+        fill_lds_twiddles<T, N, E, E, +1>(ltw, tw, threadIdx.x, blockDim.x);
+        lds_barrier();
+    }
     const int chunks = (ev0.S + spw - 1) / spw;
     const int d = blockIdx.x / chunks;
     const int s0 = (blockIdx.x - d * chunks) * spw, s1 = min(ev0.S, s0 + spw);
@@ -701,7 +708,7 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
             lds_barrier();
         }
         if constexpr (DUAL) {
-            fft2<T, N, E, +1, TWM, E>(x, xh, la, lb, tw, t, w);
+            fft2<T, N, E, +1, TWM, E>(x, xh, la, lb, tw, t, w, ltw);
         } else {
             fft<T, N, E, +1>(x, la, tw, t);
             fft<T, N, E, +1>(xh, la, tw, t);
@@ -2163,7 +2170,7 @@ static hipError_t launch_env_n(hipStream_t st, const EvDesc& ev0, int spw, int n
     constexpr int E = N >= 1024 ? 8 : (N < 16 ? N : 16);
     constexpr int TT = N / E;
     constexpr int G = groups_per_block<T, N, E, env_bufs<T>()>();
-    constexpr size_t LDS = (size_t)G * env_bufs<T>() * lds_elems<N>() * sizeof(C2<T>);
+    constexpr size_t LDS = ((size_t)G * env_bufs<T>() * lds_elems<N>() + env_ltw<T, N, E>()) * sizeof(C2<T>);
     hipLaunchKernelGGL((k_unfold_env<T, N, E>), dim3(n_units), dim3(G * TT), LDS, st, ev0, spw, X, M,
                        efield, peak, arg, tw, skip);
     return hipGetLastError();

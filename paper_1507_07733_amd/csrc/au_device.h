@@ -527,7 +527,7 @@ __device__ __forceinline__ void fft_pass_pp(C2<T> (&x)[E], C2<T>* __restrict__ l
 template <typename T, int N, int E, int RMAX, int TWMODE, int NS, int SIGN>
 __device__ __forceinline__ void fft_pass2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* __restrict__ la,
                                           C2<T>* __restrict__ lb, const C2<T>* __restrict__ tw,
-                                          const C2<T>* __restrict__ w, int t)
+                                          const C2<T>* __restrict__ w, int t, const C2<T>* __restrict__ ltw)
 {
     constexpr int R = pass_radix<N, RMAX>(NS);
     constexpr int TT = N / E;
@@ -552,6 +552,8 @@ __device__ __forceinline__ void fft_pass2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* _
                 C2<T> wr;
                 if constexpr (TWMODE == TW_TABLE)
                     wr = twiddle_tab<SIGN>(tw, r * k * STRIDE);
+                else if constexpr (TWMODE == TW_HYB && NS < TT)
+                    wr = ltw[ltw_offset<N, E, RMAX>(NS) + k * (R - 1) + r - 1];
                 else
                     wr = w[OFF + m * (R - 1) + r - 1];
                 u[r] = cmul(u[r], wr);
@@ -583,16 +585,17 @@ __device__ __forceinline__ void fft_pass2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* _
             y[i] = lb[lpad(t + TT * i)];
         }
         lds_barrier();
-        fft_pass2<T, N, E, RMAX, TWMODE, NS * R, SIGN>(x, y, la, lb, tw, w, t);
+        fft_pass2<T, N, E, RMAX, TWMODE, NS * R, SIGN>(x, y, la, lb, tw, w, t, ltw);
     }
 }
 
 template <typename T, int N, int E, int SIGN, int TWMODE, int RMAX>
 __device__ __forceinline__ void fft2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* __restrict__ la, C2<T>* __restrict__ lb,
-                                     const C2<T>* __restrict__ tw, int t, const C2<T>* __restrict__ w)
+                                     const C2<T>* __restrict__ tw, int t, const C2<T>* __restrict__ w,
+                                     const C2<T>* __restrict__ ltw = nullptr)
 {
     static_assert((N & (N - 1)) == 0 && N >= E && (E & (E - 1)) == 0 && RMAX <= 32, "sizes");
-    fft_pass2<T, N, E, (RMAX < E ? RMAX : E), TWMODE, 1, SIGN>(x, y, la, lb, tw, w, t);
+    fft_pass2<T, N, E, (RMAX < E ? RMAX : E), TWMODE, 1, SIGN>(x, y, la, lb, tw, w, t, ltw);
 }
 
 // Full transform with ping-pong buffers; the first exchange writes `la`.
