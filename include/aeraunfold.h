@@ -280,6 +280,9 @@ au_status au_pattern_response_quantized(const au_table* table, const au_event* e
  *   h_dirs: host [sum_e n_dirs[e]][2] degrees, event-major;
  *   volt_offset[e]: element offset of event e's [S][2][N] traces inside d_volt;
  *   efield_offset[e]: element offset of its [D][S][2][N] output inside d_efield.
+ * Offsets may alias: events may share input traces, and events whose output
+ * regions overlap write them in an unspecified order (a throughput run can
+ * recycle one output ring this way).
  * au_plan_create validates, sorts work longest-first, uploads the work lists
  * and allocates the plan's workspace (the only allocation; au_plan_run
  * allocates nothing).  flags: AU_PLAN_GRAPH to capture the launch sequence in

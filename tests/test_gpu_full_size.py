@@ -1,0 +1,135 @@
+"""Parity at the workloads' full sizes, in the launch configurations the
+benchmark times, on sampled outputs the oracle computes one by one:
+  - the plain FP64 direction scan: 1 event x 124 stations x 4096 float64
+    samples x 2048 directions (complex128 table, 1 MHz / 5 deg);
+  - the batched FP32 plan: 256 events, stations U{3..124}, N in {2048, 4096},
+    16 x 16 directions, complex64 table at 0.5 MHz / 1 deg, persistent +
+    XCD-aware + hipGraph (105 GB of output);
+  - the large batch: 10 000 events x 124 stations x 4096 float32 samples x
+    4 x 4 directions through the same plan form.  Its 650 GB of output exceed
+    HBM, so 9 900 events recycle one output ring (and 100 distinct input
+    events are shared round-robin); 100 events keep their own output slots
+    and are the ones sampled.
+FP64: per-trace r <= 1e-12; FP32: per station E-field trace r <= 1e-5 (both
+components, the larger peak) and per component where a component carries at
+least 10 % of the station's peak."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1507_07733_amd import synth as S
+
+from helpers import TOL_FP32, TOL_FP64, assert_traces_close, station_errors, trace_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    from paper_1507_07733_amd import api as A
+    A.lib()
+    torch.cuda.init()
+    return A
+
+
+def check_fp32_units(got, ref):
+    """got/ref [U][2][N]: the FP32 bar per station trace, and per component for the strong ones."""
+    rs = station_errors(got, ref)
+    assert rs.max() <= TOL_FP32, rs.max()
+    r = trace_errors(got, ref)
+    pk = np.max(np.abs(ref), axis=-1)
+    strong = pk >= 0.1 * pk.max(axis=-1, keepdims=True)
+    assert r[strong].max() <= TOL_FP32, r[strong].max()
+
+
+def test_plain_fp64_scan_full_size(api):
+    import torch
+    g = S.GRID_COARSE
+    t = S.pattern_table(g, cfg=1)
+    tab = api.Table(g, t)
+    s, n = 124, 4096
+    dirs = S.direction_grid(32, 64)
+    v = S.traces(s, n, cfg=1, event=0)
+    ev = api.make_event(s, n)
+    say("full size: plain fp64 scan 124 x 4096 x 2048")
+    out = api.unfold_direction_scan(tab, ev, torch.from_numpy(v).cuda(), dirs)
+    torch.cuda.synchronize()
+    r = np.random.default_rng(21)
+    units = np.stack([r.integers(0, len(dirs), 48), r.integers(0, s, 48)], 1)
+    units[:4] = [[0, 0], [len(dirs) - 1, s - 1], [1023, 61], [2047, 0]]
+    got = np.stack([out[d, st].cpu().numpy() for d, st in units])
+    del out
+    torch.cuda.empty_cache()
+    ref, _, _ = O.unfold(g, t, v, dirs, S.FS_HZ, S.BAND_LO_HZ, S.BAND_HI_HZ, units=units)
+    assert_traces_close(got, ref, TOL_FP64, "plain fp64 scan, sampled units")
+
+
+def _batched_check(api, g, t32, specs, plan, volt_host, out, events, per_event, seed):
+    r = np.random.default_rng(seed)
+    for e in events:
+        s, n, d = specs[e]
+        o = int(plan.volt_offsets[e])
+        v = volt_host[o:o + s * 2 * n].reshape(s, 2, n)
+        units = np.stack([r.integers(0, len(d), per_event), r.integers(0, s, per_event)], 1)
+        eo = plan.event_output(out, e)
+        got = np.stack([eo[di, si].cpu().numpy() for di, si in units])
+        ref, _, _ = O.unfold(g, t32.astype(np.complex128), v.astype(np.float64), d, S.FS_HZ, S.BAND_LO_HZ,
+                             S.BAND_HI_HZ, units=units)
+        check_fp32_units(got, ref)
+
+
+def test_batched_fp32_plan_full_size(api):
+    import torch
+    g = S.GRID_FINE
+    t32 = S.pattern_table(g, cfg=2).astype(np.complex64)
+    tab = api.Table(g, t32)
+    dirs = S.direction_grid(16, 16)
+    specs = [(e.n_stations, e.n_samples, dirs) for e in S.event_mix(256, cfg=2, dirs=dirs)]
+    plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=7)
+    volt = np.empty(plan.volt_elems, dtype=np.float32)
+    for e, (s, n, _) in enumerate(specs):
+        volt[plan.volt_offsets[e]:plan.volt_offsets[e] + s * 2 * n] = S.traces(s, n, cfg=2, event=e,
+                                                                              dtype=np.float32).ravel()
+    say("full size: batched fp32 plan, 256 events, %d station-unfolds" % plan.station_unfolds)
+    dv = torch.from_numpy(volt).cuda()
+    out = torch.empty(plan.efield_elems, dtype=torch.float32, device="cuda")
+    plan.run(dv, out)
+    plan.run(dv, out)               # a graph replay
+    torch.cuda.synchronize()
+    _batched_check(api, g, t32, specs, plan, volt, out, [0, 17, 101, 200, 255], 6, seed=22)
+    del out, dv
+    torch.cuda.empty_cache()
+
+
+def test_large_batch_fp32_ring(api):
+    import torch
+    g = S.GRID_FINE
+    t32 = S.pattern_table(g, cfg=4).astype(np.complex64)
+    tab = api.Table(g, t32)
+    s, n, n_ev, n_inputs, n_kept, ring = 124, 4096, 10000, 100, 100, 100
+    dirs = S.direction_grid(4, 4)
+    specs = [(s, n, dirs)] * n_ev
+    vsz = s * 2 * n
+    esz = len(dirs) * s * 2 * n
+    volt_off = (np.arange(n_ev) % n_inputs).astype(np.int64) * vsz
+    # the first n_kept events own their output slots; the rest recycle a ring after them
+    eff = np.where(np.arange(n_ev) < n_kept, np.arange(n_ev), n_kept + (np.arange(n_ev) % ring)).astype(np.int64)
+    plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=7, volt_offsets=volt_off,
+                    efield_offsets=eff * esz)
+    assert plan.station_unfolds == n_ev * s * len(dirs)
+    volt = np.empty(n_inputs * vsz, dtype=np.float32)
+    for i in range(n_inputs):
+        volt[i * vsz:(i + 1) * vsz] = S.traces(s, n, cfg=4, event=i, dtype=np.float32).ravel()
+    say("full size: large batch 10000 x 124 x 4096 x 16 directions (ring of %d)" % ring)
+    dv = torch.from_numpy(volt).cuda()
+    out = torch.empty(plan.efield_elems, dtype=torch.float32, device="cuda")
+    plan.run(dv, out)
+    torch.cuda.synchronize()
+    _batched_check(api, g, t32, specs, plan, volt, out, [0, 37, 99], 8, seed=23)
+    del out, dv
+    torch.cuda.empty_cache()
