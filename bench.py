@@ -268,7 +268,7 @@ def reconstruction_latency(api, synth, tab64, tab32, dev, n_events=8, n_st=124, 
     return out
 
 
-def direction_fit_latency(api, synth, tab64, dev, n_events=4, n_st=124, n=4096, levels=4, k=5):
+def direction_fit_latency(api, synth, tab64, dev, n_events=4, n_st=124, n=4096, levels=4, k=5, fp32=False):
     """Wall time per event of the device direction fit: 32 x 64 coarse candidates (the FP64 scan's grid)
     plus `levels` 5 x 5 refinements, on plane-wave events."""
     import torch
@@ -276,10 +276,14 @@ def direction_fit_latency(api, synth, tab64, dev, n_events=4, n_st=124, n=4096, 
     r = synth.rng(6, synth.STREAM_EVENTS)
     truth = np.stack([r.uniform(5.0, 65.0, n_events), r.uniform(0.0, 360.0, n_events)], 1)
     coarse = synth.direction_grid(32, 64)
-    ev = api.make_event(n_st, n)
+    if fp32:
+        ev = api.make_event(n_st, n, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32)
+    else:
+        ev = api.make_event(n_st, n)
+    dt = np.float32 if fp32 else np.float64
     work = torch.empty(api.direction_fit_workspace_bytes(tab64, ev, len(coarse), levels, k), dtype=torch.uint8,
                        device=dev)
-    vols = [torch.from_numpy(synth.plane_wave_traces(pos, n, z, a, cfg=6, event=i)[0]).to(dev)
+    vols = [torch.from_numpy(synth.plane_wave_traces(pos, n, z, a, cfg=6, event=i, dtype=dt)[0]).to(dev)
             for i, (z, a) in enumerate(truth)]
     step = (90.0 / 32, 360.0 / 64)
     api.direction_fit(tab64, ev, vols[0], pos, coarse, levels=levels, k=k, step=step, work=work)
@@ -296,8 +300,8 @@ def direction_fit_latency(api, synth, tab64, dev, n_events=4, n_st=124, n=4096, 
     su = (len(coarse) + levels * k * k) * n_st
     return {"ms_per_event": ms, "station_unfolds_per_event": su, "station_unfolds_per_s": su / (ms / 1e3),
             "max_angle_err_deg": float(np.max(err)), "events": n_events,
-            "workload": "FP64, %d plane-wave events, %d stations x %d samples, 32x64 candidates + %d levels of %dx%d"
-                        % (n_events, n_st, n, levels, k, k)}
+            "workload": "%s, %d plane-wave events, %d stations x %d samples, 32x64 candidates + %d levels of %dx%d"
+                        % ("FP32" if fp32 else "FP64", n_events, n_st, n, levels, k, k)}
 
 
 def serving_benchmark(api, synth, tab32, tab64, rate_hz=2000.0, duration_s=3.0, warm_s=0.5,
@@ -597,8 +601,11 @@ def main():
         del work, workf, v1f
         fp64["reconstruction"] = reconstruction_latency(api, synth, t1, tab, dev)
         fp64["direction_fit"] = direction_fit_latency(api, synth, t1, dev)
-        log("direction fit (124 x 4096, 2048 + 100 candidates): %.3f ms/event, max error %.3f deg"
-            % (fp64["direction_fit"]["ms_per_event"], fp64["direction_fit"]["max_angle_err_deg"]))
+        fp64["direction_fit_fp32"] = direction_fit_latency(api, synth, tab, dev, fp32=True)
+        log("direction fit (124 x 4096, 2048 + 100 candidates): fp64 %.3f ms/event, fp32 %.3f ms/event, "
+            "max error %.3f / %.3f deg"
+            % (fp64["direction_fit"]["ms_per_event"], fp64["direction_fit_fp32"]["ms_per_event"],
+               fp64["direction_fit"]["max_angle_err_deg"], fp64["direction_fit_fp32"]["max_angle_err_deg"]))
         log("reconstruction loop (124 stations x 4096): fp64 %.3f ms/event, fp32 %.3f ms/event"
             % (fp64["reconstruction"]["fp64"]["ms_per_event"], fp64["reconstruction"]["fp32"]["ms_per_event"]))
         torch.cuda.empty_cache()
