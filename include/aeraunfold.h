@@ -217,6 +217,32 @@ au_status au_reconstruct(const au_table* table, const au_event* ev, const void* 
                          void* stream);
 
 /*
+ * The reconstruction loop (as au_reconstruct) for n_events events at once:
+ * each step is one launch over all events and every event stops on its own
+ * (converged, out of passes, or degenerate geometry).  Common to all events:
+ * ev's n_samples, sampling rate, band, precision, trace type and thresholds
+ * (ev->n_stations is ignored).  Per event e: h_n_stations[e] >= 3 stations
+ * whose [S][2][N] traces start at element h_volt_offset[e] of d_volt (offsets
+ * may alias).  h_pos [sum S][2] ground positions in metres, events in order.
+ * Outputs (host; the call synchronises the stream):
+ *   h_dirs [n_events][max_iter][2] degrees, rows 0..h_n_dirs[e]-1 defined;
+ *   h_times [max_iter+1][sum S] int32 samples, the stations in event order,
+ *           rows 0..h_n_dirs[e] defined for the stations of event e;
+ *   h_n_dirs [n_events]; h_converged [n_events]: 1 converged, 0 ran out of
+ *           passes, -1 degenerate geometry (collinear or coincident).
+ * A result equals the one-event au_reconstruct of that event.  Workspace:
+ * au_reconstruct_batch_workspace_bytes, or NULL for the stream's pool.
+ */
+au_status au_reconstruct_batch_workspace_bytes(const au_table* table, const au_event* ev, int32_t n_events,
+                                               const int32_t* h_n_stations, const int64_t* h_volt_offset,
+                                               int32_t max_iter, uint64_t* bytes);
+au_status au_reconstruct_batch(const au_table* table, const au_event* ev, int32_t n_events,
+                               const int32_t* h_n_stations, const int64_t* h_volt_offset, const void* d_volt,
+                               const double* h_pos, int32_t max_iter, double* h_dirs, int32_t* h_times,
+                               int32_t* h_n_dirs, int32_t* h_converged, void* d_work, uint64_t work_bytes,
+                               void* stream);
+
+/*
  * Direction fit of one event over candidate directions (the reconstruction
  * repeats the E-field step per candidate, section 2; the paper names no
  * objective).  Per candidate d every station is unfolded for d and timed at

@@ -118,6 +118,12 @@ _SIG = {
                                      C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_double, C.c_double,
                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_int32), C.POINTER(C.c_double), _VP, C.c_uint64, _VP]),
+    "au_reconstruct_batch_workspace_bytes": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.POINTER(C.c_int32),
+                                                         C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_uint64)]),
+    "au_reconstruct_batch": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int64), _VP, C.POINTER(C.c_double), C.c_int32,
+                                         C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int32), _VP, C.c_uint64, _VP]),
     "au_reconstruct_workspace_bytes": (C.c_int32, [_VP, C.POINTER(AuEvent), C.c_int32, C.POINTER(C.c_uint64)]),
     "au_reconstruct": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.POINTER(C.c_double), C.c_int32,
                                    C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -409,6 +415,45 @@ def direction_fit(table: Table, ev: AuEvent, volt, positions, dirs, levels: int 
                                   best.ctypes.data_as(C.POINTER(C.c_int32)), res.ctypes.data_as(dp), wp, wb,
                                   _stream_handle(stream)))
     return {"result": res, "best": best, "chi2": chi2, "power": pw, "level_dirs": ld[:levels]}
+
+
+def reconstruct_batch(table: Table, ev: AuEvent, volt, n_stations, volt_offsets, positions, max_iter: int = 8,
+                      work=None, stream=None):
+    """The reconstruction loop for many events at once; see au_reconstruct_batch.
+
+    volt: flat device tensor holding every event's [S][2][N] traces at volt_offsets[e];
+    positions: [sum S][2].  Returns a list of Reconstruction (efield and peak None).
+    """
+    if not volt.is_cuda or not volt.is_contiguous() or trace_code(volt) != ev.trace_dtype:
+        raise ValueError("traces must be a contiguous device tensor of the event's trace type")
+    ns = np.ascontiguousarray(np.asarray(n_stations, dtype=np.int32))
+    vo = np.ascontiguousarray(np.asarray(volt_offsets, dtype=np.int64))
+    pos = np.ascontiguousarray(np.asarray(positions, dtype=np.float64).reshape(-1, 2))
+    n_ev = len(ns)
+    if len(vo) != n_ev or len(pos) != int(ns.sum()):
+        raise ValueError("one offset per event and one position per station")
+    if np.any(vo + ns.astype(np.int64) * 2 * ev.n_samples > volt.numel()):
+        raise ValueError("trace offsets exceed the trace buffer")
+    stot = int(ns.sum())
+    dirs = np.zeros((n_ev, max_iter, 2))
+    times = np.zeros((max_iter + 1, stot), dtype=np.int32)
+    nd = np.zeros(n_ev, dtype=np.int32)
+    conv = np.zeros(n_ev, dtype=np.int32)
+    i32 = C.POINTER(C.c_int32)
+    wp, wb = _work(work)
+    _check(lib().au_reconstruct_batch(table.handle, C.byref(ev), n_ev, ns.ctypes.data_as(i32),
+                                      vo.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(volt),
+                                      pos.ctypes.data_as(C.POINTER(C.c_double)), int(max_iter),
+                                      dirs.ctypes.data_as(C.POINTER(C.c_double)), times.ctypes.data_as(i32),
+                                      nd.ctypes.data_as(i32), conv.ctypes.data_as(i32), wp, wb,
+                                      _stream_handle(stream)))
+    out = []
+    so = 0
+    for e in range(n_ev):
+        k = int(nd[e])
+        out.append(Reconstruction(dirs[e, :k], times[:k + 1, so:so + ns[e]], int(conv[e]), None, None))
+        so += int(ns[e])
+    return out
 
 
 def pattern_response(table: Table, ev: AuEvent, dirs, device=None, stream=None, weight_bits: int = 0):

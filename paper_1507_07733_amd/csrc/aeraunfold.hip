@@ -639,14 +639,34 @@ constexpr int env_bufs() { return env_dual<T>() ? 2 : 1; }
 template <typename T, int N, int E>
 __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_env(
     EvDesc ev0, int spw, const XBin<T>* __restrict__ X, const MBin<T>* __restrict__ M, T* __restrict__ efield,
-    T* __restrict__ peak, int* __restrict__ arg, const C2<T>* __restrict__ tw, const int* __restrict__ skip)
+    T* __restrict__ peak, int* __restrict__ arg, const C2<T>* __restrict__ tw, const int* __restrict__ skip,
+    const EvDesc* __restrict__ evs, const int4* __restrict__ units, int skip_stride)
 {
     constexpr int TT = N / E;
     constexpr int G = groups_per_block<T, N, E, env_bufs<T>()>();
     constexpr int NW = (TT + 63) / 64;  // waves per group
     constexpr int TWM = env_twmode<T, E>();
     constexpr bool DUAL = env_dual<T>();
-    if (skip != nullptr && *skip) return;  // set by a converged reconstruction loop
+    // one event (ev0; workgroup = direction x chunk of spw stations), or many
+    // (units[b] = (event, direction, s0, s1) with descriptors evs[]; then
+    // ev.efield_off is the element offset of the event's [D][S][3] peak and
+    // sample block and no traces are stored)
+    int e = 0, d, s0, s1;
+    if (units != nullptr) {
+        const int4 u = units[blockIdx.x];
+        e = u.x;
+        d = u.y;
+        s0 = u.z;
+        s1 = u.w;
+    } else {
+        const int chunks = (ev0.S + spw - 1) / spw;
+        d = blockIdx.x / chunks;
+        s0 = (blockIdx.x - d * chunks) * spw;
+        s1 = min(ev0.S, s0 + spw);
+    }
+    if (skip != nullptr && skip[(int64_t)e * skip_stride]) return;  // set by a converged reconstruction loop
+    const EvDesc ev = units != nullptr ? evs[e] : ev0;
+    const int64_t pk_off = units != nullptr ? ev.efield_off : 0;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ T red_v[G][NW][3];
     __shared__ int red_i[G][NW][3];
@@ -660,15 +680,12 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
         fill_lds_twiddles<T, N, E, E, +1>(ltw, tw, threadIdx.x, blockDim.x);
         lds_barrier();
     }
-    const int chunks = (ev0.S + spw - 1) / spw;
-    const int d = blockIdx.x / chunks;
-    const int s0 = (blockIdx.x - d * chunks) * spw, s1 = min(ev0.S, s0 + spw);
-    const unsigned nb = (unsigned)ev0.nb, k_lo = (unsigned)ev0.k_lo;
-    const MBin<T>* __restrict__ Md = M + ev0.m_off + (int64_t)d * ev0.nb;
+    const unsigned nb = (unsigned)ev.nb, k_lo = (unsigned)ev.k_lo;
+    const MBin<T>* __restrict__ Md = M + ev.m_off + (int64_t)d * ev.nb;
     for (int base = s0; base < s1; base += G) {
         const int s = base + g;
         const bool active = s < s1;
-        const XBin<T>* __restrict__ Xs = X + ev0.x_off + (int64_t)s * ev0.nb;
+        const XBin<T>* __restrict__ Xs = X + ev.x_off + (int64_t)s * ev.nb;
         // the packed spectra: Z into la and Zh into lb at once (DUAL), or Z
         // then Zh through the one buffer
         C2<T> x[E], xh[E];
@@ -765,12 +782,12 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                     ix = oi;
                 }
             }
-            const int64_t o = ((int64_t)d * ev0.S + s) * 3 + c;
+            const int64_t o = pk_off + ((int64_t)d * ev.S + s) * 3 + c;
             peak[o] = v;
             arg[o] = ix;
         }
-        if (active && efield != nullptr) {
-            T* out = efield + ((int64_t)d * ev0.S + s) * 2 * N;
+        if (active && efield != nullptr && units == nullptr) {
+            T* out = efield + ((int64_t)d * ev.S + s) * 2 * N;
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 __builtin_nontemporal_store(x[i].re, out + t + TT * i);
@@ -2165,14 +2182,15 @@ static int env_spw(int S, int64_t n_dir)
 template <typename T, int N>
 static hipError_t launch_env_n(hipStream_t st, const EvDesc& ev0, int spw, int n_units, const XBin<T>* X,
                                const MBin<T>* M, T* efield, T* peak, int* arg, const C2<T>* tw,
-                               const int* skip = nullptr)
+                               const int* skip = nullptr, const EvDesc* evs = nullptr,
+                               const int4* units = nullptr, int skip_stride = 0)
 {
     constexpr int E = N >= 1024 ? 8 : (N < 16 ? N : 16);
     constexpr int TT = N / E;
     constexpr int G = groups_per_block<T, N, E, env_bufs<T>()>();
     constexpr size_t LDS = ((size_t)G * env_bufs<T>() * lds_elems<N>() + env_ltw<T, N, E>()) * sizeof(C2<T>);
     hipLaunchKernelGGL((k_unfold_env<T, N, E>), dim3(n_units), dim3(G * TT), LDS, st, ev0, spw, X, M,
-                       efield, peak, arg, tw, skip);
+                       efield, peak, arg, tw, skip, evs, units, skip_stride);
     return hipGetLastError();
 }
 
@@ -2323,10 +2341,15 @@ __device__ void block_sum(double (&v)[K])
 // with every operation rounded on its own (no contraction into fma), so the
 // decision is the one a plain double evaluation takes.  One block per station.
 template <typename Tin>
-__global__ __launch_bounds__(kBlock) void k_volt_timing(const Tin* __restrict__ volt, int N, int* __restrict__ t0)
+__global__ __launch_bounds__(kBlock) void k_volt_timing(const Tin* __restrict__ volt, int N, int* __restrict__ t0,
+                                                         const EvDesc* __restrict__ evs,
+                                                         const int2* __restrict__ units)
 {
 #pragma clang fp contract(off)
-    const Tin* __restrict__ v0 = volt + (int64_t)blockIdx.x * 2 * N;
+    // station blockIdx.x of one event, or units[blockIdx.x] = (event, station)
+    const Tin* __restrict__ v0 =
+        units != nullptr ? volt + evs[units[blockIdx.x].x].volt_off + (int64_t)units[blockIdx.x].y * 2 * N
+                         : volt + (int64_t)blockIdx.x * 2 * N;
     const Tin* __restrict__ v1 = v0 + N;
     double bv = -1.0;
     int bi = 0;
@@ -2347,19 +2370,34 @@ __global__ __launch_bounds__(kBlock) void k_volt_timing(const Tin* __restrict__ 
 // fitted by least squares about the centroid and the direction of arrival,
 // n = (-c p, -c q) on the ground, is written to dirs[it] and cur.  last: the
 // step after the final unfold, convergence check only.
+// Many events: workgroup e takes event e, whose stations are [so, so + S) of
+// the Stot stations (ev_st[e] = (so, S)), with state, cur and dirs
+// (max_iter directions) per event.  One event: ev_st == nullptr, Stot = S.
 __global__ __launch_bounds__(kBlock) void k_recon_step(int it, int last, int S, double dt_ns,
                                                         const double* __restrict__ pos,
                                                         const int* __restrict__ env_arg, int* __restrict__ hist,
                                                         double* __restrict__ dirs, double* __restrict__ cur,
-                                                        int* __restrict__ state)
+                                                        int* __restrict__ state, const int2* __restrict__ ev_st,
+                                                        int Stot, int max_iter)
 {
+    const int e = blockIdx.x;
+    int so = 0;
+    if (ev_st != nullptr) {
+        so = ev_st[e].x;
+        S = ev_st[e].y;
+    }
+    state += 4 * e;
+    cur += 2 * e;
+    dirs += (int64_t)2 * max_iter * e;
+    pos += 2 * (int64_t)so;
+    env_arg += 3 * (int64_t)so;
     if (state[0]) return;
-    int* __restrict__ row = hist + (int64_t)it * S;
+    int* __restrict__ row = hist + (int64_t)it * Stot + so;
     if (it > 0) {
         int changed = 0;
         for (int s = threadIdx.x; s < S; s += kBlock) {
             const int t = env_arg[3 * s + 2];
-            changed |= t != row[s - S];
+            changed |= t != row[s - Stot];
             row[s] = t;
         }
         changed = __syncthreads_or(changed);
@@ -2475,10 +2513,12 @@ static au_status run_reconstruct(const au_table* tb, const au_event* ev, const E
     hipError_t e;
     if (ev->trace_dtype == AU_F64) {
         e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
-        hipLaunchKernelGGL(k_volt_timing<double>, dim3(p.S), dim3(kBlock), 0, st, (const double*)d_volt, p.N, hist);
+        hipLaunchKernelGGL(k_volt_timing<double>, dim3(p.S), dim3(kBlock), 0, st, (const double*)d_volt, p.N, hist,
+                           (const EvDesc*)nullptr, (const int2*)nullptr);
     } else {
         e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
-        hipLaunchKernelGGL(k_volt_timing<float>, dim3(p.S), dim3(kBlock), 0, st, (const float*)d_volt, p.N, hist);
+        hipLaunchKernelGGL(k_volt_timing<float>, dim3(p.S), dim3(kBlock), 0, st, (const float*)d_volt, p.N, hist,
+                           (const EvDesc*)nullptr, (const int2*)nullptr);
     }
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("spectrum/timing: ") + hipGetErrorString(e));
@@ -2486,7 +2526,7 @@ static au_status run_reconstruct(const au_table* tb, const au_event* ev, const E
     for (int it = 0; it <= max_iter; ++it) {
         const int last = it == max_iter;
         hipLaunchKernelGGL(k_recon_step, dim3(1), dim3(kBlock), 0, st, it, last, p.S, dt_ns, (const double*)pos,
-                           (const int*)arg, hist, dirs, cur, state);
+                           (const int*)arg, hist, dirs, cur, state, (const int2*)nullptr, p.S, max_iter);
         if (last) break;
         if (tb->dtype == AU_F64)
             launch_coef<double, T>(st, tb, ev0, nullptr, nullptr, 1, cur, 0, 0, ev->fs_hz, ev->fallback_rel,
@@ -2815,6 +2855,243 @@ extern "C" au_status au_direction_fit(const au_table* tb, const au_event* ev, co
                               h_level_dirs, h_chi2, h_power, h_best, h_result)
             : run_fit<float>(tb, ev, p, d_volt, h_pos, n_dir, h_dirs, levels, k, step_zen, step_az, work, st,
                              h_level_dirs, h_chi2, h_power, h_best, h_result);
+    if (pooled) {
+        hipError_t e = hipFreeAsync(work, st);
+        if (s == AU_OK && e != hipSuccess)
+            return fail(AU_EDEVICE, std::string("hipFreeAsync: ") + hipGetErrorString(e));
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// the reconstruction loop over many events at once: every step is one launch
+// over all events (per-event stop flags), so the per-event launch and
+// synchronisation costs of the one-event form are paid once per batch
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct BatchReconLayout {
+    size_t x, m, hist, dirs, cur, state, pos, peak, arg, evs, sunits, cunits, eunits, evst, total;
+};
+
+BatchReconLayout batch_recon_layout(int prec, int64_t stot, int n_events, int nb, int max_iter, int64_t n_eunits)
+{
+    const size_t tsz = prec == AU_PREC_FP64 ? sizeof(double) : sizeof(float);
+    BatchReconLayout r;
+    r.x = align256((size_t)stot * nb * 4 * tsz + 1);
+    r.m = align256((size_t)n_events * nb * 8 * tsz + 1);
+    r.hist = align256((size_t)(max_iter + 1) * stot * sizeof(int32_t));
+    r.dirs = align256((size_t)n_events * max_iter * 2 * sizeof(double));
+    r.cur = align256((size_t)n_events * 2 * sizeof(double));
+    r.state = align256((size_t)n_events * 4 * sizeof(int32_t));
+    r.pos = align256((size_t)stot * 2 * sizeof(double));
+    r.peak = align256((size_t)stot * 3 * tsz);
+    r.arg = align256((size_t)stot * 3 * sizeof(int32_t));
+    r.evs = align256((size_t)n_events * sizeof(EvDesc));
+    r.sunits = align256((size_t)stot * sizeof(int2));
+    r.cunits = align256((size_t)n_events * sizeof(int2));
+    r.eunits = align256((size_t)n_eunits * sizeof(int4));
+    r.evst = align256((size_t)n_events * sizeof(int2));
+    r.total = r.x + r.m + r.hist + r.dirs + r.cur + r.state + r.pos + r.peak + r.arg + r.evs + r.sunits +
+              r.cunits + r.eunits + r.evst;
+    return r;
+}
+
+// Validates the batch; fills p (common sizes, S = the largest event), the
+// station total and the envelope unit count for its stations-per-workgroup.
+au_status check_recon_batch(const au_table* tb, const au_event* ev, int32_t n_events, const int32_t* h_ns,
+                            const int64_t* h_voff, int32_t max_iter, EvParams* p, int64_t* stot, int* spw,
+                            int64_t* n_eunits)
+{
+    if (!ev || !h_ns || !h_voff) return fail(AU_EINVAL, "null argument");
+    if (n_events < 1) return fail(AU_EINVAL, "n_events must be >= 1");
+    if (max_iter < 1 || max_iter > kMaxReconIter) return fail(AU_EINVAL, "max_iter must be in [1, 1024]");
+    int smax = 0;
+    int64_t tot = 0;
+    for (int32_t e = 0; e < n_events; ++e) {
+        if (h_ns[e] < 3) return fail(AU_EINVAL, "every event needs at least 3 stations");
+        if (h_voff[e] < 0) return fail(AU_EINVAL, "negative trace offset");
+        smax = std::max(smax, (int)h_ns[e]);
+        tot += h_ns[e];
+    }
+    if (tot > (int64_t)0x7fffffff / 4) return fail(AU_EINVAL, "too many stations");
+    au_event e1 = *ev;
+    e1.n_stations = smax;
+    au_status s = check_event(tb, &e1, p);
+    if (s != AU_OK) return s;
+    *stot = tot;
+    *spw = env_spw((int)std::min<int64_t>(tot, 0x7fffffff), 1);
+    int64_t nu = 0;
+    for (int32_t e = 0; e < n_events; ++e) nu += (h_ns[e] + *spw - 1) / *spw;
+    *n_eunits = nu;
+    return AU_OK;
+}
+
+}  // namespace
+
+template <typename T>
+static au_status run_reconstruct_batch(const au_table* tb, const au_event* ev, const EvParams& p, int32_t n_events,
+                                       const int32_t* h_ns, const int64_t* h_voff, const void* d_volt,
+                                       const double* h_pos, int max_iter, int64_t stot, int spw, int64_t n_eunits,
+                                       void* d_work, hipStream_t st, double* h_dirs, int32_t* h_times,
+                                       int32_t* h_n_dirs, int32_t* h_converged)
+{
+    const BatchReconLayout r = batch_recon_layout(ev->prec, stot, n_events, p.nb, max_iter, n_eunits);
+    unsigned char* q = (unsigned char*)d_work;
+    XBin<T>* X = (XBin<T>*)q;
+    MBin<T>* M = (MBin<T>*)(q += r.x);
+    int* hist = (int*)(q += r.m);
+    double* dirs = (double*)(q += r.hist);
+    double* cur = (double*)(q += r.dirs);
+    int* state = (int*)(q += r.cur);
+    double* pos = (double*)(q += r.state);
+    T* peak = (T*)(q += r.pos);
+    int* arg = (int*)(q += r.peak);
+    EvDesc* evs = (EvDesc*)(q += r.arg);
+    int2* sunits = (int2*)(q += r.evs);
+    int2* cunits = (int2*)(q += r.sunits);
+    int4* eunits = (int4*)(q += r.cunits);
+    int2* evst = (int2*)(q += r.eunits);
+    // descriptors, built on the host and copied once
+    std::vector<EvDesc> hevs((size_t)n_events);
+    std::vector<int2> hsu((size_t)stot), hcu((size_t)n_events), hst((size_t)n_events);
+    std::vector<int4> heu;
+    heu.reserve((size_t)n_eunits);
+    int64_t so = 0;
+    for (int32_t e = 0; e < n_events; ++e) {
+        EvDesc d{};
+        d.volt_off = h_voff[e];
+        d.efield_off = 3 * so;  // the event's [1][S][3] peak and sample block
+        d.x_off = so * p.nb;
+        d.m_off = (int64_t)e * p.nb;
+        d.dir_off = e;
+        d.S = h_ns[e];
+        d.N = p.N;
+        d.D = 1;
+        d.k_lo = p.k_lo;
+        d.nb = p.nb;
+        hevs[(size_t)e] = d;
+        for (int s = 0; s < h_ns[e]; ++s) hsu[(size_t)(so + s)] = int2{e, s};
+        for (int s0 = 0; s0 < h_ns[e]; s0 += spw) heu.push_back(int4{e, 0, s0, std::min((int)h_ns[e], s0 + spw)});
+        hcu[(size_t)e] = int2{e, 0};
+        hst[(size_t)e] = int2{(int)so, h_ns[e]};
+        so += h_ns[e];
+    }
+    HIP_TRY(hipMemcpyAsync(evs, hevs.data(), hevs.size() * sizeof(EvDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(sunits, hsu.data(), hsu.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(cunits, hcu.data(), hcu.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(eunits, heu.data(), heu.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(evst, hst.data(), hst.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(pos, h_pos, sizeof(double) * 2 * stot, hipMemcpyHostToDevice, st));
+    const int zero_blocks = (int)((4 * (int64_t)n_events + 255) / 256);
+    hipLaunchKernelGGL(k_zero_u32, dim3(zero_blocks), dim3(256), 0, st, (unsigned int*)state, 4 * n_events);
+    EvDesc ev0{};
+    ev0.N = p.N;
+    ev0.k_lo = p.k_lo;
+    ev0.nb = p.nb;
+    const C2<T>* tw = twiddles<T>(tb->device);
+    if (tw == nullptr) return fail(AU_EDEVICE, "twiddle tables missing on this device");
+    hipError_t e;
+    if (ev->trace_dtype == AU_F64) {
+        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, evs, sunits, (int)stot, X, tw);
+        hipLaunchKernelGGL(k_volt_timing<double>, dim3((unsigned)stot), dim3(kBlock), 0, st, (const double*)d_volt,
+                           p.N, hist, (const EvDesc*)evs, (const int2*)sunits);
+    } else {
+        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, evs, sunits, (int)stot, X, tw);
+        hipLaunchKernelGGL(k_volt_timing<float>, dim3((unsigned)stot), dim3(kBlock), 0, st, (const float*)d_volt,
+                           p.N, hist, (const EvDesc*)evs, (const int2*)sunits);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("spectrum/timing: ") + hipGetErrorString(e));
+    const double dt_ns = 1e9 / (double)ev->fs_hz;
+    for (int it = 0; it <= max_iter; ++it) {
+        const int last = it == max_iter;
+        hipLaunchKernelGGL(k_recon_step, dim3(n_events), dim3(kBlock), 0, st, it, last, 0, dt_ns, (const double*)pos,
+                           (const int*)arg, hist, dirs, cur, state, (const int2*)evst, (int)stot, max_iter);
+        if (last) break;
+        if (tb->dtype == AU_F64)
+            launch_coef<double, T>(st, tb, ev0, evs, cunits, n_events, cur, 0, 0, ev->fs_hz, ev->fallback_rel,
+                                   ev->singular_rel, M, nullptr);
+        else
+            launch_coef<float, T>(st, tb, ev0, evs, cunits, n_events, cur, 0, 0, ev->fs_hz, ev->fallback_rel,
+                                  ev->singular_rel, M, nullptr);
+        switch (p.N) {
+#define X_(NN)                                                                                          \
+    case NN:                                                                                            \
+        e = launch_env_n<T, NN>(st, ev0, spw, (int)n_eunits, X, M, (T*)nullptr, peak, arg, tw,          \
+                                (const int*)state, (const EvDesc*)evs, (const int4*)eunits, 4);         \
+        break;
+            AU_FOR_EACH_N(X_)
+#undef X_
+            default: e = hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return fail(AU_EDEVICE, std::string("reconstruction step: ") + hipGetErrorString(e));
+    }
+    std::vector<int32_t> hstate((size_t)n_events * 4);
+    HIP_TRY(hipMemcpyAsync(hstate.data(), state, sizeof(int32_t) * 4 * n_events, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h_dirs, dirs, sizeof(double) * 2 * max_iter * (size_t)n_events, hipMemcpyDeviceToHost,
+                           st));
+    HIP_TRY(hipMemcpyAsync(h_times, hist, sizeof(int32_t) * (size_t)(max_iter + 1) * stot, hipMemcpyDeviceToHost,
+                           st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int32_t k = 0; k < n_events; ++k) {
+        h_n_dirs[k] = hstate[4 * (size_t)k + 1];
+        h_converged[k] = hstate[4 * (size_t)k + 3] ? -1 : hstate[4 * (size_t)k + 2];
+    }
+    return AU_OK;
+}
+
+extern "C" au_status au_reconstruct_batch_workspace_bytes(const au_table* tb, const au_event* ev, int32_t n_events,
+                                                          const int32_t* h_n_stations, const int64_t* h_volt_offset,
+                                                          int32_t max_iter, uint64_t* bytes)
+{
+    if (!bytes) return fail(AU_EINVAL, "null argument");
+    EvParams p;
+    int64_t stot = 0, nu = 0;
+    int spw = 1;
+    au_status s = check_recon_batch(tb, ev, n_events, h_n_stations, h_volt_offset, max_iter, &p, &stot, &spw, &nu);
+    if (s != AU_OK) return s;
+    *bytes = batch_recon_layout(ev->prec, stot, n_events, p.nb, max_iter, nu).total;
+    return AU_OK;
+}
+
+extern "C" au_status au_reconstruct_batch(const au_table* tb, const au_event* ev, int32_t n_events,
+                                          const int32_t* h_n_stations, const int64_t* h_volt_offset,
+                                          const void* d_volt, const double* h_pos, int32_t max_iter,
+                                          double* h_dirs, int32_t* h_times, int32_t* h_n_dirs,
+                                          int32_t* h_converged, void* d_work, uint64_t work_bytes, void* stream)
+{
+    EvParams p;
+    int64_t stot = 0, nu = 0;
+    int spw = 1;
+    au_status s = check_recon_batch(tb, ev, n_events, h_n_stations, h_volt_offset, max_iter, &p, &stot, &spw, &nu);
+    if (s != AU_OK) return s;
+    if (!d_volt || !h_pos || !h_dirs || !h_times || !h_n_dirs || !h_converged) return fail(AU_EINVAL, "null argument");
+    for (int64_t i = 0; i < 2 * stot; ++i)
+        if (!std::isfinite(h_pos[i]) || std::fabs(h_pos[i]) > 1e7)
+            return fail(AU_EINVAL, "station positions must be finite and within 1e7 m");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != tb->device) return fail(AU_EINVAL, "table lives on another device");
+    const BatchReconLayout r = batch_recon_layout(ev->prec, stot, n_events, p.nb, max_iter, nu);
+    hipStream_t st = (hipStream_t)stream;
+    void* work = d_work;
+    bool pooled = false;
+    if (work == nullptr) {
+        hipError_t e = hipMallocAsync(&work, r.total, st);
+        if (e != hipSuccess) return fail(AU_ENOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        pooled = true;
+    } else if (work_bytes < r.total) {
+        return fail(AU_ENOMEM, "workspace smaller than au_reconstruct_batch_workspace_bytes");
+    }
+    s = ev->prec == AU_PREC_FP64
+            ? run_reconstruct_batch<double>(tb, ev, p, n_events, h_n_stations, h_volt_offset, d_volt, h_pos,
+                                            max_iter, stot, spw, nu, work, st, h_dirs, h_times, h_n_dirs,
+                                            h_converged)
+            : run_reconstruct_batch<float>(tb, ev, p, n_events, h_n_stations, h_volt_offset, d_volt, h_pos,
+                                           max_iter, stot, spw, nu, work, st, h_dirs, h_times, h_n_dirs,
+                                           h_converged);
     if (pooled) {
         hipError_t e = hipFreeAsync(work, st);
         if (s == AU_OK && e != hipSuccess)

@@ -58,6 +58,8 @@ def test_validation_without_device(lib):
     assert lib.au_direction_fit(None, C.byref(ev), None, None, 4, None, 1, 3, 1.0, 1.0, None, None, None, None,
                                 None, None, 0, None) == api.AU_EINVAL
     assert lib.au_pattern_response_quantized(None, C.byref(ev), 1, None, 8, None, None) == api.AU_EINVAL
+    assert lib.au_reconstruct_batch(None, C.byref(ev), 0, None, None, None, None, 4, None, None, None, None, None,
+                                    0, None) == api.AU_EINVAL
     assert lib.au_free_pattern_table(None) == api.AU_OK
 
 

@@ -139,3 +139,59 @@ def test_reconstruct_rejects_degenerate_geometry(api):
         api.reconstruct(tab, ev, torch.from_numpy(v).cuda(), bad, max_iter=4)
     with pytest.raises(api.AuError):
         api.reconstruct(tab, ev, torch.from_numpy(v).cuda(), pos, max_iter=0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_reconstruct_batch_equals_single(api, prec):
+    """Many events in one call (uneven station counts, a shared input, a degenerate layout): every
+    event's directions, times, pass count and stop reason equal the one-event loop's, bitwise."""
+    import torch
+    f32 = prec == "fp32"
+    g = S.GRID_COARSE
+    t = S.pattern_table(g, cfg=0)
+    if f32:
+        t = t.astype(np.complex64)
+    tab = api.Table(g, t)
+    n = 2048
+    dt = np.float32 if f32 else np.float64
+    cases = [(40, 1.9, 35.0, 120.0), (124, 6.0, 20.0, 10.0), (3, 0.01, 30.0, 45.0), (17, 0.8, 50.0, 300.0),
+             (60, 2.9, 10.0, 200.0)]
+    pos_l, vol_l = [], []
+    for i, (ns, area, z, a) in enumerate(cases):
+        p = S.station_positions(ns, area_km2=area)
+        v, _ = S.plane_wave_traces(p, n, z, a, cfg=8, event=i, dtype=dt)
+        pos_l.append(p)
+        vol_l.append(v)
+    # event 5 reuses event 1's traces; event 6 has collinear stations
+    pos_l.append(pos_l[1])
+    col = np.stack([np.linspace(0, 400, 5), np.linspace(0, 200, 5)], 1)
+    pos_l.append(col)
+    vol_l.append(S.traces(5, n, cfg=8, event=9, dtype=dt))
+    ns = [len(p) for p in pos_l]
+    offs, flat, o = [], [], 0
+    for i in range(len(ns)):
+        if i == 5:
+            offs.append(offs[1])
+            continue
+        v = vol_l[i if i < 5 else 5]
+        offs.append(o)
+        flat.append(v.ravel())
+        o += v.size
+    volt = torch.from_numpy(np.concatenate(flat)).cuda()
+    ev = api.make_event(3, n, prec=api.AU_PREC_FP32 if f32 else api.AU_PREC_FP64,
+                        trace_dtype=api.AU_F32 if f32 else api.AU_F64)
+    say("reconstruct batch", prec, "events", len(ns))
+    res = api.reconstruct_batch(tab, ev, volt, ns, offs, np.concatenate(pos_l), max_iter=6)
+    for i, r in enumerate(res):
+        evi = api.make_event(ns[i], n, prec=ev.prec, trace_dtype=ev.trace_dtype)
+        vi = volt[offs[i]:offs[i] + ns[i] * 2 * n].view(ns[i], 2, n)
+        if i == 6:
+            assert r.converged == -1
+            with pytest.raises(api.AuError):
+                api.reconstruct(tab, evi, vi, pos_l[i], max_iter=6)
+            continue
+        one = api.reconstruct(tab, evi, vi, pos_l[i], max_iter=6)
+        assert np.array_equal(r.dirs, one.dirs), i
+        assert np.array_equal(r.times, one.times), i
+        assert r.converged == int(one.converged), i
+    assert np.array_equal(res[5].dirs, res[1].dirs) and np.array_equal(res[5].times, res[1].times)
