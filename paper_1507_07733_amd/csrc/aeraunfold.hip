@@ -623,18 +623,20 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, PAIR, PP>()))) void k_
 // env = sqrt(e^2 + H(e)^2) is reduced to its maximum and the first sample
 // attaining it, per component.  Optionally the traces are stored too.  A
 // non-null skip flag that reads nonzero turns the launch into a no-op.
-// Shape of the envelope kernel.  FP32: the two transforms run in lockstep
-// (fft2) through two LDS buffers with twiddles in registers.  FP64: the
-// registers do not hold two 8-value transforms, so they run one after the
-// other through one buffer with table twiddles.
-template <typename T>
-constexpr bool env_dual() { return sizeof(T) == 4; }
+// Shape of the envelope kernel.  FP32, and FP64 at 8 values per thread: the
+// two transforms run in lockstep (fft2) through two LDS buffers, with the
+// early passes' twiddles from the LDS table and the rest in registers
+// (TW_HYB) at 8 values per thread.  FP64 at 16 values per thread (N < 1024):
+// the registers do not hold two transforms, so they run one after the other
+// through one buffer with table twiddles.
 template <typename T, int E>
-constexpr int env_twmode() { return env_dual<T>() && E <= 8 ? TW_HYB : TW_TABLE; }
+constexpr bool env_dual() { return sizeof(T) == 4 || E <= 8; }
+template <typename T, int E>
+constexpr int env_twmode() { return env_dual<T, E>() && E <= 8 ? TW_HYB : TW_TABLE; }
 template <typename T, int N, int E>
 constexpr int env_ltw() { return env_twmode<T, E>() == TW_HYB ? ltw_count<N, E, E>() : 0; }
-template <typename T>
-constexpr int env_bufs() { return env_dual<T>() ? 2 : 1; }
+template <typename T, int E>
+constexpr int env_bufs() { return env_dual<T, E>() ? 2 : 1; }
 
 template <typename T, int N, int E>
 __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_env(
@@ -643,10 +645,10 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
     const EvDesc* __restrict__ evs, const int4* __restrict__ units, int skip_stride)
 {
     constexpr int TT = N / E;
-    constexpr int G = groups_per_block<T, N, E, env_bufs<T>()>();
+    constexpr int G = groups_per_block<T, N, E, env_bufs<T, E>()>();
     constexpr int NW = (TT + 63) / 64;  // waves per group
     constexpr int TWM = env_twmode<T, E>();
-    constexpr bool DUAL = env_dual<T>();
+    constexpr bool DUAL = env_dual<T, E>();
     // one event (ev0; workgroup = direction x chunk of spw stations), or many
     // (units[b] = (event, direction, s0, s1) with descriptors evs[]; then
     // ev.efield_off is the element offset of the event's [D][S][3] peak and
@@ -671,9 +673,9 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
     __shared__ T red_v[G][NW][3];
     __shared__ int red_i[G][NW][3];
     const int g = threadIdx.x / TT, t = threadIdx.x % TT;
-    C2<T>* la = reinterpret_cast<C2<T>*>(smem) + g * env_bufs<T>() * lds_elems<N>();
+    C2<T>* la = reinterpret_cast<C2<T>*>(smem) + g * env_bufs<T, E>() * lds_elems<N>();
     C2<T>* lb = DUAL ? la + lds_elems<N>() : la;
-    C2<T>* ltw = reinterpret_cast<C2<T>*>(smem) + G * env_bufs<T>() * lds_elems<N>();
+    C2<T>* ltw = reinterpret_cast<C2<T>*>(smem) + G * env_bufs<T, E>() * lds_elems<N>();
     C2<T> w[tw_count<N, E, E, TWM>()];
     load_twiddles<T, N, E, E, TWM, +1>(w, tw, t);
     if constexpr (TWM == TW_HYB) {
@@ -2187,8 +2189,8 @@ static hipError_t launch_env_n(hipStream_t st, const EvDesc& ev0, int spw, int n
 {
     constexpr int E = N >= 1024 ? 8 : (N < 16 ? N : 16);
     constexpr int TT = N / E;
-    constexpr int G = groups_per_block<T, N, E, env_bufs<T>()>();
-    constexpr size_t LDS = ((size_t)G * env_bufs<T>() * lds_elems<N>() + env_ltw<T, N, E>()) * sizeof(C2<T>);
+    constexpr int G = groups_per_block<T, N, E, env_bufs<T, E>()>();
+    constexpr size_t LDS = ((size_t)G * env_bufs<T, E>() * lds_elems<N>() + env_ltw<T, N, E>()) * sizeof(C2<T>);
     hipLaunchKernelGGL((k_unfold_env<T, N, E>), dim3(n_units), dim3(G * TT), LDS, st, ev0, spw, X, M,
                        efield, peak, arg, tw, skip, evs, units, skip_stride);
     return hipGetLastError();
