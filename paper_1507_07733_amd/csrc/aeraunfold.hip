@@ -367,13 +367,20 @@ __device__ __forceinline__ void stage_bin(C2<T>* __restrict__ lds, unsigned k, c
 // Minimum waves per SIMD the register allocator must leave room for: the
 // FP32 shapes with 8 values per thread and two LDS buffers or paired lanes
 // fit in 128 VGPRs (four waves per SIMD, the same as the plain 8-value shape)
-// without spilling; unconstrained they take 129-130 and drop to three.
-template <typename T, int E, bool PAIR, bool PP>
-constexpr int unfold_min_waves() { return (sizeof(T) == 4 && E == 8 && (PAIR || PP)) ? 4 : 1; }
+// without spilling; unconstrained they take 129-130 and drop to three.  The
+// FP64 8-value shape with hybrid twiddles and one buffer fits in 128 too
+// (unconstrained 142: three waves, one 8-wave workgroup per CU; at four, two).
+template <typename T, int E, int TWMODE, bool PAIR, bool PP>
+constexpr int unfold_min_waves()
+{
+    if (sizeof(T) == 4 && E == 8 && (PAIR || PP)) return 4;
+    if (sizeof(T) == 8 && E == 8 && TWMODE == TW_HYB && !PAIR && !PP) return 4;
+    return 1;
+}
 
 template <typename T, int N, int E, int RMAX, int TWMODE, bool WAVE, bool PAIR, bool PP>
 __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock)
-__attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, PAIR, PP>()))) void k_unfold(EvDesc ev0, const EvDesc* __restrict__ evs,
+__attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>()))) void k_unfold(EvDesc ev0, const EvDesc* __restrict__ evs,
                                                    const int4* __restrict__ units, int n_units,
                                                    int spw, const XBin<T>* __restrict__ X,
                                                    const MBin<T>* __restrict__ M,
