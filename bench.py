@@ -114,10 +114,18 @@ def cpu_baseline(grid, table_c64, specs, plan, volt_host, budget_s=12.0):
                 done += u
                 n_by[n] = n_by.get(n, 0) + u
     wall = time.perf_counter() - t0
+    # the same tasks on one thread, for the per-core rate
+    done1 = 0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < budget_s / 4:
+        done1 += task(i)[0]
+        i += 1
+    wall1 = time.perf_counter() - t1
     return {"value": done / wall, "unit": "station-unfolds/s", "cores": threads, "kind": "oracle",
             "sample": "%d random (event, direction, station) units of the batched workload "
                       "(%d at N=2048, %d at N=4096), FP64 on the float32 inputs, %.1f s wall on %d threads"
-                      % (done, n_by.get(2048, 0), n_by.get(4096, 0), wall, threads)}
+                      % (done, n_by.get(2048, 0), n_by.get(4096, 0), wall, threads),
+            "single_thread_value": done1 / wall1}
 
 
 def parity_sample(grid, table_c64, specs, plan, volt_host, efield, n_units=8):
@@ -544,12 +552,14 @@ def main():
     for _ in range(max(2, args.warmup)):
         gplan.run(volt, efield, counts)
     torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    marks[0].record(stream)
+    for k in range(args.steps):
         gplan.run(volt, efield, counts)
-    ev1.record(stream)
+        marks[k + 1].record(stream)
     torch.cuda.synchronize()
-    graph_ms = ev0.elapsed_time(ev1) / args.steps
+    graph_ms = marks[0].elapsed_time(marks[-1]) / args.steps
+    per_step = [marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps)]
     ms_per_step = graph_ms
     value = plan.station_unfolds / (graph_ms / 1e3)
     log("batched fp32 graph replay: %.3f ms/step, %.1f M station-unfolds/s" % (graph_ms, value / 1e6))
@@ -660,7 +670,8 @@ def main():
                                % len(specs),
                    "events": len(specs), "station_unfolds": int(plan.station_unfolds),
                    "plan_flags": args.flags | api.AU_PLAN_GRAPH, "timed": "hipGraph replay of the plan",
-                   "eager_ms_per_step": eager_ms, "autotuned": tuned},
+                   "eager_ms_per_step": eager_ms, "step_ms_median": float(np.median(per_step)),
+                   "step_ms_min": float(np.min(per_step)), "autotuned": tuned},
         "roofline": roofline,
         "fp64_plain": fp64,
         "serving": serving,
