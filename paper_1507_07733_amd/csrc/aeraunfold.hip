@@ -103,8 +103,37 @@ __device__ __forceinline__ C2<T> clerp(C2<T> a, C2<T> b, T t)
     return {s * a.re + t * b.re, s * a.im + t * b.im};
 }
 
-// Trilinear interpolation of the four (channel, component) entries: along
-// azimuth, then zenith, then frequency.  Table layout [f][z][a][4] complex.
+// The four (channel, component) entries at frequency node f, interpolated
+// along azimuth, then zenith (a direction's angular slice at that node).
+// Table layout [f][z][a][4] complex.
+template <typename Tt, typename T>
+__device__ __forceinline__ void slice4(const C2<Tt>* __restrict__ nodes, const GridDev& g, int f, int iz, T tz,
+                                       int ia, int ja, T ta, C2<T> out[4])
+{
+    C2<T> za[2][4];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+        const int64_t row = ((int64_t)f * g.n_zen + (iz + dz)) * g.n_az;
+        const C2<Tt>* p0 = nodes + (row + ia) * 4;
+        const C2<Tt>* p1 = nodes + (row + ja) * 4;
+#pragma unroll
+        for (int cp = 0; cp < 4; ++cp) {
+            const C2<T> a0{(T)p0[cp].re, (T)p0[cp].im};
+            const C2<T> a1{(T)p1[cp].re, (T)p1[cp].im};
+            za[dz][cp] = clerp(a0, a1, ta);
+        }
+    }
+#pragma unroll
+    for (int cp = 0; cp < 4; ++cp) out[cp] = clerp(za[0][cp], za[1][cp], tz);
+}
+
+// Frequency nodes a direction's angular slice may hold in LDS (the 30-80 MHz
+// band spans 52 nodes at 1 MHz, 102 at 0.5 MHz); wider bands interpolate per
+// bin from the table.
+constexpr int kMaxSliceNodes = 256;
+
+// Trilinear interpolation of the four entries: along azimuth, then zenith,
+// then frequency (between nodes ifr and ifr + 1).
 template <typename Tt, typename T>
 __device__ __forceinline__ void interp4(const C2<Tt>* __restrict__ nodes, const GridDev& g, int ifr,
                                         T tf, int iz, T tz, int ia, int ja, T ta, C2<T> h[4])
@@ -250,6 +279,25 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
     const T inv_n = (T)(1.0 / (double)ev.N);
     unsigned int n_fb = 0, n_sg = 0;
     MBin<T>* out = M + ev.m_off + (int64_t)d * ev.nb;
+    // The direction's angular slice (bilinear in azimuth and zenith) at every
+    // frequency node the band's bins fall between, once, in LDS; each bin then
+    // only interpolates in frequency between two slice nodes.  The same
+    // operations in the same order as interpolating every bin from the table.
+    __shared__ C2<T> sl[kMaxSliceNodes][4];
+    int f_lo = 0, n_nodes = 0;
+    if (ev.nb > 0) {
+        int f_hi;
+        double tdummy;
+        freq_cell(gd, (int64_t)ev.k_lo, ev.N, fs, f_lo, tdummy);
+        freq_cell(gd, (int64_t)(ev.k_lo + ev.nb - 1), ev.N, fs, f_hi, tdummy);
+        n_nodes = f_hi - f_lo + 2;
+    }
+    const bool use_slice = n_nodes > 0 && n_nodes <= kMaxSliceNodes;  // uniform over the workgroup
+    if (use_slice) {
+        for (int i = threadIdx.x; i < n_nodes; i += blockDim.x)
+            slice4<Tt, T>(nodes, gd, f_lo + i, iz, (T)tz, ia, ja, (T)ta, sl[i]);
+        __syncthreads();
+    }
     for (int j = threadIdx.x; j < ev.nb; j += blockDim.x) {
         int ifr;
         double tf;
@@ -258,7 +306,12 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
             if (wq > 0.0) tf = rint(tf * wq) / wq;
         }
         C2<T> h[4];
-        interp4<Tt, T>(nodes, gd, ifr, (T)tf, iz, (T)tz, ia, ja, (T)ta, h);
+        if (use_slice) {
+#pragma unroll
+            for (int cp = 0; cp < 4; ++cp) h[cp] = clerp(sl[ifr - f_lo][cp], sl[ifr + 1 - f_lo][cp], (T)tf);
+        } else {
+            interp4<Tt, T>(nodes, gd, ifr, (T)tf, iz, (T)tz, ia, ja, (T)ta, h);
+        }
         MBin<T> m;
         if constexpr (RESP) {
             m.m00 = h[0];
