@@ -394,6 +394,9 @@ __device__ __forceinline__ void touch(const C2<T>& v)
 // An LDS slot no pass ever reads: lpad() skips index 16 (i = 15 -> 15,
 // i = 16 -> 17).
 constexpr int kLdsPadSlot = 16;
+// Another slot no pass reads or writes (i = 31 -> 32, i = 32 -> 34), zeroed
+// once per block in every buffer: the gather reads it for out-of-band bins.
+constexpr int kLdsZeroSlot = 33;
 
 // One in-band bin of the packed spectrum: (E_theta, E_phi) = C X, stored as
 // Z[k] = E_theta + i E_phi and Z[N-k] = conj E_theta + i conj E_phi (only the
@@ -411,6 +414,15 @@ __device__ __forceinline__ void stage_bin(C2<T>* __restrict__ lds, unsigned k, c
         lds[lpad(k)] = C2<T>{et.re - ep.im, et.im + ep.re};
         lds[lpad(N - k)] = C2<T>{et.re + ep.im, ep.re - et.im};
     }
+}
+
+// Zero the zero slot of LDS buffer b of the block (G groups of one or two
+// buffers, buffer after buffer).
+template <typename T, int N>
+__device__ __forceinline__ void zero_slot_clear(unsigned char* smem, int b)
+{
+    static_assert(lds_elems<N>() > kLdsZeroSlot, "zero slot inside the buffer");
+    reinterpret_cast<C2<T>*>(smem)[b * lds_elems<N>() + kLdsZeroSlot] = C2<T>{0, 0};
 }
 
 #ifndef AU_UNFOLD_PF
@@ -451,7 +463,9 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
     __shared__ int sh_u;
     __shared__ int sh_list;
     static_assert(!PAIR || ((N / E) % 64 == 0 && E % 2 == 0), "paired lanes need whole wavefronts");
-    const int g = threadIdx.x / TT, t = fft_thread<TT, PAIR>(threadIdx.x % TT);
+    // g is stated as 0 with one group per block, so that the compiler treats
+    // the station and everything derived from it as uniform
+    const int g = G == 1 ? 0 : (int)(threadIdx.x / TT), t = fft_thread<TT, PAIR>(threadIdx.x % TT);
     // PP: two buffers per group; the staging exchange uses lds, the passes
     // alternate lds2, lds, ...
     C2<T>* lds = reinterpret_cast<C2<T>*>(smem) + g * (PP ? 2 : 1) * lds_elems<N>();
@@ -460,6 +474,9 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
     C2<T> w[tw_count<N, E, RMAX, TWMODE>()];
     load_twiddles<T, N, E, RMAX, TWMODE, +1>(w, tw, t);
     if constexpr (TWMODE == TW_HYB) fill_lds_twiddles<T, N, E, RMAX, +1>(ltw, tw, threadIdx.x, blockDim.x);
+    if constexpr (PF > 0) {  // (PF > 0 implies TW_HYB: the barrier below orders it)
+        if (threadIdx.x < (PP ? 2 : 1) * G) zero_slot_clear<T, N>(smem, threadIdx.x);
+    }
     // Wait for the twiddle loads here, once.  Left to the compiler, the wait
     // lands at their first use inside the station loop, where vector-memory
     // completions are counted in issue order: every station would then wait
@@ -534,9 +551,19 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
             for (int q = 0; q < PF; ++q) {
                 const unsigned j = min(tv + TT * q, nbv > 0 ? (int)nbv - 1 : 0);
                 const MBin<T>* pmq = nbv > 0 ? md + j : reinterpret_cast<const MBin<T>*>(safe);
-                const XBin<T>* pxq = nbv > 0 ? xe + (int64_t)sv * nbv + j : reinterpret_cast<const XBin<T>*>(safe);
                 pm[q] = *pmq;
-                px[q] = *pxq;
+                if constexpr (G == 1 && sizeof(XBin<T>) == 16) {
+                    // uniform station: the row as a buffer range (one record
+                    // of the twiddle table when the band is empty)
+                    const __amdgpu_buffer_rsrc_t xr =
+                        nbv > 0 ? buffer_range(xe + (int64_t)sv * nbv, nbv * (unsigned)sizeof(XBin<T>))
+                                : buffer_range(safe, (unsigned)sizeof(XBin<T>));
+                    px[q] = buffer_load16<XBin<T>>(xr, j * (unsigned)sizeof(XBin<T>));
+                } else {
+                    const XBin<T>* pxq =
+                        nbv > 0 ? xe + (int64_t)sv * nbv + j : reinterpret_cast<const XBin<T>*>(safe);
+                    px[q] = *pxq;
+                }
             }
         };
         if constexpr (PF > 0) {
@@ -638,7 +665,13 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
                     const unsigned k = t + TT * i;
                     const unsigned kk = (k <= N / 2) ? k : N - k;
                     const bool inb = active && (kk - k_lo) < nb;
-                    x[i] = inb ? lds[lpad(k)] : C2<T>{0, 0};
+                    // with the prefetch the registers are short: a zero slot
+                    // in place of a per-bin select (the compiler keeps the
+                    // eight addresses for the unit)
+                    if constexpr (PF > 0)
+                        x[i] = lds[inb ? lpad(k) : kLdsZeroSlot];
+                    else
+                        x[i] = inb ? lds[lpad(k)] : C2<T>{0, 0};
                 }
                 if constexpr (!PP) lds_sync<WAVE>();
             }
@@ -661,7 +694,18 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
             // issued after the stores would wait for every store to land.
             // Branch-free, clamped to a valid station and bin.
             if constexpr (PF > 0) prefetch_bins(Md, X + ev.x_off, min(s + G, s1 - 1), nb, tw, t);
-            if (G == 1 || active) {  // one group per block: its station is always active
+            if constexpr (G == 1) {
+                // one group per block: its station is always active and the
+                // trace base uniform
+                const __amdgpu_buffer_rsrc_t r = buffer_range(
+                    efield + ev.efield_off + ((int64_t)d * ev.S + s) * 2 * N, 2 * N * (unsigned)sizeof(T));
+                const unsigned toff = (unsigned)t * (unsigned)sizeof(T);
+#pragma unroll
+                for (int i = 0; i < E; ++i) {
+                    buffer_store_nt(x[i].re, r, toff, (int)(TT * i * sizeof(T)));
+                    buffer_store_nt(x[i].im, r, toff, (int)((N + TT * i) * sizeof(T)));
+                }
+            } else if (active) {
                 T* out = efield + ev.efield_off + ((int64_t)d * ev.S + s) * 2 * N;
 #pragma unroll
                 for (int i = 0; i < E; ++i) {

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace au {
 
 template <typename T>
@@ -344,6 +346,40 @@ __device__ __forceinline__ void fill_lds_twiddles(C2<T>* __restrict__ ltw, const
                                                   int nthr)
 {
     fill_lds_twiddles_from<T, N, E, (RMAX < E ? RMAX : E), 1, SIGN>(ltw, tw, tid, nthr);
+}
+
+// Buffer-resource access to one range the whole wavefront addresses alike (a
+// station's output trace, its spectrum row): the base sits in scalar
+// registers and each lane supplies a 32-bit byte offset, so the accesses
+// issue no per-lane 64-bit address arithmetic.  `bytes` bounds the range
+// (the hardware drops stores and zeroes loads whose lane offset is past it;
+// callers keep every offset inside it regardless).  Word 3 is the CDNA raw
+// buffer format: 32-bit data, no swizzle.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_range(const void* base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
+// cache-policy operand of the buffer builtins: streaming (non-temporal)
+constexpr int kBufNT = 2;
+
+__device__ __forceinline__ void buffer_store_nt(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, soff, kBufNT);
+}
+
+__device__ __forceinline__ void buffer_store_nt(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, int soff)
+{
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, soff, kBufNT);
+}
+
+// 16-byte record at byte offset voff of a buffer range.
+template <typename V>
+__device__ __forceinline__ V buffer_load16(__amdgpu_buffer_rsrc_t r, unsigned voff)
+{
+    static_assert(sizeof(V) == 16, "16-byte record");
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0));
 }
 
 // Workgroup barrier that orders LDS only.  The exchanges between FFT passes
