@@ -391,12 +391,7 @@ __device__ __forceinline__ void touch(const C2<T>& v)
     asm volatile("" ::"v"(v.re), "v"(v.im));
 }
 
-// An LDS slot no pass ever reads: lpad() skips index 16 (i = 15 -> 15,
-// i = 16 -> 17).
-constexpr int kLdsPadSlot = 16;
-// Another slot no pass reads or writes (i = 31 -> 32, i = 32 -> 34), zeroed
-// once per block in every buffer: the gather reads it for out-of-band bins.
-constexpr int kLdsZeroSlot = 33;
+
 
 // One in-band bin of the packed spectrum: (E_theta, E_phi) = C X, stored as
 // Z[k] = E_theta + i E_phi and Z[N-k] = conj E_theta + i conj E_phi (only the
@@ -416,13 +411,13 @@ __device__ __forceinline__ void stage_bin(C2<T>* __restrict__ lds, unsigned k, c
     }
 }
 
-// Zero the zero slot of LDS buffer b of the block (G groups of one or two
-// buffers, buffer after buffer).
+// Zero the spare zero slot of LDS buffer b of the block (G groups of one or
+// two buffers, buffer after buffer); no transform writes it, and the gather
+// reads it for out-of-band bins.
 template <typename T, int N>
 __device__ __forceinline__ void zero_slot_clear(unsigned char* smem, int b)
 {
-    static_assert(lds_elems<N>() > kLdsZeroSlot, "zero slot inside the buffer");
-    reinterpret_cast<C2<T>*>(smem)[b * lds_elems<N>() + kLdsZeroSlot] = C2<T>{0, 0};
+    reinterpret_cast<C2<T>*>(smem)[b * lds_elems<N>() + lds_zero_slot<N>()] = C2<T>{0, 0};
 }
 
 #ifndef AU_UNFOLD_PF
@@ -639,9 +634,9 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
                     // The first PF bins of this thread were loaded ahead (at
                     // the unit's start, or before the previous station's
                     // stores).  Branch-free: every lane computes them, and a
-                    // lane with nothing to write writes pad slot 16 (never
-                    // read), so that the only wait for these loads is the one
-                    // before their use.
+                    // lane with nothing to write writes the spare pad slot
+                    // (never read), so that the only wait for these loads is
+                    // the one before their use.
 #pragma unroll
                     for (int q = 0; q < PF; ++q) {
                         const unsigned j = t + TT * q;
@@ -653,8 +648,8 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
                         const C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
                         const C2<T> zk = k == 0 ? C2<T>{et.re, ep.re} : C2<T>{et.re - ep.im, et.im + ep.re};
                         const C2<T> zn{et.re + ep.im, ep.re - et.im};
-                        lds[ok ? lpad(k) : kLdsPadSlot] = zk;
-                        lds[(ok && k != 0) ? lpad(N - k) : kLdsPadSlot] = zn;
+                        lds[ok ? lpad(k) : lds_pad_slot<N>()] = zk;
+                        lds[(ok && k != 0) ? lpad(N - k) : lds_pad_slot<N>()] = zn;
                     }
                 } else if (active) {
                     for (unsigned j = t; j < nb; j += TT) stage_bin<T, N>(lds, k_lo + j, Md[j], Xs[j]);
@@ -669,7 +664,7 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
                     // in place of a per-bin select (the compiler keeps the
                     // eight addresses for the unit)
                     if constexpr (PF > 0)
-                        x[i] = lds[inb ? lpad(k) : kLdsZeroSlot];
+                        x[i] = lds[inb ? lpad(k) : lds_zero_slot<N>()];
                     else
                         x[i] = inb ? lds[lpad(k)] : C2<T>{0, 0};
                 }
