@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_spectrum(const Tin* __restrict__ vol
     constexpr int TT = N / E;
     constexpr int G = groups_per_block<T, N, E>();
     extern __shared__ __align__(16) unsigned char smem[];
-    const int g = threadIdx.x / TT, t = threadIdx.x % TT;
+    const int g = G == 1 ? 0 : (int)(threadIdx.x / TT), t = threadIdx.x % TT;
     C2<T>* lds = reinterpret_cast<C2<T>*>(smem) + g * lds_elems<N>();
     const int u = blockIdx.x * G + g;
     const bool active = u < n_units;
@@ -452,8 +452,10 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
     constexpr int TT = N / E;
     constexpr int G = groups_per_block<T, N, E, PP ? 2 : 1>();
     // bins per thread prefetched for the next station: the FP32 shapes whose
-    // early twiddles live in LDS have the registers for it
-    constexpr int PF = (sizeof(T) == 4 && TWMODE == TW_HYB && E <= 8 && !PAIR && !WAVE) ? AU_UNFOLD_PF : 0;
+    // early twiddles live in LDS have the registers for it; in FP64 the
+    // two-buffer shape, at two waves per SIMD (one workgroup per CU, which
+    // its LDS allows anyway)
+    constexpr int PF = (TWMODE == TW_HYB && E <= 8 && !PAIR && !WAVE && (sizeof(T) == 4 || PP)) ? AU_UNFOLD_PF : 0;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sh_u;
     __shared__ int sh_list;
@@ -720,7 +722,9 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
 // (Zh is the packed spectrum of the Hilbert transforms H(e_th) + i H(e_ph),
 // with H = IDFT(-i sgn(k) DFT)), both are inverse-transformed, and
 // env = sqrt(e^2 + H(e)^2) is reduced to its maximum and the first sample
-// attaining it, per component.  Optionally the traces are stored too.  A
+// attaining it, per component (decided on env^2, in the compute precision;
+// the peak is the root of the largest square).  Optionally the traces are
+// stored too.  A
 // non-null skip flag that reads nonzero turns the launch into a no-op.
 // Shape of the envelope kernel.  FP32, and FP64 at 8 values per thread: the
 // two transforms run in lockstep (fft2) through two LDS buffers, with the
@@ -771,7 +775,8 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ T red_v[G][NW][3];
     __shared__ int red_i[G][NW][3];
-    const int g = threadIdx.x / TT, t = threadIdx.x % TT;
+    // g stated as 0 with one group per block: per-station values stay uniform
+    const int g = G == 1 ? 0 : (int)(threadIdx.x / TT), t = threadIdx.x % TT;
     C2<T>* la = reinterpret_cast<C2<T>*>(smem) + g * env_bufs<T, E>() * lds_elems<N>();
     C2<T>* lb = DUAL ? la + lds_elems<N>() : la;
     C2<T>* ltw = reinterpret_cast<C2<T>*>(smem) + G * env_bufs<T, E>() * lds_elems<N>();
@@ -832,14 +837,16 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
             fft<T, N, E, +1>(xh, la, tw, t);
         }
         // per-thread maxima over its samples n = t + TT i (increasing in i) of
-        // the theta, phi and total-field envelopes
+        // the squared theta, phi and total-field envelopes: the square root is
+        // monotone, so it is taken once, of the largest square (a correctly
+        // rounded root per sample is some fifteen instructions)
         T bv[3] = {(T)-1, (T)-1, (T)-1};
         int bi[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const T p0 = x[i].re * x[i].re + xh[i].re * xh[i].re;
             const T p1 = x[i].im * x[i].im + xh[i].im * xh[i].im;
-            const T e[3] = {sqrt(p0), sqrt(p1), sqrt(p0 + p1)};
+            const T e[3] = {p0, p1, p0 + p1};
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 if (e[c] > bv[c]) {
@@ -884,7 +891,7 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                 }
             }
             const int64_t o = pk_off + ((int64_t)d * ev.S + s) * 3 + c;
-            peak[o] = v;
+            peak[o] = sqrt(v);
             arg[o] = ix;
         }
         if (active && efield != nullptr && units == nullptr) {
@@ -995,12 +1002,13 @@ static int ilog2(int n)
 }
 
 // Selected variant per [precision][log2 N]; the defaults are the shapes
-// that measured fastest on MI355X (from 1024 samples up: E=8 with the early
-// twiddles in LDS -- for double with one LDS buffer, for float with two and
-// the next station's bins prefetched; below, E=16 with register twiddles for
-// float and table twiddles for double).
+// that measured fastest on MI355X (from 1024 samples up, E=8 with two LDS
+// buffers: for float and for double at 2048 and 4096 samples the early
+// twiddles in LDS and the next station's bins prefetched, for double at 1024
+// register twiddles; below, E=16 with register twiddles for float and table
+// twiddles for double).
 static std::mutex g_var_mu;
-static int g_variant[2][13] = {{1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 13, 13, 13},
+static int g_variant[2][13] = {{1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10, 12, 12},
                                {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 12, 12, 12}};
 
 static int unfold_variant(int prec, int n)
