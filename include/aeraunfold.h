@@ -314,10 +314,10 @@ au_status au_pattern_response_quantized(const au_table* table, const au_event* e
  * allocates nothing).  flags: AU_PLAN_GRAPH to capture the launch sequence in
  * a hipGraph on first run (re-captured if d_volt / d_efield change),
  * AU_PLAN_PERSISTENT to run the unfold stage as a persistent kernel fed by an
- * atomic work counter, AU_PLAN_XCD to place all station chunks of one
- * (event, direction) on one of the 8 XCDs (8 unit lists balanced by work;
- * workgroup b takes units from list b mod 8, then steals) so that the
- * direction's coefficient row is fetched into one XCD's L2 only.
+ * atomic work counter, AU_PLAN_XCD to place all work units of one event on
+ * one of the 8 XCDs (8 unit lists balanced by work; workgroup b takes units
+ * from list b mod 8, then steals) so that the event's spectrum rows and its
+ * directions' coefficient rows are fetched into one XCD's L2 only.
  */
 #define AU_PLAN_GRAPH 1
 #define AU_PLAN_PERSISTENT 2

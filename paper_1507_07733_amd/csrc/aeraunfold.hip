@@ -481,12 +481,12 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
     vmem_wait_all();
     if constexpr (TWMODE == TW_HYB) lds_barrier();
     // XCD-aware placement (xcd_off != nullptr): the unit array holds 8 lists,
-    // list x = [xcd_off[x], xcd_off[x+1]), built so that all station chunks of
-    // one (event, direction) -- which share a coefficient row -- sit in one
-    // list.  Workgroups are dispatched round-robin over the 8 XCDs, so block b
-    // runs on XCD b mod 8 and takes its units from that list (persistent: from
-    // that list's counter, then from the other lists once it is empty), and
-    // the coefficient row is fetched into one XCD's L2 only.
+    // list x = [xcd_off[x], xcd_off[x+1]), built so that all units of one
+    // event -- which share its spectrum rows, and per direction a coefficient
+    // row -- sit in one list.  Workgroups are dispatched round-robin over the
+    // 8 XCDs, so block b runs on XCD b mod 8 and takes its units from that
+    // list (persistent: from that list's counter, then from the other lists
+    // once it is empty), and those rows are fetched into one XCD's L2 only.
     if (threadIdx.x == 0) sh_list = blockIdx.x & 7;
     for (int iter = 0;; ++iter) {
         int u;
@@ -1797,14 +1797,16 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
             }
         }
         if (b->flags & AU_PLAN_XCD) {
-            // all station chunks of one (event, direction) go to one of 8 lists,
-            // the list with the least work so far (work = stations)
+            // all units of one event (its directions' station chunks) go to one
+            // of 8 lists, the list with the least work so far (work =
+            // stations): the event's spectrum rows and each direction's
+            // coefficient row are then fetched into one XCD's L2 only
             std::vector<std::vector<int4>> lists(8);
             std::vector<int64_t> load(8, 0);
             for (size_t i = 0; i < c.uu.size();) {
                 size_t j = i;
                 int64_t work = 0;
-                while (j < c.uu.size() && c.uu[j].x == c.uu[i].x && c.uu[j].y == c.uu[i].y) {
+                while (j < c.uu.size() && c.uu[j].x == c.uu[i].x) {
                     work += c.uu[j].w - c.uu[j].z;
                     ++j;
                 }
