@@ -854,45 +854,90 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                     bi[c] = t + TT * i;
                 }
         }
-        // larger value wins; equal values: smaller sample index.  A group of
-        // TT < 64 threads shares its wave with other groups, so the butterfly
-        // stays within the group's TT lanes.
-        constexpr int kShfl = TT < 64 ? TT / 2 : 32;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            for (int off = kShfl; off >= 1; off >>= 1) {
-                const T ov = __shfl_xor(bv[c], off);
-                const int oi = __shfl_xor(bi[c], off);
-                if (ov > bv[c] || (ov == bv[c] && oi < bi[c])) {
-                    bv[c] = ov;
-                    bi[c] = oi;
-                }
-            }
-        }
-        const int wv = t >> 6;
-        if ((t & 63) == 0) {
+        // larger value wins; equal values: smaller sample index.
+        if constexpr (TT >= 256) {
+            // Three waves reduce one component each: every thread leaves its
+            // three candidates in the first buffer (the transforms' last
+            // gathers are behind a barrier, so it is free), then wave c scans
+            // component c (TT / 64 candidates per lane and a butterfly)
+            // while the other waves go on -- a fraction of the VALU work of a
+            // three-component butterfly in every wave.
+            T* cv = reinterpret_cast<T*>(la);
+            int* ci = reinterpret_cast<int*>(cv + 3 * TT);
+            static_assert(3 * TT * (sizeof(T) + sizeof(int)) <= lds_elems<N>() * sizeof(C2<T>), "scratch");
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                red_v[g][wv][c] = bv[c];
-                red_i[g][wv][c] = bi[c];
+                cv[c * TT + t] = bv[c];
+                ci[c * TT + t] = bi[c];
             }
-        }
-        lds_barrier();
-        // components c = t, t + TT, ... (a group of N = 16 or 32 has fewer than 3 threads)
-        for (int c = t; active && c < 3; c += TT) {
-            T v = red_v[g][0][c];
-            int ix = red_i[g][0][c];
-            for (int w2 = 1; w2 < NW; ++w2) {
-                const T ov = red_v[g][w2][c];
-                const int oi = red_i[g][w2][c];
-                if (ov > v || (ov == v && oi < ix)) {
-                    v = ov;
-                    ix = oi;
+            lds_barrier();
+            const int wv = t >> 6, lane = t & 63;
+            if (wv < 3 && active) {  // whole waves: no barrier inside
+                T v = cv[wv * TT + lane];
+                int ix = ci[wv * TT + lane];
+#pragma unroll
+                for (int k = lane + 64; k < TT; k += 64) {
+                    const T ov = cv[wv * TT + k];
+                    const int oi = ci[wv * TT + k];
+                    if (ov > v || (ov == v && oi < ix)) {
+                        v = ov;
+                        ix = oi;
+                    }
+                }
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const T ov = __shfl_xor(v, off);
+                    const int oi = __shfl_xor(ix, off);
+                    if (ov > v || (ov == v && oi < ix)) {
+                        v = ov;
+                        ix = oi;
+                    }
+                }
+                if (lane == 0) {
+                    const int64_t o = pk_off + ((int64_t)d * ev.S + s) * 3 + wv;
+                    peak[o] = sqrt(v);
+                    arg[o] = ix;
                 }
             }
-            const int64_t o = pk_off + ((int64_t)d * ev.S + s) * 3 + c;
-            peak[o] = sqrt(v);
-            arg[o] = ix;
+        } else {
+            // A group of TT < 64 threads shares its wave with other groups, so the
+            // butterfly stays within the group's TT lanes.
+            constexpr int kShfl = TT < 64 ? TT / 2 : 32;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                for (int off = kShfl; off >= 1; off >>= 1) {
+                    const T ov = __shfl_xor(bv[c], off);
+                    const int oi = __shfl_xor(bi[c], off);
+                    if (ov > bv[c] || (ov == bv[c] && oi < bi[c])) {
+                        bv[c] = ov;
+                        bi[c] = oi;
+                    }
+                }
+            }
+            const int wv = t >> 6;
+            if ((t & 63) == 0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    red_v[g][wv][c] = bv[c];
+                    red_i[g][wv][c] = bi[c];
+                }
+            }
+            lds_barrier();
+            // components c = t, t + TT, ... (a group of N = 16 or 32 has fewer than 3 threads)
+            for (int c = t; active && c < 3; c += TT) {
+                T v = red_v[g][0][c];
+                int ix = red_i[g][0][c];
+                for (int w2 = 1; w2 < NW; ++w2) {
+                    const T ov = red_v[g][w2][c];
+                    const int oi = red_i[g][w2][c];
+                    if (ov > v || (ov == v && oi < ix)) {
+                        v = ov;
+                        ix = oi;
+                    }
+                }
+                const int64_t o = pk_off + ((int64_t)d * ev.S + s) * 3 + c;
+                peak[o] = sqrt(v);
+                arg[o] = ix;
+            }
         }
         if (active && efield != nullptr && units == nullptr) {
             T* out = efield + ((int64_t)d * ev.S + s) * 2 * N;
