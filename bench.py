@@ -209,6 +209,28 @@ def fp32_error_report(api, plan, specs, efield, tab64, volt, dev):
 FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
+# Dynamic VALU instructions (wave-instructions) per station-unfold of the dominant kernel, from the
+# committed SQ_INSTS_VALU profile of the same build and workload, keyed like the traffic.
+PROFILED_VALU_INSTR = {
+    ("k_unfold<float, 4096, 8, 8, 3, false, false, true>", 2047488): 2870.5,
+}
+# wave64 VALU issue without packed FP32: one instruction per SIMD every 4 cycles, 1024 SIMDs at 2.4 GHz
+VALU_ISSUE_PEAK_GINSTR = 256 * 4 * 2.4e9 / 4 / 1e9
+
+
+def valu_issue_view(cls):
+    """The dominant launch against the VALU issue rate: profiled instructions per station-unfold x the
+    launch's station-unfolds over its time, against the nominal-clock issue limit (the chip runs this
+    kernel at 1.8-1.9 GHz, so the limit at the sustained clock is about 0.78 of the nominal one)."""
+    per = PROFILED_VALU_INSTR.get((cls["kernel"], cls["station_unfolds"]))
+    if per is None:
+        return None
+    achieved = per * cls["station_unfolds"] / (cls["unfold_ms"] / 1e3) / 1e9
+    return {"bound": "alu", "achieved": round(achieved, 1), "peak": round(VALU_ISSUE_PEAK_GINSTR, 1),
+            "unit": "G wave-instructions/s", "frac": round(achieved / VALU_ISSUE_PEAK_GINSTR, 4),
+            "instructions_per_unit": per, "source": PROFILED_TRAFFIC_SOURCE}
+
+
 def alu_view(cls):
     """The dominant launch against the vector ALU: algorithmic flops per station-unfold (inverse
     complex FFT at 5 N log2 N, plus 4 complex multiply-adds per in-band bin) over the launch time."""
@@ -586,7 +608,7 @@ def main():
                 "launch_ms": dom["unfold_ms"], "station_unfolds_per_launch": dom["station_unfolds"],
                 "measured_copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "per_class": per_class,
-                "alu": alu_view(dom)}
+                "alu": alu_view(dom), "valu_issue": valu_issue_view(dom)}
 
     # the timed step: the same plan captured in a hipGraph and replayed back to back
     gplan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=args.flags | api.AU_PLAN_GRAPH)
