@@ -161,8 +161,9 @@ __device__ __forceinline__ void interp4(const C2<Tt>* __restrict__ nodes, const 
     for (int cp = 0; cp < 4; ++cp) h[cp] = clerp(fz[0][cp], fz[1][cp], tf);
 }
 
-// Coefficients of the bin: (1/N) H^-1 = (1/(N det)) [h3 -h1; -h2 h0], with
-// H = [h0 h1; h2 h3] indexed [channel][component].  Returns 1 if singular.
+// Coefficients of the bin: C = (1/N) H^-1 = (1/(N det)) [h3 -h1; -h2 h0],
+// with H = [h0 h1; h2 h3] indexed [channel][component], in the packed form
+// of MBin (p_j = C_0j + i C_1j, q_j = C_0j - i C_1j).  Returns 1 if singular.
 template <typename T>
 __device__ __forceinline__ int invert2(const C2<T> h[4], T inv_n, double singular_rel, MBin<T>& m)
 {
@@ -173,16 +174,36 @@ __device__ __forceinline__ int invert2(const C2<T> h[4], T inv_n, double singula
     const T ad2 = det.re * det.re + det.im * det.im;
     const T thr = (T)singular_rel * fro2;
     if (!(ad2 > thr * thr)) {
-        m.m00 = m.m01 = m.m10 = m.m11 = C2<T>{0, 0};
+        m.p0 = m.p1 = m.q0 = m.q1 = C2<T>{0, 0};
         return 1;
     }
     const T sc = inv_n / ad2;
     const C2<T> inv{det.re * sc, -det.im * sc};
-    m.m00 = cmul(h[3], inv);
-    m.m01 = cmul(C2<T>{-h[1].re, -h[1].im}, inv);
-    m.m10 = cmul(C2<T>{-h[2].re, -h[2].im}, inv);
-    m.m11 = cmul(h[0], inv);
+    const C2<T> c00 = cmul(h[3], inv);
+    const C2<T> c01 = cmul(C2<T>{-h[1].re, -h[1].im}, inv);
+    const C2<T> c10 = cmul(C2<T>{-h[2].re, -h[2].im}, inv);
+    const C2<T> c11 = cmul(h[0], inv);
+    // c + i c' = (c.re - c'.im, c.im + c'.re); c - i c' = (c.re + c'.im, c.im - c'.re)
+    m.p0 = C2<T>{c00.re - c10.im, c00.im + c10.re};
+    m.p1 = C2<T>{c01.re - c11.im, c01.im + c11.re};
+    m.q0 = C2<T>{c00.re + c10.im, c00.im - c10.re};
+    m.q1 = C2<T>{c01.re + c11.im, c01.im - c11.re};
     return 0;
+}
+
+// The packed spectrum of one bin from its packed coefficients: zp = Z[k] and
+// zq = conj Z[N - k] (see MBin); at k = 0 the packed value is (E_theta.re,
+// E_phi.re) = ((zp + zq).re / 2, (zp - zq).im / 2).
+template <typename T>
+__device__ __forceinline__ void packed_bin(const MBin<T>& m, const XBin<T>& xb, C2<T>& zp, C2<T>& zq)
+{
+    zp = cadd(cmul(m.p0, xb.x0), cmul(m.p1, xb.x1));
+    zq = cadd(cmul(m.q0, xb.x0), cmul(m.q1, xb.x1));
+}
+template <typename T>
+__device__ __forceinline__ C2<T> packed_dc(const C2<T>& zp, const C2<T>& zq)
+{
+    return C2<T>{(T)0.5 * (zp.re + zq.re), (T)0.5 * (zp.im - zq.im)};
 }
 
 // ---------------------------------------------------------------------------
@@ -314,10 +335,10 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
         }
         MBin<T> m;
         if constexpr (RESP) {
-            m.m00 = h[0];
-            m.m01 = h[1];
-            m.m10 = h[2];
-            m.m11 = h[3];
+            m.p0 = h[0];
+            m.p1 = h[1];
+            m.q0 = h[2];
+            m.q1 = h[3];
         } else if constexpr (sizeof(T) == 4) {
             const C2<float> det = csub(cmul(h[0], h[3]), cmul(h[1], h[2]));
             float fro2 = 0.f;
@@ -332,10 +353,10 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
                 MBin<double> md;
                 n_sg += invert2<double>(hd, 1.0 / (double)ev.N, singular_rel, md);
                 ++n_fb;
-                m.m00 = C2<T>{(T)md.m00.re, (T)md.m00.im};
-                m.m01 = C2<T>{(T)md.m01.re, (T)md.m01.im};
-                m.m10 = C2<T>{(T)md.m10.re, (T)md.m10.im};
-                m.m11 = C2<T>{(T)md.m11.re, (T)md.m11.im};
+                m.p0 = C2<T>{(T)md.p0.re, (T)md.p0.im};
+                m.p1 = C2<T>{(T)md.p1.re, (T)md.p1.im};
+                m.q0 = C2<T>{(T)md.q0.re, (T)md.q0.im};
+                m.q1 = C2<T>{(T)md.q1.re, (T)md.q1.im};
             } else {
                 n_sg += invert2<T>(h, inv_n, singular_rel, m);
             }
@@ -393,21 +414,18 @@ __device__ __forceinline__ void touch(const C2<T>& v)
 
 
 
-// One in-band bin of the packed spectrum: (E_theta, E_phi) = C X, stored as
-// Z[k] = E_theta + i E_phi and Z[N-k] = conj E_theta + i conj E_phi (only the
-// real parts at k = 0).
+// One in-band bin of the packed spectrum: Z[k] = E_theta + i E_phi and
+// Z[N-k] = conj E_theta + i conj E_phi (only the real parts at k = 0).
 template <typename T, int N>
-__device__ __forceinline__ void stage_bin(C2<T>* __restrict__ lds, unsigned k, const MBin<T>& m, const XBin<T>& xb,
-                                          bool write = true)
+__device__ __forceinline__ void stage_bin(C2<T>* __restrict__ lds, unsigned k, const MBin<T>& m, const XBin<T>& xb)
 {
-    const C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
-    const C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
-    if (!write) return;
+    C2<T> zp, zq;
+    packed_bin(m, xb, zp, zq);
     if (k == 0) {
-        lds[0] = C2<T>{et.re, ep.re};
+        lds[0] = packed_dc(zp, zq);
     } else {
-        lds[lpad(k)] = C2<T>{et.re - ep.im, et.im + ep.re};
-        lds[lpad(N - k)] = C2<T>{et.re + ep.im, ep.re - et.im};
+        lds[lpad(k)] = zp;
+        lds[lpad(N - k)] = C2<T>{zq.re, -zq.im};
     }
 }
 
@@ -572,10 +590,10 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
             // flight.
 #pragma unroll
             for (int q = 0; q < PF; ++q) {
-                touch(pm[q].m00);
-                touch(pm[q].m01);
-                touch(pm[q].m10);
-                touch(pm[q].m11);
+                touch(pm[q].p0);
+                touch(pm[q].p1);
+                touch(pm[q].q0);
+                touch(pm[q].q1);
                 touch(px[q].x0);
                 touch(px[q].x1);
             }
@@ -588,43 +606,29 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
             if constexpr (PAIR) {
                 // registers i < E/2 hold bins k = t + TT i < N/2: solve them here;
                 // registers i >= E/2 hold the mirrors of the partner's (or, for
-                // t = 0 and TT/2, the lane's own) lower registers.
-                C2<T> eth[E / 2], eph[E / 2];
+                // t = 0 and TT/2, the lane's own) lower registers, Z[N - b] =
+                // conj zq(b).
+                C2<T> zqs[E / 2];
 #pragma unroll
                 for (int i = 0; i < E / 2; ++i) {
                     const unsigned k = t + TT * i;
                     const unsigned j = k - k_lo;
-                    C2<T> et{0, 0}, ep{0, 0};
+                    C2<T> zp{0, 0}, zq{0, 0};
                     if (active && j < nb) {
-                        const MBin<T> m = Md[j];
-                        const XBin<T> xb = Xs[j];
-                        et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
-                        ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
-                        if (k == 0) {
-                            et.im = 0;
-                            ep.im = 0;
-                        }
+                        packed_bin(Md[j], Xs[j], zp, zq);
+                        if (k == 0) zp = packed_dc(zp, zq);
                     }
-                    eth[i] = et;
-                    eph[i] = ep;
-                    x[i] = C2<T>{et.re - ep.im, et.im + ep.re};
+                    zqs[i] = zq;
+                    x[i] = zp;
                 }
                 const bool self0 = (t == 0), selfh = (t == TT / 2);
 #pragma unroll
                 for (int i = E / 2; i < E; ++i) {
                     const int jp = E - 1 - i;
-                    C2<T> et{__shfl_xor(eth[jp].re, 32), __shfl_xor(eth[jp].im, 32)};
-                    C2<T> ep{__shfl_xor(eph[jp].re, 32), __shfl_xor(eph[jp].im, 32)};
-                    if (selfh) {
-                        et = eth[jp];
-                        ep = eph[jp];
-                    }
-                    if (self0) {
-                        et = (i > E / 2) ? eth[E - i] : C2<T>{0, 0};
-                        ep = (i > E / 2) ? eph[E - i] : C2<T>{0, 0};
-                    }
-                    // Z[N - b] = conj E_th[b] + i conj E_ph[b]
-                    x[i] = C2<T>{et.re + ep.im, ep.re - et.im};
+                    C2<T> zq{__shfl_xor(zqs[jp].re, 32), __shfl_xor(zqs[jp].im, 32)};
+                    if (selfh) zq = zqs[jp];
+                    if (self0) zq = (i > E / 2) ? zqs[E - i] : C2<T>{0, 0};
+                    x[i] = C2<T>{zq.re, -zq.im};
                 }
             } else {
                 if constexpr (PF > 0) {
@@ -644,14 +648,13 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
                         const unsigned j = t + TT * q;
                         const unsigned k = k_lo + j;
                         const bool ok = (G == 1 || active) && j < nb;
-                        const MBin<T>& m = pm[q];
-                        const XBin<T>& xb = px[q];
-                        const C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
-                        const C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
-                        const C2<T> zk = k == 0 ? C2<T>{et.re, ep.re} : C2<T>{et.re - ep.im, et.im + ep.re};
-                        const C2<T> zn{et.re + ep.im, ep.re - et.im};
-                        lds[ok ? lpad(k) : lds_pad_slot<N>()] = zk;
-                        lds[(ok && k != 0) ? lpad(N - k) : lds_pad_slot<N>()] = zn;
+                        C2<T> zp, zq;
+                        packed_bin(pm[q], px[q], zp, zq);
+                        lds[ok ? lpad(k) : lds_pad_slot<N>()] = zp;
+                        lds[(ok && k != 0) ? lpad(N - k) : lds_pad_slot<N>()] = C2<T>{zq.re, -zq.im};
+                        // a band that includes DC (a uniform test, skipped
+                        // otherwise): bin 0 keeps real parts only
+                        if (q == 0 && k_lo == 0u && ok && k == 0) lds[0] = packed_dc(zp, zq);
                     }
                 } else if (active) {
                     for (unsigned j = t; j < nb; j += TT) stage_bin<T, N>(lds, k_lo + j, Md[j], Xs[j]);
@@ -799,22 +802,22 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
         for (int h = 0; h < (DUAL ? 1 : 2); ++h) {
             if (active) {
                 for (unsigned j = t; j < nb; j += TT) {
-                    const MBin<T> m = Md[j];
-                    const XBin<T> xb = Xs[j];
-                    const C2<T> et = cadd(cmul(m.m00, xb.x0), cmul(m.m01, xb.x1));
-                    const C2<T> ep = cadd(cmul(m.m10, xb.x0), cmul(m.m11, xb.x1));
+                    // Z[k] = zp, Z[N-k] = conj zq; the Hilbert spectrum
+                    // Zh[k] = -i Z[k], Zh[N-k] = i Z[N-k]
+                    C2<T> zp, zq;
+                    packed_bin(Md[j], Xs[j], zp, zq);
                     const unsigned k = k_lo + j;
                     if (k == 0) {
-                        if (DUAL || h == 0) la[0] = C2<T>{et.re, ep.re};
+                        if (DUAL || h == 0) la[0] = packed_dc(zp, zq);
                         if (DUAL || h == 1) lb[0] = C2<T>{0, 0};
                     } else {
                         if (DUAL || h == 0) {
-                            la[lpad(k)] = C2<T>{et.re - ep.im, et.im + ep.re};
-                            la[lpad(N - k)] = C2<T>{et.re + ep.im, ep.re - et.im};
+                            la[lpad(k)] = zp;
+                            la[lpad(N - k)] = C2<T>{zq.re, -zq.im};
                         }
                         if (DUAL || h == 1) {
-                            lb[lpad(k)] = C2<T>{et.im + ep.re, ep.im - et.re};
-                            lb[lpad(N - k)] = C2<T>{et.im - ep.re, et.re + ep.im};
+                            lb[lpad(k)] = C2<T>{zp.im, -zp.re};
+                            lb[lpad(N - k)] = C2<T>{zq.im, zq.re};
                         }
                     }
                 }

@@ -34,11 +34,16 @@ struct alignas(16) XBin {
     C2<T> x0, x1;
 };
 
-// Coefficients of one (direction, bin): [E_theta; E_phi] = [m00 m01; m10 m11] [X_0; X_1],
-// already multiplied by 1/N and zero where the bin is singular.
+// Coefficients of one (direction, bin) in packed form.  With the solution
+// [E_theta; E_phi] = C [X_0; X_1] (C = (1/N) H^-1, zero where the bin is
+// singular), the inverse transform's packed spectrum needs
+//   Z[k]            = E_theta + i E_phi = p0 X_0 + p1 X_1,
+//   conj Z[N - k]   = E_theta - i E_phi = q0 X_0 + q1 X_1,
+// so p_j = C_0j + i C_1j and q_j = C_0j - i C_1j.  (The pattern-response
+// entry point stores the interpolated H = [p0 p1; q0 q1] in the same record.)
 template <typename T>
 struct alignas(16) MBin {
-    C2<T> m00, m01, m10, m11;
+    C2<T> p0, p1, q0, q1;
 };
 
 // Pattern grid as the kernels see it.
