@@ -376,9 +376,10 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
 
 // E-field traces of one (event, direction, station range) per block; each
 // FFT group takes one station at a time.  Per station:
-//   1. every in-band bin k is handled once: (E_th, E_ph) = coef * (X_0, X_1),
-//      and the packed spectrum Z[k] = E_th + i E_ph, Z[N-k] = conj E_th +
-//      i conj E_ph is written to LDS (DC keeps real parts only);
+//   1. every in-band bin k is handled once: the packed spectrum
+//      Z[k] = E_th + i E_ph, Z[N-k] = conj E_th + i conj E_ph comes straight
+//      from the packed coefficients and (X_0, X_1) (see MBin) and is written
+//      to LDS (DC keeps real parts only);
 //   2. each thread reads its column of Z (zero outside the band);
 //   3. inverse FFT; thread t ends with z[t + (N/E) i], whose real and
 //      imaginary parts are E_theta and E_phi -- stored with non-temporal,
@@ -721,7 +722,7 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
 // the maximum of the Hilbert envelope of its E-field trace).  Per (direction,
 // station) the in-band solution (E_th, E_ph) is packed twice:
 //   Z[k]   = E_th + i E_ph,            Z[N-k]   = conj E_th + i conj E_ph
-//   Zh[k]  = -i E_th + E_ph,           Zh[N-k]  = i conj E_th - conj E_ph
+//   Zh[k]  = -i E_th + E_ph = -i Z[k],  Zh[N-k]  = i conj E_th - conj E_ph = i Z[N-k]
 // (Zh is the packed spectrum of the Hilbert transforms H(e_th) + i H(e_ph),
 // with H = IDFT(-i sgn(k) DFT)), both are inverse-transformed, and
 // env = sqrt(e^2 + H(e)^2) is reduced to its maximum and the first sample
