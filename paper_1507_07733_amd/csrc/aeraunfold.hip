@@ -1022,7 +1022,7 @@ constexpr bool variant_built(int n, int v, int tsize)
     if (kUnfoldVariants[v].wave && e > 16) return false;
     if (kUnfoldVariants[v].rmax > e) return false;
     if (kUnfoldVariants[v].pair && ((n / e) % 64 != 0 || e % 2 != 0)) return false;
-    if (kUnfoldVariants[v].pp && 2 * (n + n / 16) * 2 * tsize > kMaxLdsPerBlock) return false;
+    if (kUnfoldVariants[v].pp && 2 * (n + 16) * 2 * tsize > kMaxLdsPerBlock) return false;  // 2 x lds_elems
     return true;
 }
 
