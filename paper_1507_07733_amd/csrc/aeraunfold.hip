@@ -1841,8 +1841,13 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
             for (int st = 0; st < descs[e].S; ++st) c.su.push_back(int2{ci, st});
             for (int d = 0; d < descs[e].D; ++d) {
                 c.cu.push_back(int2{ci, d});
-                for (int s0 = 0; s0 < descs[e].S; s0 += kStationsPerUnit)
-                    c.uu.push_back(int4{ci, d, s0, std::min(descs[e].S, s0 + kStationsPerUnit)});
+                // events with many directions have units to spare: chunks of
+                // twice the stations halve the per-unit start (work fetch and
+                // the first station's loads) -- measured +1.5 % on 256
+                // directions per event, and a loss at 16 directions per event
+                const int cs = descs[e].D >= kWideUnitMinDirs ? 2 * kStationsPerUnit : kStationsPerUnit;
+                for (int s0 = 0; s0 < descs[e].S; s0 += cs)
+                    c.uu.push_back(int4{ci, d, s0, std::min(descs[e].S, s0 + cs)});
             }
         }
         if (b->flags & AU_PLAN_XCD) {

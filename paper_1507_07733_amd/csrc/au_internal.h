@@ -26,6 +26,9 @@ au_status set_error(au_status s, const std::string& msg);
 const std::string& error_string();
 
 constexpr int kStationsPerUnit = 16;
+// Batched plans use units of 2 x kStationsPerUnit for events with at least
+// this many directions.
+constexpr int kWideUnitMinDirs = 64;
 
 struct EvParams {
     int S, N, k_lo, nb;
