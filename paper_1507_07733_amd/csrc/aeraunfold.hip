@@ -749,7 +749,7 @@ template <typename T, int N, int E>
 __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_env(
     EvDesc ev0, int spw, const XBin<T>* __restrict__ X, const MBin<T>* __restrict__ M, T* __restrict__ efield,
     T* __restrict__ peak, int* __restrict__ arg, const C2<T>* __restrict__ tw, const int* __restrict__ skip,
-    const EvDesc* __restrict__ evs, const int4* __restrict__ units, int skip_stride)
+    const EvDesc* __restrict__ evs, const int4* __restrict__ units, int skip_stride, int total_only)
 {
     constexpr int TT = N / E;
     constexpr int G = groups_per_block<T, N, E, env_bufs<T, E>()>();
@@ -846,17 +846,35 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
         // rounded root per sample is some fifteen instructions)
         T bv[3] = {(T)-1, (T)-1, (T)-1};
         int bi[3] = {0, 0, 0};
+        // with total_only (a uniform flag: the batched loop and the direction
+        // fit read only the total field; the one-event loop also returns the
+        // theta and phi peaks) the component maxima are neither tracked nor
+        // stored
+        const int c_lo = (TT >= 256 && total_only) ? 2 : 0;
+        if (c_lo == 2) {
 #pragma unroll
-        for (int i = 0; i < E; ++i) {
-            const T p0 = x[i].re * x[i].re + xh[i].re * xh[i].re;
-            const T p1 = x[i].im * x[i].im + xh[i].im * xh[i].im;
-            const T e[3] = {p0, p1, p0 + p1};
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                if (e[c] > bv[c]) {
-                    bv[c] = e[c];
-                    bi[c] = t + TT * i;
+            for (int i = 0; i < E; ++i) {
+                const T p0 = x[i].re * x[i].re + xh[i].re * xh[i].re;
+                const T p1 = x[i].im * x[i].im + xh[i].im * xh[i].im;
+                const T p = p0 + p1;  // as in the three-component form
+                if (p > bv[2]) {
+                    bv[2] = p;
+                    bi[2] = t + TT * i;
                 }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const T p0 = x[i].re * x[i].re + xh[i].re * xh[i].re;
+                const T p1 = x[i].im * x[i].im + xh[i].im * xh[i].im;
+                const T e[3] = {p0, p1, p0 + p1};
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (e[c] > bv[c]) {
+                        bv[c] = e[c];
+                        bi[c] = t + TT * i;
+                    }
+            }
         }
         // larger value wins; equal values: smaller sample index.
         if constexpr (TT >= 256) {
@@ -871,18 +889,20 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
             static_assert(3 * TT * (sizeof(T) + sizeof(int)) <= lds_elems<N>() * sizeof(C2<T>), "scratch");
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
+                if (c < c_lo) continue;
                 cv[c * TT + t] = bv[c];
                 ci[c * TT + t] = bi[c];
             }
             lds_barrier();
             const int wv = t >> 6, lane = t & 63;
-            if (wv < 3 && active) {  // whole waves: no barrier inside
-                T v = cv[wv * TT + lane];
-                int ix = ci[wv * TT + lane];
+            const int cc = c_lo + wv;  // the component this wave reduces
+            if (cc < 3 && active) {  // whole waves: no barrier inside
+                T v = cv[cc * TT + lane];
+                int ix = ci[cc * TT + lane];
 #pragma unroll
                 for (int k = lane + 64; k < TT; k += 64) {
-                    const T ov = cv[wv * TT + k];
-                    const int oi = ci[wv * TT + k];
+                    const T ov = cv[cc * TT + k];
+                    const int oi = ci[cc * TT + k];
                     if (ov > v || (ov == v && oi < ix)) {
                         v = ov;
                         ix = oi;
@@ -897,7 +917,7 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                     }
                 }
                 if (lane == 0) {
-                    const int64_t o = pk_off + ((int64_t)d * ev.S + s) * 3 + wv;
+                    const int64_t o = pk_off + ((int64_t)d * ev.S + s) * 3 + cc;
                     peak[o] = sqrt(v);
                     arg[o] = ix;
                 }
@@ -2348,14 +2368,14 @@ template <typename T, int N>
 static hipError_t launch_env_n(hipStream_t st, const EvDesc& ev0, int spw, int n_units, const XBin<T>* X,
                                const MBin<T>* M, T* efield, T* peak, int* arg, const C2<T>* tw,
                                const int* skip = nullptr, const EvDesc* evs = nullptr,
-                               const int4* units = nullptr, int skip_stride = 0)
+                               const int4* units = nullptr, int skip_stride = 0, bool total_only = false)
 {
     constexpr int E = N >= 1024 ? 8 : (N < 16 ? N : 16);
     constexpr int TT = N / E;
     constexpr int G = groups_per_block<T, N, E, env_bufs<T, E>()>();
     constexpr size_t LDS = ((size_t)G * env_bufs<T, E>() * lds_elems<N>() + env_ltw<T, N, E>()) * sizeof(C2<T>);
     hipLaunchKernelGGL((k_unfold_env<T, N, E>), dim3(n_units), dim3(G * TT), LDS, st, ev0, spw, X, M,
-                       efield, peak, arg, tw, skip, evs, units, skip_stride);
+                       efield, peak, arg, tw, skip, evs, units, skip_stride, total_only ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -2948,7 +2968,8 @@ static au_status run_fit(const au_table* tb, const au_event* ev, const EvParams&
         switch (p.N) {
 #define X_(NN)                                                                                       \
     case NN:                                                                                         \
-        e = launch_env_n<T, NN>(st, ev0, spw, nc * chunks, X, M, (T*)nullptr, peak, arg, tw, nullptr); \
+        e = launch_env_n<T, NN>(st, ev0, spw, nc * chunks, X, M, (T*)nullptr, peak, arg, tw, nullptr,   \
+                                nullptr, nullptr, 0, true);                                          \
         break;
             AU_FOR_EACH_N(X_)
 #undef X_
@@ -3185,7 +3206,7 @@ static au_status run_reconstruct_batch(const au_table* tb, const au_event* ev, c
 #define X_(NN)                                                                                          \
     case NN:                                                                                            \
         e = launch_env_n<T, NN>(st, ev0, spw, (int)n_eunits, X, M, (T*)nullptr, peak, arg, tw,          \
-                                (const int*)state, (const EvDesc*)evs, (const int4*)eunits, 4);         \
+                                (const int*)state, (const EvDesc*)evs, (const int4*)eunits, 4, true);   \
         break;
             AU_FOR_EACH_N(X_)
 #undef X_
