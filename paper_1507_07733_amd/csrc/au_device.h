@@ -18,8 +18,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <type_traits>
-
 namespace au {
 
 template <typename T>
