@@ -243,14 +243,14 @@ __global__ __launch_bounds__(kBlock) void k_spectrum(const Tin* __restrict__ vol
     }
     fft<T, N, E, -1>(x, lds, tw, t);
 #pragma unroll
-    for (int i = 0; i < E; ++i) lds[lpad(t + TT * i)] = x[i];
+    for (int i = 0; i < E; ++i) lds[lpad<T>(t + TT * i)] = x[i];
     __syncthreads();
     if (active) {
         XBin<T>* out = X + ev.x_off + (int64_t)s * ev.nb;
         for (int j = t; j < ev.nb; j += TT) {
             const int k = ev.k_lo + j;
-            const C2<T> a = lds[lpad(k)];
-            const C2<T> b = lds[lpad((N - k) & (N - 1))];
+            const C2<T> a = lds[lpad<T>(k)];
+            const C2<T> b = lds[lpad<T>((N - k) & (N - 1))];
             XBin<T> r;
             r.x0 = C2<T>{(T)0.5 * (a.re + b.re), (T)0.5 * (a.im - b.im)};
             r.x1 = C2<T>{(T)0.5 * (a.im + b.im), (T)0.5 * (b.re - a.re)};
@@ -425,8 +425,8 @@ __device__ __forceinline__ void stage_bin(C2<T>* __restrict__ lds, unsigned k, c
     if (k == 0) {
         lds[0] = packed_dc(zp, zq);
     } else {
-        lds[lpad(k)] = zp;
-        lds[lpad(N - k)] = C2<T>{zq.re, -zq.im};
+        lds[lpad<T>(k)] = zp;
+        lds[lpad<T>(N - k)] = C2<T>{zq.re, -zq.im};
     }
 }
 
@@ -651,8 +651,8 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
                         const bool ok = (G == 1 || active) && j < nb;
                         C2<T> zp, zq;
                         packed_bin(pm[q], px[q], zp, zq);
-                        lds[ok ? lpad(k) : lds_pad_slot<N>()] = zp;
-                        lds[(ok && k != 0) ? lpad(N - k) : lds_pad_slot<N>()] = C2<T>{zq.re, -zq.im};
+                        lds[ok ? lpad<T>(k) : lds_pad_slot<N>()] = zp;
+                        lds[(ok && k != 0) ? lpad<T>(N - k) : lds_pad_slot<N>()] = C2<T>{zq.re, -zq.im};
                         // a band that includes DC (a uniform test, skipped
                         // otherwise): bin 0 keeps real parts only
                         if (q == 0 && k_lo == 0u && ok && k == 0) lds[0] = packed_dc(zp, zq);
@@ -670,9 +670,9 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
                     // in place of a per-bin select (the compiler keeps the
                     // eight addresses for the unit)
                     if constexpr (PF > 0)
-                        x[i] = lds[inb ? lpad(k) : lds_zero_slot<N>()];
+                        x[i] = lds[inb ? lpad<T>(k) : lds_zero_slot<N>()];
                     else
-                        x[i] = inb ? lds[lpad(k)] : C2<T>{0, 0};
+                        x[i] = inb ? lds[lpad<T>(k)] : C2<T>{0, 0};
                 }
                 if constexpr (!PP) lds_sync<WAVE>();
             }
@@ -813,12 +813,12 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                         if (DUAL || h == 1) lb[0] = C2<T>{0, 0};
                     } else {
                         if (DUAL || h == 0) {
-                            la[lpad(k)] = zp;
-                            la[lpad(N - k)] = C2<T>{zq.re, -zq.im};
+                            la[lpad<T>(k)] = zp;
+                            la[lpad<T>(N - k)] = C2<T>{zq.re, -zq.im};
                         }
                         if (DUAL || h == 1) {
-                            lb[lpad(k)] = C2<T>{zp.im, -zp.re};
-                            lb[lpad(N - k)] = C2<T>{zq.im, zq.re};
+                            lb[lpad<T>(k)] = C2<T>{zp.im, -zp.re};
+                            lb[lpad<T>(N - k)] = C2<T>{zq.im, zq.re};
                         }
                     }
                 }
@@ -829,8 +829,8 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                 const unsigned k = t + TT * i;
                 const unsigned kk = (k <= N / 2) ? k : N - k;
                 const bool inb = active && (kk - k_lo) < nb;
-                if (DUAL || h == 0) x[i] = inb ? la[lpad(k)] : C2<T>{0, 0};
-                if (DUAL || h == 1) xh[i] = inb ? lb[lpad(k)] : C2<T>{0, 0};
+                if (DUAL || h == 0) x[i] = inb ? la[lpad<T>(k)] : C2<T>{0, 0};
+                if (DUAL || h == 1) xh[i] = inb ? lb[lpad<T>(k)] : C2<T>{0, 0};
             }
             lds_barrier();
         }

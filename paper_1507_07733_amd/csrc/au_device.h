@@ -213,17 +213,27 @@ constexpr CxRoot cx_root(long long p, long long q)
 // operation issued so far has completed.
 __device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-// LDS slot of sequence element i (8- or 16-byte elements): the low four
-// bits are XOR-ed with bits 4-7 and bit 3 also with bit 6, a permutation of
-// every aligned block of 16.  Measured on gfx950 with 8-byte accesses, a
-// wave's reads are served 32 lanes per cycle from 64 banks and its writes 16
-// lanes per cycle from 32 banks; under that model this layout keeps the
-// gathers (consecutive elements) and the radix-8 scatters of the first
-// passes (lane strides of 8 and 64 elements) free of bank conflicts, where
-// one pad slot per 16 elements left the gathers and the stride-8 scatters
-// two-way conflicted (LDS cycles per FFT -35 % at N = 4096, 8 values per
-// thread).
-__device__ __forceinline__ constexpr int lpad(int i) { return i ^ ((i >> 4) & 15) ^ (((i >> 6) & 1) << 3); }
+// LDS slot of sequence element i, an XOR swizzle of the low index bits (a
+// permutation of every aligned block of 16 or 8 elements) chosen per
+// element size.  Measured on gfx950: a wave's 8-byte reads are served 32
+// lanes per cycle from 64 four-byte banks and its 8-byte writes 16 lanes per
+// cycle from 32 banks; its 16-byte writes 8 lanes per cycle from 32 banks,
+// and its 16-byte reads about 16 lanes per cycle from 64 banks.  Under those
+// models the layouts keep the gathers (consecutive elements) and the radix-8
+// scatters (lane strides of 8 and 64 elements) nearly free of bank
+// conflicts: 8-byte (complex float) elements XOR bits 0-3 with bits 4-7 and
+// bit 3 with bit 6; 16-byte (complex double) elements XOR bits 0-2 with bits
+// 3-5 and with bits 4-6.  (One pad slot per 16 elements left the gathers and
+// the stride-8 scatters two-way conflicted: LDS cycles per FFT -35 % for
+// complex float at N = 4096, 8 values per thread.)
+template <typename T>
+__device__ __forceinline__ constexpr int lpad(int i)
+{
+    if constexpr (sizeof(T) == 8)
+        return i ^ ((i >> 3) & 7) ^ ((i >> 4) & 7);
+    else
+        return i ^ ((i >> 4) & 15) ^ (((i >> 6) & 1) << 3);
+}
 
 // Elements per LDS buffer: the N slots of the sequence plus 16 spare ones
 // (lds_pad_slot, lds_zero_slot) that no transform touches.
@@ -479,13 +489,13 @@ __device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
         } else {
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[lpad(base + r * NS)] = v[r];
+            for (int r = 0; r < R; ++r) lds[lpad<T>(base + r * NS)] = v[r];
         }
     }
     if constexpr (!LAST) {
         lds_sync<WAVE>();
 #pragma unroll
-        for (int i = 0; i < E; ++i) x[i] = lds[lpad(t + TT * i)];
+        for (int i = 0; i < E; ++i) x[i] = lds[lpad<T>(t + TT * i)];
         lds_sync<WAVE>();
         fft_pass<T, N, E, RMAX, TWMODE, WAVE, NS * R, SIGN>(x, lds, tw, w, t, ltw);
     }
@@ -555,13 +565,13 @@ __device__ __forceinline__ void fft_pass_pp(C2<T> (&x)[E], C2<T>* __restrict__ l
         } else {
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) la[lpad(base + r * NS)] = v[r];
+            for (int r = 0; r < R; ++r) la[lpad<T>(base + r * NS)] = v[r];
         }
     }
     if constexpr (!LAST) {
         lds_sync<WAVE>();
 #pragma unroll
-        for (int i = 0; i < E; ++i) x[i] = la[lpad(t + TT * i)];
+        for (int i = 0; i < E; ++i) x[i] = la[lpad<T>(t + TT * i)];
         fft_pass_pp<T, N, E, RMAX, TWMODE, WAVE, NS * R, SIGN>(x, lb, la, tw, w, t, ltw);
     }
 }
@@ -619,8 +629,8 @@ __device__ __forceinline__ void fft_pass2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* _
             const int base = (j - k) * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                la[lpad(base + r * NS)] = u[r];
-                lb[lpad(base + r * NS)] = v[r];
+                la[lpad<T>(base + r * NS)] = u[r];
+                lb[lpad<T>(base + r * NS)] = v[r];
             }
         }
     }
@@ -628,8 +638,8 @@ __device__ __forceinline__ void fft_pass2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* _
         lds_barrier();
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            x[i] = la[lpad(t + TT * i)];
-            y[i] = lb[lpad(t + TT * i)];
+            x[i] = la[lpad<T>(t + TT * i)];
+            y[i] = lb[lpad<T>(t + TT * i)];
         }
         lds_barrier();
         fft_pass2<T, N, E, RMAX, TWMODE, NS * R, SIGN>(x, y, la, lb, tw, w, t, ltw);
