@@ -259,6 +259,106 @@ __global__ __launch_bounds__(kBlock) void k_spectrum(const Tin* __restrict__ vol
     }
 }
 
+// Bins per thread the streaming spectrum kernel stores: it serves bands of at
+// most N/4 bins (30-80 MHz at 200 MHz sampling is 0.25 N bins); wider bands
+// take k_spectrum.
+constexpr int kSpecStreamBins = 2;
+
+// The same spectra by a persistent grid (FP32, 8 values per thread, radix 8):
+// each workgroup takes the stations blockIdx.x, blockIdx.x + gridDim.x, ...
+// and issues the trace loads of its next station before transforming the
+// current one, so that their latency hides behind the transform.  Nothing in
+// the station loop waits for a load issued after the previous station's
+// stores (vector-memory completions count in issue order): the early passes'
+// twiddles sit in an LDS table and the last pass's in registers, both set
+// once, and every thread issues a fixed number of spectrum stores, the lanes
+// past the band storing out of range of the row (dropped).
+template <typename Tin, int N>
+__global__ __launch_bounds__(N / 8) void k_spectrum_stream(const Tin* __restrict__ volt, EvDesc ev0,
+                                                           const EvDesc* __restrict__ evs,
+                                                           const int2* __restrict__ units, int n_units,
+                                                           XBin<float>* __restrict__ X,
+                                                           const C2<float>* __restrict__ tw)
+{
+    using T = float;
+    constexpr int E = 8, RMAX = 8, TT = N / E;
+    static_assert(kSpecStreamBins * TT <= N, "gathered bins stay inside the transform");
+    extern __shared__ __align__(16) unsigned char smem[];
+    C2<T>* lds = reinterpret_cast<C2<T>*>(smem);
+    C2<T>* ltw = lds + lds_elems<N>();
+    const int t = threadIdx.x;
+    C2<T> w[tw_count<N, E, RMAX, TW_HYB>()];
+    load_twiddles<T, N, E, RMAX, TW_HYB, -1>(w, tw, t);
+    fill_lds_twiddles<T, N, E, RMAX, -1>(ltw, tw, t, TT);
+    vmem_wait_all();
+    lds_barrier();
+    // the host launches at most n_units workgroups; a station's trace pair,
+    // spectrum row, row length and first bin:
+    struct Row {
+        const Tin* v;
+        XBin<T>* out;
+        int nb, k_lo;
+    };
+    auto locate = [&](int uu) {
+        int e = 0, s = uu;
+        if (units != nullptr) {
+            const int2 su = units[uu];
+            e = su.x;
+            s = su.y;
+        }
+        const int64_t volt_off = evs ? evs[e].volt_off : ev0.volt_off;
+        const int64_t x_off = evs ? evs[e].x_off : ev0.x_off;
+        const int nb = evs ? evs[e].nb : ev0.nb;
+        const int k_lo = evs ? evs[e].k_lo : ev0.k_lo;
+        return Row{volt + volt_off + (int64_t)s * 2 * N, X + x_off + (int64_t)s * nb, nb, k_lo};
+    };
+    int u = blockIdx.x;
+    Row row = locate(u);
+    Tin a[E], b[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        a[i] = row.v[t + TT * i];
+        b[i] = row.v[N + t + TT * i];
+    }
+    for (;;) {
+        C2<T> x[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) x[i] = C2<T>{(T)a[i], (T)b[i]};
+        const int un = u + (int)gridDim.x;
+        Row next = row;
+        if (un < n_units) {
+            next = locate(un);
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                a[i] = next.v[t + TT * i];
+                b[i] = next.v[N + t + TT * i];
+            }
+        }
+        fft<T, N, E, -1, TW_HYB, RMAX>(x, lds, tw, t, w, ltw);
+#pragma unroll
+        for (int i = 0; i < E; ++i) lds[lpad<T>(t + TT * i)] = x[i];
+        lds_barrier();
+        const unsigned nb = (unsigned)row.nb;
+        const __amdgpu_buffer_rsrc_t out = buffer_range(row.out, nb * (unsigned)sizeof(XBin<T>));
+#pragma unroll
+        for (int q = 0; q < kSpecStreamBins; ++q) {
+            const unsigned j = (unsigned)(t + TT * q);
+            const int k = j < nb ? row.k_lo + (int)j : 0;
+            const C2<T> za = lds[lpad<T>(k)];
+            const C2<T> zb = lds[lpad<T>((N - k) & (N - 1))];
+            XBin<T> r;
+            r.x0 = C2<T>{(T)0.5 * (za.re + zb.re), (T)0.5 * (za.im - zb.im)};
+            r.x1 = C2<T>{(T)0.5 * (za.im + zb.im), (T)0.5 * (zb.re - za.re)};
+            buffer_store16(r, out, (j < nb ? j : nb) * (unsigned)sizeof(XBin<T>));
+        }
+        if (un >= n_units) break;
+        // every gather done before the next transform writes the buffer
+        lds_barrier();
+        u = un;
+        row = next;
+    }
+}
+
 // Coefficients of every in-band bin of one (event, direction) per block.
 // FP32 (T = float): interpolation, determinant and inverse in float; where
 // |det| < fallback_rel ||H||_F^2 in float, the determinant and inverse are
@@ -1095,13 +1195,39 @@ static int unfold_variant(int prec, int n)
     return g_variant[prec == AU_PREC_FP32 ? 1 : 0][ilog2(n)];
 }
 
+// Workgroups of k_spectrum_stream the device holds at once (0 if unknown).
+template <typename Tin, int N>
+static int spectrum_stream_blocks()
+{
+    static const int blocks = [] {
+        constexpr size_t lds = (lds_elems<N>() + ltw_count<N, 8, 8>()) * sizeof(C2<float>);
+        int dev = 0, cus = 0, occ = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_spectrum_stream<Tin, N>, N / 8, lds) != hipSuccess)
+            return 0;
+        return cus * occ;
+    }();
+    return blocks;
+}
+
+// max_nb: the largest band (bins) of the launch's events.
 template <typename Tin, typename T, int N>
 static hipError_t launch_spectrum_n(hipStream_t st, const Tin* volt, const EvDesc& ev0,
-                                    const EvDesc* evs, const int2* units, int n_units, XBin<T>* X,
-                                    const C2<T>* tw)
+                                    const EvDesc* evs, const int2* units, int n_units, int max_nb,
+                                    XBin<T>* X, const C2<T>* tw)
 {
     using S = Shape<T, N>;
     if (n_units <= 0) return hipSuccess;
+    if constexpr (sizeof(T) == 4 && N >= 1024) {
+        const int blocks = spectrum_stream_blocks<Tin, N>();
+        if (max_nb <= kSpecStreamBins * (N / 8) && blocks > 0) {
+            constexpr size_t lds = (lds_elems<N>() + ltw_count<N, 8, 8>()) * sizeof(C2<float>);
+            hipLaunchKernelGGL((k_spectrum_stream<Tin, N>), dim3(std::min(n_units, blocks)), dim3(N / 8), lds,
+                               st, volt, ev0, evs, units, n_units, X, tw);
+            return hipGetLastError();
+        }
+    }
     const int grid = (n_units + S::G - 1) / S::G;
     hipLaunchKernelGGL((k_spectrum<Tin, T, N, S::E>), dim3(grid), dim3(S::BLOCK), S::LDS, st, volt,
                        ev0, evs, units, n_units, X, tw);
@@ -1164,12 +1290,12 @@ static int occupancy_nv()
 
 template <typename Tin, typename T>
 static hipError_t launch_spectrum(int n, hipStream_t st, const Tin* volt, const EvDesc& ev0,
-                                  const EvDesc* evs, const int2* units, int n_units, XBin<T>* X,
-                                  const C2<T>* tw)
+                                  const EvDesc* evs, const int2* units, int n_units, int max_nb,
+                                  XBin<T>* X, const C2<T>* tw)
 {
     switch (n) {
 #define X_(NN) \
-    case NN: return launch_spectrum_n<Tin, T, NN>(st, volt, ev0, evs, units, n_units, X, tw);
+    case NN: return launch_spectrum_n<Tin, T, NN>(st, volt, ev0, evs, units, n_units, max_nb, X, tw);
         AU_FOR_EACH_N(X_)
 #undef X_
     }
@@ -1519,9 +1645,9 @@ static au_status run_event(const au_table* tb, const au_event* ev, const EvParam
     if (tw == nullptr) return fail(AU_EDEVICE, "twiddle tables missing on this device");
     hipError_t e;
     if (ev->trace_dtype == AU_F64)
-        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, ev0.nb, X, tw);
     else
-        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, ev0.nb, X, tw);
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
     unsigned long long* cnt = (unsigned long long*)d_counts;
     if (tb->dtype == AU_F64)
@@ -1669,6 +1795,7 @@ struct ClassPlan {
     int variant = 0;
     int* d_xcd_off = nullptr;
     int xcd_max_list = 0;
+    int max_nb = 0;  // largest band of the class's events (bins)
 };
 
 struct au_plan {
@@ -1710,9 +1837,9 @@ static au_status enqueue_class_t(const au_table* tb, int tin, int64_t fs, double
     EvDesc ev0{};
     hipError_t e;
     if (tin == AU_F64)
-        e = launch_spectrum<double, T>(c.N, st, (const double*)volt, ev0, c.d_evs, c.d_sunits, c.n_sunits, X, tw);
+        e = launch_spectrum<double, T>(c.N, st, (const double*)volt, ev0, c.d_evs, c.d_sunits, c.n_sunits, c.max_nb, X, tw);
     else
-        e = launch_spectrum<float, T>(c.N, st, (const float*)volt, ev0, c.d_evs, c.d_sunits, c.n_sunits, X, tw);
+        e = launch_spectrum<float, T>(c.N, st, (const float*)volt, ev0, c.d_evs, c.d_sunits, c.n_sunits, c.max_nb, X, tw);
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
     if (stage_events) HIP_TRY(hipEventRecord(stage_events[0], st));
     if (c.n_cunits > 0) {
@@ -1772,6 +1899,7 @@ static au_status plan_enqueue(au_plan* pl, const void* d_volt, void* d_efield, h
         c.persistent_blocks = cp.persistent_blocks;
         c.d_xcd_off = cp.d_xcd_off;
         c.xcd_max_list = cp.xcd_max_list;
+        c.max_nb = cp.max_nb;
         au_status s = enqueue_class(pl->tb, pl->prec, pl->tin, pl->fs, pl->fb, pl->sg, c, d_volt, d_efield,
                                     pl->d_x, pl->d_m, pl->d_dirs, st, d_counts, tm ? &pl->ev[ei] : nullptr);
         if (s != AU_OK) return s;
@@ -1962,7 +2090,10 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
     for (size_t i = 0; i < hc.size(); ++i) {
         ClassPlan c;
         c.N = hc[i].N;
-        for (const EvDesc& d : hc[i].evs) c.station_unfolds += (uint64_t)d.S * d.D;
+        for (const EvDesc& d : hc[i].evs) {
+            c.station_unfolds += (uint64_t)d.S * d.D;
+            c.max_nb = std::max(c.max_nb, d.nb);
+        }
         c.n_sunits = (int)hc[i].su.size();
         c.n_cunits = (int)hc[i].cu.size();
         c.n_uunits = (int)hc[i].uu.size();
@@ -2409,9 +2540,9 @@ static au_status run_envelope(const au_table* tb, const au_event* ev, const EvPa
     if (tw == nullptr) return fail(AU_EDEVICE, "twiddle tables missing on this device");
     hipError_t e;
     if (ev->trace_dtype == AU_F64)
-        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, ev0.nb, X, tw);
     else
-        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, ev0.nb, X, tw);
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
     if (tb->dtype == AU_F64)
         launch_coef<double, T>(st, tb, ev0, nullptr, nullptr, n_dir, dirs, 0, 0, ev->fs_hz, ev->fallback_rel,
@@ -2706,11 +2837,11 @@ static au_status run_reconstruct(const au_table* tb, const au_event* ev, const E
     if (tw == nullptr) return fail(AU_EDEVICE, "twiddle tables missing on this device");
     hipError_t e;
     if (ev->trace_dtype == AU_F64) {
-        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, ev0.nb, X, tw);
         hipLaunchKernelGGL(k_volt_timing<double>, dim3(p.S), dim3(kBlock), 0, st, (const double*)d_volt, p.N, hist,
                            (const EvDesc*)nullptr, (const int2*)nullptr);
     } else {
-        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, ev0.nb, X, tw);
         hipLaunchKernelGGL(k_volt_timing<float>, dim3(p.S), dim3(kBlock), 0, st, (const float*)d_volt, p.N, hist,
                            (const EvDesc*)nullptr, (const int2*)nullptr);
     }
@@ -2957,8 +3088,8 @@ static au_status run_fit(const au_table* tb, const au_event* ev, const EvParams&
     const C2<T>* tw = twiddles<T>(tb->device);
     if (tw == nullptr) return fail(AU_EDEVICE, "twiddle tables missing on this device");
     hipError_t e = ev->trace_dtype == AU_F64
-                       ? launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, X, tw)
-                       : launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, X, tw);
+                       ? launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, ev0.nb, X, tw)
+                       : launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, ev0.nb, X, tw);
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
     const double dt_ns = 1e9 / (double)ev->fs_hz;
     int64_t off = 0;
@@ -3189,11 +3320,11 @@ static au_status run_reconstruct_batch(const au_table* tb, const au_event* ev, c
     if (tw == nullptr) return fail(AU_EDEVICE, "twiddle tables missing on this device");
     hipError_t e;
     if (ev->trace_dtype == AU_F64) {
-        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, evs, sunits, (int)stot, X, tw);
+        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, evs, sunits, (int)stot, p.nb, X, tw);
         hipLaunchKernelGGL(k_volt_timing<double>, dim3((unsigned)stot), dim3(kBlock), 0, st, (const double*)d_volt,
                            p.N, hist, (const EvDesc*)evs, (const int2*)sunits);
     } else {
-        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, evs, sunits, (int)stot, X, tw);
+        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, evs, sunits, (int)stot, p.nb, X, tw);
         hipLaunchKernelGGL(k_volt_timing<float>, dim3((unsigned)stot), dim3(kBlock), 0, st, (const float*)d_volt,
                            p.N, hist, (const EvDesc*)evs, (const int2*)sunits);
     }

@@ -403,6 +403,17 @@ __device__ __forceinline__ V buffer_load16(__amdgpu_buffer_rsrc_t r, unsigned vo
     return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0));
 }
 
+// Store of a 16-byte record at byte offset voff of a buffer range (default
+// cache policy).  A lane whose offset is at or past the range's end stores
+// nothing: the buffer unit's range check drops it.
+template <typename V>
+__device__ __forceinline__ void buffer_store16(const V& v, __amdgpu_buffer_rsrc_t r, unsigned voff)
+{
+    static_assert(sizeof(V) == 16, "16-byte record");
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)voff, 0, 0);
+}
+
 // Workgroup barrier that orders LDS only.  The exchanges between FFT passes
 // (and the small LDS reductions) need every LDS write before the barrier
 // visible after it; no thread reads another thread's global writes.  The

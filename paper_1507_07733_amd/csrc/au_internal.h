@@ -60,6 +60,7 @@ struct ClassLaunch {
     int persistent_blocks = 0;
     const int* d_xcd_off = nullptr;     // non-null: 8 per-XCD unit lists (9 boundaries)
     int xcd_max_list = 0;               // longest of the 8 lists
+    int max_nb = 1 << 30;               // largest band of the events, in bins (default: unknown)
 };
 
 // Enqueue spectrum, coefficient and unfold launches of one class on `st`.

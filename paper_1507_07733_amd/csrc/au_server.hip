@@ -307,6 +307,8 @@ static void launch_batch(au_server* sv)
         c.n_cunits = (int)hc[i].cu.size();
         c.d_uunits = (const int4*)put(hc[i].uu.data(), hc[i].uu.size() * sizeof(int4));
         c.n_uunits = (int)hc[i].uu.size();
+        c.max_nb = 0;
+        for (const EvDesc& d : hc[i].evs) c.max_nb = std::max(c.max_nb, d.nb);
         cl.push_back(c);
     }
     const int si = sv->next_stream;
