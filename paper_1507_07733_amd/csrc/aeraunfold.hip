@@ -127,39 +127,11 @@ __device__ __forceinline__ void slice4(const C2<Tt>* __restrict__ nodes, const G
     for (int cp = 0; cp < 4; ++cp) out[cp] = clerp(za[0][cp], za[1][cp], tz);
 }
 
-// Frequency nodes a direction's angular slice may hold in LDS (the 30-80 MHz
-// band spans 52 nodes at 1 MHz, 102 at 0.5 MHz); wider bands interpolate per
-// bin from the table.
+// Frequency nodes a direction's angular slice holds in LDS at a time (the
+// 30-80 MHz band spans 52 nodes at 1 MHz, 102 at 0.5 MHz); wider bands are
+// taken in windows of this many nodes.
 constexpr int kMaxSliceNodes = 256;
 
-// Trilinear interpolation of the four entries: along azimuth, then zenith,
-// then frequency (between nodes ifr and ifr + 1).
-template <typename Tt, typename T>
-__device__ __forceinline__ void interp4(const C2<Tt>* __restrict__ nodes, const GridDev& g, int ifr,
-                                        T tf, int iz, T tz, int ia, int ja, T ta, C2<T> h[4])
-{
-    C2<T> fz[2][4];
-#pragma unroll
-    for (int df = 0; df < 2; ++df) {
-        C2<T> za[2][4];
-#pragma unroll
-        for (int dz = 0; dz < 2; ++dz) {
-            const int64_t row = ((int64_t)(ifr + df) * g.n_zen + (iz + dz)) * g.n_az;
-            const C2<Tt>* p0 = nodes + (row + ia) * 4;
-            const C2<Tt>* p1 = nodes + (row + ja) * 4;
-#pragma unroll
-            for (int cp = 0; cp < 4; ++cp) {
-                const C2<T> a0{(T)p0[cp].re, (T)p0[cp].im};
-                const C2<T> a1{(T)p1[cp].re, (T)p1[cp].im};
-                za[dz][cp] = clerp(a0, a1, ta);
-            }
-        }
-#pragma unroll
-        for (int cp = 0; cp < 4; ++cp) fz[df][cp] = clerp(za[0][cp], za[1][cp], tz);
-    }
-#pragma unroll
-    for (int cp = 0; cp < 4; ++cp) h[cp] = clerp(fz[0][cp], fz[1][cp], tf);
-}
 
 // Coefficients of the bin: C = (1/N) H^-1 = (1/(N det)) [h3 -h1; -h2 h0],
 // with H = [h0 h1; h2 h3] indexed [channel][component], in the packed form
@@ -404,6 +376,9 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
     // frequency node the band's bins fall between, once, in LDS; each bin then
     // only interpolates in frequency between two slice nodes.  The same
     // operations in the same order as interpolating every bin from the table.
+    // A band spanning more than kMaxSliceNodes nodes is taken in windows of
+    // that many nodes, consecutive windows sharing one node; a bin belongs to
+    // the window that holds both of its nodes.
     __shared__ C2<T> sl[kMaxSliceNodes][4];
     int f_lo = 0, n_nodes = 0;
     if (ev.nb > 0) {
@@ -413,57 +388,56 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
         freq_cell(gd, (int64_t)(ev.k_lo + ev.nb - 1), ev.N, fs, f_hi, tdummy);
         n_nodes = f_hi - f_lo + 2;
     }
-    const bool use_slice = n_nodes > 0 && n_nodes <= kMaxSliceNodes;  // uniform over the workgroup
-    if (use_slice) {
-        for (int i = threadIdx.x; i < n_nodes; i += blockDim.x)
-            slice4<Tt, T>(nodes, gd, f_lo + i, iz, (T)tz, ia, ja, (T)ta, sl[i]);
+    for (int w0 = 0; w0 < n_nodes - 1; w0 += kMaxSliceNodes - 1) {
+        const int wn = min(kMaxSliceNodes, n_nodes - w0);  // uniform over the workgroup
+        if (w0 > 0) __syncthreads();                         // the previous window's reads are done
+        for (int i = threadIdx.x; i < wn; i += blockDim.x)
+            slice4<Tt, T>(nodes, gd, f_lo + w0 + i, iz, (T)tz, ia, ja, (T)ta, sl[i]);
         __syncthreads();
-    }
-    for (int j = threadIdx.x; j < ev.nb; j += blockDim.x) {
-        int ifr;
-        double tf;
-        freq_cell(gd, (int64_t)(ev.k_lo + j), ev.N, fs, ifr, tf);
-        if constexpr (RESP) {
-            if (wq > 0.0) tf = rint(tf * wq) / wq;
-        }
-        C2<T> h[4];
-        if (use_slice) {
+        for (int j = threadIdx.x; j < ev.nb; j += blockDim.x) {
+            int ifr;
+            double tf;
+            freq_cell(gd, (int64_t)(ev.k_lo + j), ev.N, fs, ifr, tf);
+            const int li = ifr - f_lo - w0;
+            if (li < 0 || li > wn - 2) continue;  // in another window
+            if constexpr (RESP) {
+                if (wq > 0.0) tf = rint(tf * wq) / wq;
+            }
+            C2<T> h[4];
 #pragma unroll
-            for (int cp = 0; cp < 4; ++cp) h[cp] = clerp(sl[ifr - f_lo][cp], sl[ifr + 1 - f_lo][cp], (T)tf);
-        } else {
-            interp4<Tt, T>(nodes, gd, ifr, (T)tf, iz, (T)tz, ia, ja, (T)ta, h);
-        }
-        MBin<T> m;
-        if constexpr (RESP) {
-            m.p0 = h[0];
-            m.p1 = h[1];
-            m.q0 = h[2];
-            m.q1 = h[3];
-        } else if constexpr (sizeof(T) == 4) {
-            const C2<float> det = csub(cmul(h[0], h[3]), cmul(h[1], h[2]));
-            float fro2 = 0.f;
+            for (int cp = 0; cp < 4; ++cp) h[cp] = clerp(sl[li][cp], sl[li + 1][cp], (T)tf);
+            MBin<T> m;
+            if constexpr (RESP) {
+                m.p0 = h[0];
+                m.p1 = h[1];
+                m.q0 = h[2];
+                m.q1 = h[3];
+            } else if constexpr (sizeof(T) == 4) {
+                const C2<float> det = csub(cmul(h[0], h[3]), cmul(h[1], h[2]));
+                float fro2 = 0.f;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) fro2 += h[i].re * h[i].re + h[i].im * h[i].im;
-            const float ad2 = det.re * det.re + det.im * det.im;
-            const float thr = (float)fallback_rel * fro2;
-            if (ad2 < thr * thr) {
-                C2<double> hd[4];
+                for (int i = 0; i < 4; ++i) fro2 += h[i].re * h[i].re + h[i].im * h[i].im;
+                const float ad2 = det.re * det.re + det.im * det.im;
+                const float thr = (float)fallback_rel * fro2;
+                if (ad2 < thr * thr) {
+                    C2<double> hd[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) hd[i] = C2<double>{(double)h[i].re, (double)h[i].im};
-                MBin<double> md;
-                n_sg += invert2<double>(hd, 1.0 / (double)ev.N, singular_rel, md);
-                ++n_fb;
-                m.p0 = C2<T>{(T)md.p0.re, (T)md.p0.im};
-                m.p1 = C2<T>{(T)md.p1.re, (T)md.p1.im};
-                m.q0 = C2<T>{(T)md.q0.re, (T)md.q0.im};
-                m.q1 = C2<T>{(T)md.q1.re, (T)md.q1.im};
+                    for (int i = 0; i < 4; ++i) hd[i] = C2<double>{(double)h[i].re, (double)h[i].im};
+                    MBin<double> md;
+                    n_sg += invert2<double>(hd, 1.0 / (double)ev.N, singular_rel, md);
+                    ++n_fb;
+                    m.p0 = C2<T>{(T)md.p0.re, (T)md.p0.im};
+                    m.p1 = C2<T>{(T)md.p1.re, (T)md.p1.im};
+                    m.q0 = C2<T>{(T)md.q0.re, (T)md.q0.im};
+                    m.q1 = C2<T>{(T)md.q1.re, (T)md.q1.im};
+                } else {
+                    n_sg += invert2<T>(h, inv_n, singular_rel, m);
+                }
             } else {
                 n_sg += invert2<T>(h, inv_n, singular_rel, m);
             }
-        } else {
-            n_sg += invert2<T>(h, inv_n, singular_rel, m);
+            out[j] = m;
         }
-        out[j] = m;
     }
     if (!RESP && counts != nullptr) {
         if (n_fb) atomicAdd(&cnt[0], n_fb);

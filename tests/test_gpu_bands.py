@@ -133,3 +133,47 @@ def test_band_envelope_peaks(api, coarse, identity, case, prec):
     ref = oracle_band(tref, v, dirs, lo, hi)
     frac = check_peaks(peak.cpu().numpy(), arg.cpu().numpy(), ref, TOL_FP64 if prec == "fp64" else TOL_FP32)
     assert frac > 0.9
+
+
+# 0-100 MHz in 0.1 MHz steps: the 30-80 MHz band spans about 500 frequency nodes and the
+# 1-99 MHz band about 980, more than the coefficient kernel's angular slice holds in LDS at
+# once (256 nodes), so it takes the band in windows of nodes; every window boundary is crossed.
+GRID_DENSE_F = S.Grid(1001, 10, 36, 0, 100_000, 0.0, 10.0, 0.0, 10.0)
+
+
+@pytest.mark.parametrize("band", [(30_000_000, 80_000_000), (1_000_000, 99_000_000)], ids=["30-80", "1-99"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_dense_frequency_grid_windows(api, prec, band):
+    import torch
+    lo, hi = band
+    g = GRID_DENSE_F
+    t = S.pattern_table(g, cfg=1)
+    p = api.AU_PREC_FP64 if prec == "fp64" else api.AU_PREC_FP32
+    tref = t if prec == "fp64" else t.astype(np.complex64)
+    tab = api.Table(g, tref)
+    n, s = 2048, 3
+    dt = np.float64 if prec == "fp64" else np.float32
+    v = S.traces(s, n, cfg=3, event=77, dtype=dt)
+    dirs = np.array([[40.0, 120.0], [72.5, 355.0], [3.0, 8.0]])
+    ev = api.make_event(s, n, prec=p, trace_dtype=api.AU_F64 if prec == "fp64" else api.AU_F32,
+                        band_lo_hz=lo, band_hi_hz=hi)
+    k_lo, nb = api.band_bins(ev)
+    nodes = (k_lo + nb - 1) * S.FS_HZ // (n * g.df_hz) - k_lo * S.FS_HZ // (n * g.df_hz) + 2
+    assert nodes > 256
+    say("dense frequency grid", prec, "band", lo, hi, "nodes", nodes)
+    out = api.unfold_direction_scan(tab, ev, torch.from_numpy(v).cuda(), dirs).cpu().numpy()
+    ref = O.unfold(g, tref.astype(np.complex128), np.asarray(v, dtype=np.float64), dirs, S.FS_HZ, lo, hi)[0]
+    assert_traces_close(out, ref, TOL_FP64 if prec == "fp64" else TOL_FP32, "dense grid %s" % prec)
+    # the interpolated pattern itself, at every bin (pattern-response mode of the same kernel)
+    from test_gpu_parity import corner_max
+    h = api.pattern_response(tab, ev, dirs).cpu().numpy()
+    t128 = tref.astype(np.complex128)
+    for di, (z, a) in enumerate(dirs):
+        for j in range(nb):
+            ref_h = O.pattern_at_bin(g, t128, k_lo + j, n, S.FS_HZ, z, a)
+            err = np.max(np.abs(h[di, j] - ref_h))
+            if prec == "fp64":
+                assert err <= 8e-15 * max(np.max(np.abs(ref_h)), 1e-300), (di, j, err)
+            else:
+                # 7 lerps x 6 operations x 2^-24 of the largest corner, as for the coarse grid
+                assert err <= 42 * 2.0 ** -24 * corner_max(g, t128, k_lo + j, n, z, a), (di, j, err)
