@@ -85,8 +85,29 @@ __device__ __forceinline__ void freq_cell(const GridDev& g, int64_t k, int n, in
 {
     const int64_t num = k * fs - g.f0_hz * (int64_t)n;
     const int64_t den = (int64_t)n * g.df_hz;
-    int64_t i = num / den;
-    const int64_t r = num - i * den;
+    // The truncated quotient num / den without a 64-bit integer division:
+    // |num| < 2^53, so num and den are exact in double and the estimate is
+    // within one of the quotient; one correction step makes it exact (the
+    // remainder takes the sign of num, as the integer division's does).
+    int64_t i = (int64_t)((double)num * (1.0 / (double)den));
+    int64_t r = num - i * den;
+    if (num >= 0) {
+        if (r < 0) {
+            --i;
+            r += den;
+        } else if (r >= den) {
+            ++i;
+            r -= den;
+        }
+    } else {
+        if (r > 0) {
+            ++i;
+            r -= den;
+        } else if (r <= -den) {
+            --i;
+            r += den;
+        }
+    }
     double t = (double)r / (double)den;
     if (i > g.n_freq - 2) {
         i = g.n_freq - 2;
