@@ -234,13 +234,17 @@ def test_batch_plan_uneven_events(api, coarse, flags):
     assert plan.station_unfolds == sum(s * len(d) for s, _, d in specs)
 
 
-def test_batch_plan_fp32_matches_plain_fp32(api):
+# the default band (spectra by the streaming kernel) and one wider than N/4 bins (by the
+# one-station-per-workgroup kernel): plan and plain scan take the same kernel either way
+@pytest.mark.parametrize("band", [(30_000_000, 80_000_000), (1_000_000, 99_000_000)], ids=["30-80", "1-99"])
+def test_batch_plan_fp32_matches_plain_fp32(api, band):
     import torch
+    lo, hi = band
     t32 = S.pattern_table(GF, cfg=2).astype(np.complex64)
     tab = api.Table(GF, t32)
     specs = [(5, 2048, S.direction_grid(2, 2)), (11, 4096, S.direction_grid(2, 1)), (4, 2048, [[30.0, 30.0]])]
-    say("batch fp32 graph+persistent vs plain")
-    plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=3)
+    say("batch fp32 graph+persistent vs plain, band", lo, hi)
+    plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=3, band_lo_hz=lo, band_hi_hz=hi)
     volt = np.zeros(plan.volt_elems, dtype=np.float32)
     vs = []
     for e, (s, n, _) in enumerate(specs):
@@ -252,11 +256,12 @@ def test_batch_plan_fp32_matches_plain_fp32(api):
     torch.cuda.synchronize()
     for e, (s, n, d) in enumerate(specs):
         got = plan.event_output(out, e).cpu().numpy()
-        ev = api.make_event(s, n, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32)
+        ev = api.make_event(s, n, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, band_lo_hz=lo, band_hi_hz=hi)
         plain = api.unfold_direction_scan(tab, ev, to_dev(vs[e]), d).cpu().numpy()
         # same kernels, same per-unit arithmetic: bitwise equal whatever the batch mix
         assert np.array_equal(got, plain)
-        ref, _, _ = oracle_unfold(GF, t32, vs[e], d)
+        ref = O.unfold(GF, t32.astype(np.complex128), vs[e].astype(np.float64), np.asarray(d, dtype=np.float64),
+                       S.FS_HZ, lo, hi)[0]
         assert_traces_close(got, ref, TOL_FP32, "batch fp32 event %d" % e)
 
 
