@@ -293,6 +293,10 @@ __global__ __launch_bounds__(N / 8) void k_spectrum_stream(const Tin* __restrict
         int nb, k_lo;
     };
     auto locate = [&](int uu) {
+        // uu is uniform; stated so, the unit is read with a scalar load: a
+        // vector load here would wait (in issue order) for the previous
+        // station's stores
+        uu = __builtin_amdgcn_readfirstlane(uu);
         int e = 0, s = uu;
         if (units != nullptr) {
             const int2 su = units[uu];
