@@ -503,8 +503,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(every event is independent; see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(events are independent: a multi-GPU run would give each GPU its own events "
+              "and its own copy of the pattern table)", file=sys.stderr)
         sys.exit(2)
 
     import torch
