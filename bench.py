@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 # WRITE_SIZE x 1.000 (copy-probe calibration), keyed by kernel and launch size.
 PROFILED_TRAFFIC_SOURCE = "profiles/k_unfold_fp32_batched_256events.md"
 PROFILED_TRAFFIC_BYTES = {
-    ("k_unfold<float, 4096, 8, 8, 3, false, false, true>", 2047488): (1182281 + 65522548) * 1024,
+    ("k_unfold<float, 4096, 8, 8, 3, false, false, true>", 2047488): (1190285 + 65522433) * 1024,
 }
 HBM_PEAK_GBS = 8000.0
 
