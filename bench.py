@@ -591,10 +591,15 @@ def main():
     for ci, (n, su, var) in enumerate(classes):
         unfold_ms = stage_ms[ci, 2] / runs
         bytes_launch = su * 2 * n * 4
+        # forward spectra: each station's two float32 traces read, its in-band bins written (16 B each)
+        stations = sum(s for s, n_e, _ in specs if n_e == n)
+        nb = api.band_bins(api.make_event(1, n, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32))[1]
+        spectrum_ms = stage_ms[ci, 0] / runs
         per_class.append({"kernel": api.unfold_kernel_name(api.AU_PREC_FP32, n, var), "variant": var,
                           "n_samples": n,
                           "station_unfolds": int(su),
-                          "spectrum_ms": stage_ms[ci, 0] / runs, "coef_ms": stage_ms[ci, 1] / runs,
+                          "spectrum_ms": spectrum_ms, "coef_ms": stage_ms[ci, 1] / runs,
+                          "spectrum_algorithmic_GBs": stations * (2 * n * 4 + nb * 16) / (spectrum_ms / 1e3) / 1e9,
                           "unfold_ms": unfold_ms,
                           "unfold_algorithmic_GBs": bytes_launch / (unfold_ms / 1e3) / 1e9})
     dom = max(per_class, key=lambda c: c["unfold_ms"])
