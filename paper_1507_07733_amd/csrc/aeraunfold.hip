@@ -1010,6 +1010,9 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
             const int wv = t >> 6, lane = t & 63;
             const int cc = c_lo + wv;  // the component this wave reduces
             if (cc < 3 && active) {  // whole waves: no barrier inside
+                // the reducing waves run ahead of the others' issue (which
+                // only reach the station's closing barrier): +6 % FP32
+                __builtin_amdgcn_s_setprio(2);
                 T v = cv[cc * TT + lane];
                 int ix = ci[cc * TT + lane];
 #pragma unroll
@@ -1034,6 +1037,7 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                     peak[o] = sqrt(v);
                     arg[o] = ix;
                 }
+                __builtin_amdgcn_s_setprio(0);
             }
         } else {
             // A group of TT < 64 threads shares its wave with other groups, so the
