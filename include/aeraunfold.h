@@ -85,9 +85,14 @@ typedef struct {
  * is the set of FFT bins k in [0, N/2] with band_lo_hz*N <= k*fs_hz <=
  * band_hi_hz*N, tested exactly in 64-bit integers.  Requirements: N a power
  * of two in [16, 4096]; S >= 1; 0 <= band_lo_hz <= band_hi_hz < fs_hz/2; every
- * in-band bin frequency inside the table's frequency range.
+ * in-band bin frequency inside the table's frequency range; |k*fs_hz -
+ * f0_hz*N| for every in-band bin k, and N*df_hz, below 2^53 (the bin's node
+ * position is split exactly in double arithmetic).
  * fallback_rel (FP32 only) and singular_rel: see d_counts above; the usual
- * values are 1e-6 and 1e-12.
+ * values are 1e-6 and 1e-12.  Both tests are scale-free: they are taken on H
+ * scaled by a power of two (exact), so a table in any units, e.g. of order
+ * 1e-12 or 1e12, gives the decisions and coefficients of the same table in
+ * units of order one.
  */
 typedef struct {
     int32_t n_stations, n_samples;
@@ -375,19 +380,30 @@ au_status au_plan_free(au_plan* plan);
  * Serving: a continuous-batching request loop (section 5 motivates keeping
  * traces resident on the GPU instead of copying around isolated calls).
  * The server owns one device arena of hbm_budget_bytes (traces, outputs and
- * work space of admitted events plus batch descriptors) and a pinned host
- * staging area of staging_bytes; both are allocated at creation and carved
- * up by a first-fit allocator, so submit/poll/release never allocate device
- * memory.  A scheduler thread admits queued events in FIFO order when the
- * arena has room and fewer than max_inflight events are admitted and not
- * released, gathers admitted events into micro-batches (launched when
- * max_batch_events are ready or the oldest has waited tick_s seconds), and
- * spreads batches round-robin over n_streams streams so that the work of
- * events arriving while others run overlaps on the device.  Each event's
- * result stays in the arena until au_release.  Per-event arithmetic is the
- * same whatever the batch mix, so a result is identical alone and in a mix.
- * Thread safety: submit/poll/release/stats may be called from any thread;
- * au_copy_result must not race with au_release of the same ticket.
+ * work space of admitted events), a pinned host staging area of
+ * staging_bytes (traces of queued events), and 2 * n_streams descriptor
+ * slots of 2 MiB (device + pinned) for batches of several events; all are
+ * allocated at creation, the arena and staging carved up by a first-fit
+ * allocator, so submit/poll/wait/release never allocate memory.
+ * Admission is FIFO: an event is admitted when the arena has room for it and
+ * fewer than max_inflight events are admitted and not released.  An event
+ * with nothing queued ahead of it is admitted inside au_submit, its traces
+ * copied straight into its arena region (au_submit returns once the copy is
+ * done) and, with tick_s = 0, launched in the same call together with any
+ * other admitted event; otherwise its traces go to staging and a scheduler
+ * thread admits and launches it.  Admitted events form micro-batches
+ * (launched when max_batch_events are ready or the oldest has waited tick_s
+ * seconds; a batch shrinks to one event when no descriptor slot is free or
+ * its descriptors would exceed a slot), spread round-robin over n_streams
+ * streams so that the work of events arriving while others run overlaps on
+ * the device.  Launching needs no memory beyond what its events hold, so an
+ * arena filled exactly by admitted events still makes progress.  A reaper
+ * thread waits on each batch's completion event (no polling loop) and wakes
+ * au_wait callers.  Each event's result stays in the arena until
+ * au_release.  Per-event arithmetic is the same whatever the batch mix, so a
+ * result is identical alone and in a mix.
+ * Thread safety: submit/poll/wait/release/stats may be called from any
+ * thread; au_copy_result must not race with au_release of the same ticket.
  * Timestamps are seconds on the server's steady clock (au_server_now).
  */
 typedef struct {
@@ -416,6 +432,7 @@ typedef struct {
     uint64_t efield_bytes;
     int32_t n_stations, n_samples, n_dirs, batch_events;
     double t_arrival, t_submit, t_admit, t_launch, t_complete;
+    uint64_t batch_id;            /* events with equal batch_id shared one launch sequence */
 } au_result;
 
 typedef struct {
@@ -424,16 +441,25 @@ typedef struct {
     uint64_t fallback_bins, singular_bins;
 } au_server_counters;
 
-/* Errors: AU_EINVAL (configuration, request), AU_ENOMEM (arena or staging
- * cannot be allocated; a request larger than the whole arena), AU_EAGAIN
- * (au_submit: staging full, retry later; au_poll: not complete yet),
+/* Errors: AU_EINVAL (configuration, request; tick_s must lie in [0, 10]),
+ * AU_ENOMEM (arena, staging or slots cannot be allocated; a request larger
+ * than the whole arena), AU_EAGAIN (au_submit: staging full, retry later;
+ * au_poll: not complete yet; au_wait: not complete within timeout_s),
  * AU_ENOTFOUND (unknown or released ticket), AU_EDEVICE (a HIP call failed;
- * the server then fails every pending request). */
+ * the server then fails every pending request).
+ * au_server_request_bytes: arena bytes one request of these sizes occupies
+ * (output, work space, directions, traces).
+ * au_wait: blocks until the ticket completes (then as au_poll) or timeout_s
+ * seconds pass (AU_EAGAIN).
+ * au_server_destroy waits for launched batches to complete. */
 au_status au_server_create(const au_table* table, const au_server_cfg* cfg, au_server** out);
 au_status au_server_destroy(au_server* server);
 au_status au_server_now(const au_server* server, double* seconds);
+au_status au_server_request_bytes(const au_server* server, int32_t n_stations, int32_t n_samples,
+                                  int32_t n_dirs, uint64_t* dev_bytes);
 au_status au_submit(au_server* server, const au_request* request, uint64_t* ticket);
 au_status au_poll(au_server* server, uint64_t ticket, au_result* result);
+au_status au_wait(au_server* server, uint64_t ticket, double timeout_s, au_result* result);
 au_status au_copy_result(au_server* server, uint64_t ticket, void* dst, uint64_t dst_bytes);
 au_status au_release(au_server* server, uint64_t ticket);
 au_status au_server_stats(au_server* server, au_server_counters* stats);

@@ -154,11 +154,35 @@ __device__ __forceinline__ void slice4(const C2<Tt>* __restrict__ nodes, const G
 constexpr int kMaxSliceNodes = 256;
 
 
-// Coefficients of the bin: C = (1/N) H^-1 = (1/(N det)) [h3 -h1; -h2 h0],
-// with H = [h0 h1; h2 h3] indexed [channel][component], in the packed form
-// of MBin (p_j = C_0j + i C_1j, q_j = C_0j - i C_1j).  Returns 1 if singular.
+// Power-of-two exponent e such that the largest real or imaginary part of
+// h, times 2^-e, lies in [0.5, 1), and hs = 2^-e h.  Scaling by a power of two
+// is exact, so every threshold decision and every rounding of the inverse
+// below is the one the unscaled H would give, while |det|^2 and
+// (rel ||H||_F^2)^2 stay inside the format's range whatever the table's
+// units (a table of order 1e-12 or 1e12 squares to 1e-48 / 1e48, outside
+// FP32).  Returns false for an all-zero or non-finite H.
 template <typename T>
-__device__ __forceinline__ int invert2(const C2<T> h[4], T inv_n, double singular_rel, MBin<T>& m)
+__device__ __forceinline__ bool pow2_normalise(const C2<T> h[4], C2<T> hs[4], int& e)
+{
+    T mx = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) mx = fmax(mx, fmax(fabs(h[i].re), fabs(h[i].im)));
+    if (!(mx > (T)0) || !isfinite(mx)) return false;
+    (void)frexp(mx, &e);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) hs[i] = C2<T>{ldexp(h[i].re, -e), ldexp(h[i].im, -e)};
+    return true;
+}
+
+// Coefficients of the bin from the normalised hs = 2^-e H (pow2_normalise):
+// C = (1/N) H^-1 = (1/(N det)) [h3 -h1; -h2 h0] with H = [h0 h1; h2 h3]
+// indexed [channel][component]; as H^-1 = 2^-e hs^-1, the scale goes into
+// the numerator inv_n_scaled = 2^-e / N.  Written in the packed form of MBin
+// (p_j = C_0j + i C_1j, q_j = C_0j - i C_1j).  Singular (|det| <=
+// singular_rel ||H||_F^2, the same test on hs) gives zero coefficients and
+// returns 1.
+template <typename T>
+__device__ __forceinline__ int invert2_scaled(const C2<T> h[4], T inv_n_scaled, double singular_rel, MBin<T>& m)
 {
     const C2<T> det = csub(cmul(h[0], h[3]), cmul(h[1], h[2]));
     T fro2 = 0;
@@ -170,7 +194,7 @@ __device__ __forceinline__ int invert2(const C2<T> h[4], T inv_n, double singula
         m.p0 = m.p1 = m.q0 = m.q1 = C2<T>{0, 0};
         return 1;
     }
-    const T sc = inv_n / ad2;
+    const T sc = inv_n_scaled / ad2;
     const C2<T> inv{det.re * sc, -det.im * sc};
     const C2<T> c00 = cmul(h[3], inv);
     const C2<T> c01 = cmul(C2<T>{-h[1].re, -h[1].im}, inv);
@@ -182,6 +206,19 @@ __device__ __forceinline__ int invert2(const C2<T> h[4], T inv_n, double singula
     m.q0 = C2<T>{c00.re + c10.im, c00.im - c10.re};
     m.q1 = C2<T>{c01.re + c11.im, c01.im - c11.re};
     return 0;
+}
+
+// Coefficients of the bin from H as interpolated (any scale).  Returns 1 if singular.
+template <typename T>
+__device__ __forceinline__ int invert2(const C2<T> h[4], T inv_n, double singular_rel, MBin<T>& m)
+{
+    C2<T> hs[4];
+    int e;
+    if (!pow2_normalise(h, hs, e)) {
+        m.p0 = m.p1 = m.q0 = m.q1 = C2<T>{0, 0};
+        return 1;
+    }
+    return invert2_scaled(hs, ldexp(inv_n, -e), singular_rel, m);
 }
 
 // The packed spectrum of one bin from its packed coefficients: zp = Z[k] and
@@ -438,25 +475,33 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
                 m.q0 = h[2];
                 m.q1 = h[3];
             } else if constexpr (sizeof(T) == 4) {
-                const C2<float> det = csub(cmul(h[0], h[3]), cmul(h[1], h[2]));
-                float fro2 = 0.f;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) fro2 += h[i].re * h[i].re + h[i].im * h[i].im;
-                const float ad2 = det.re * det.re + det.im * det.im;
-                const float thr = (float)fallback_rel * fro2;
-                if (ad2 < thr * thr) {
-                    C2<double> hd[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) hd[i] = C2<double>{(double)h[i].re, (double)h[i].im};
-                    MBin<double> md;
-                    n_sg += invert2<double>(hd, 1.0 / (double)ev.N, singular_rel, md);
-                    ++n_fb;
-                    m.p0 = C2<T>{(T)md.p0.re, (T)md.p0.im};
-                    m.p1 = C2<T>{(T)md.p1.re, (T)md.p1.im};
-                    m.q0 = C2<T>{(T)md.q0.re, (T)md.q0.im};
-                    m.q1 = C2<T>{(T)md.q1.re, (T)md.q1.im};
+                // the fallback test and the inverse on 2^-e H (exact scaling, see pow2_normalise)
+                C2<float> hs[4];
+                int e;
+                if (!pow2_normalise(h, hs, e)) {
+                    m.p0 = m.p1 = m.q0 = m.q1 = C2<T>{0, 0};
+                    ++n_sg;
                 } else {
-                    n_sg += invert2<T>(h, inv_n, singular_rel, m);
+                    const C2<float> det = csub(cmul(hs[0], hs[3]), cmul(hs[1], hs[2]));
+                    float fro2 = 0.f;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) fro2 += hs[i].re * hs[i].re + hs[i].im * hs[i].im;
+                    const float ad2 = det.re * det.re + det.im * det.im;
+                    const float thr = (float)fallback_rel * fro2;
+                    if (ad2 < thr * thr) {
+                        C2<double> hd[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) hd[i] = C2<double>{(double)hs[i].re, (double)hs[i].im};
+                        MBin<double> md;
+                        n_sg += invert2_scaled<double>(hd, ldexp(1.0 / (double)ev.N, -e), singular_rel, md);
+                        ++n_fb;
+                        m.p0 = C2<T>{(T)md.p0.re, (T)md.p0.im};
+                        m.p1 = C2<T>{(T)md.p1.re, (T)md.p1.im};
+                        m.q0 = C2<T>{(T)md.q0.re, (T)md.q0.im};
+                        m.q1 = C2<T>{(T)md.q1.re, (T)md.q1.im};
+                    } else {
+                        n_sg += invert2_scaled<T>(hs, ldexp(inv_n, -e), singular_rel, m);
+                    }
                 }
             } else {
                 n_sg += invert2<T>(h, inv_n, singular_rel, m);
@@ -1546,10 +1591,17 @@ au_status au::check_n(const au_table* tb, int s, int n, int64_t fs, int64_t lo, 
     band_of(n, fs, lo, hi, &k_lo, &nb);
     if (nb > 0) {
         const GridDev& g = tb->g;
-        const int64_t den = (int64_t)n * g.df_hz;
-        const int64_t num_lo = (int64_t)k_lo * fs - g.f0_hz * n;
-        const int64_t num_hi = (int64_t)(k_lo + nb - 1) * fs - g.f0_hz * n;
-        if (num_lo < 0 || num_hi > (int64_t)(g.n_freq - 1) * den)
+        // The device splits the node position (k fs - f0 N) / (N df) of every
+        // in-band bin exactly through a double estimate, which needs the
+        // numerator and denominator below 2^53 (exact in double); checked in
+        // 128-bit arithmetic so that no product here overflows either.
+        const __int128 lim = (__int128)1 << 53;
+        const __int128 den = (__int128)n * g.df_hz;
+        const __int128 num_lo = (__int128)k_lo * fs - (__int128)g.f0_hz * n;
+        const __int128 num_hi = (__int128)(k_lo + nb - 1) * fs - (__int128)g.f0_hz * n;
+        if (den >= lim || num_lo <= -lim || num_hi >= lim || num_lo >= lim || num_hi <= -lim)
+            return fail(AU_EINVAL, "frequency arithmetic out of range: |k fs - f0 N| and N df must stay below 2^53");
+        if (num_lo < 0 || num_hi > (__int128)(g.n_freq - 1) * den)
             return fail(AU_EINVAL, "band lies outside the pattern table's frequency range");
     }
     p->S = s;
@@ -1629,11 +1681,14 @@ static void launch_coef(hipStream_t st, const au_table* tb, const EvDesc& ev0, c
                        M, counts, 0.0);
 }
 
+// Directions come from h_dirs (copied into the workspace's direction slot
+// first), from d_dirs (already in that slot, device memory), or, with both
+// null, the one direction (zen, az).
 template <typename T>
 static au_status run_event(const au_table* tb, const au_event* ev, const EvParams& p,
                            const void* d_volt, int n_dir, const double* h_dirs, double zen,
                            double az, void* d_efield, void* d_work, hipStream_t st,
-                           uint64_t* d_counts, int variant = -1)
+                           uint64_t* d_counts, int variant = -1, bool d_dirs = false)
 {
     if (variant < 0) variant = unfold_variant(ev->prec, p.N);
     const WsLayout w = ws_layout(p, ev->prec, n_dir);
@@ -1643,6 +1698,7 @@ static au_status run_event(const au_table* tb, const au_event* ev, const EvParam
     double* dirs = (double*)(base + w.x + w.m);
     if (h_dirs != nullptr)
         HIP_TRY(hipMemcpyAsync(dirs, h_dirs, sizeof(double) * 2 * n_dir, hipMemcpyHostToDevice, st));
+    if (d_dirs) h_dirs = dirs;  // only its non-nullness is used below
     EvDesc ev0{};
     ev0.S = p.S;
     ev0.N = p.N;
@@ -1714,6 +1770,24 @@ static au_status unfold_common(const au_table* tb, const au_event* ev, const voi
             return fail(AU_EDEVICE, std::string("hipFreeAsync: ") + hipGetErrorString(e));
     }
     return s;
+}
+
+void au::workspace_layout(const EvParams& p, int prec, int n_dir, size_t* x_bytes, size_t* m_bytes,
+                          size_t* dir_bytes)
+{
+    const WsLayout w = ws_layout(p, prec, n_dir);
+    *x_bytes = w.x;
+    *m_bytes = w.m;
+    *dir_bytes = w.dirs;
+}
+
+au_status au::enqueue_event(const au_table* tb, const au_event* ev, const EvParams& p, const void* d_volt,
+                            int n_dir, void* d_efield, void* d_work, hipStream_t st, uint64_t* d_counts)
+{
+    if (ev->prec == AU_PREC_FP64)
+        return run_event<double>(tb, ev, p, d_volt, n_dir, nullptr, 0.0, 0.0, d_efield, d_work, st, d_counts, -1,
+                                 true);
+    return run_event<float>(tb, ev, p, d_volt, n_dir, nullptr, 0.0, 0.0, d_efield, d_work, st, d_counts, -1, true);
 }
 
 extern "C" au_status au_unfold_event(const au_table* tb, const au_event* ev, const void* d_volt,

@@ -1,13 +1,22 @@
-"""Shared test helpers: the per-trace comparison rule and oracle calls.
+"""Shared test helpers: the comparison rules and oracle calls.
 
-Comparison rule: for every output trace (direction, station, component),
-r = max_n |E_gpu - E_oracle| / max_n |E_oracle|; an all-zero oracle trace
-requires an all-zero GPU trace.  Bars: r <= 1e-12 for the FP64 path,
-r <= 1e-5 for the FP32 path.  The FP32 bar is stated relative to the peak
-amplitude of the station's E-field trace (both polarisation components,
-station_errors); the per-component form used by most tests is stricter and
-holds there, but a component carrying a small fraction of the field picks
-up the rounding of the strong one through the inverse.
+FP64 path: for every output trace (direction, station, component),
+r = max_n |E_gpu - E_oracle| / max_n |E_oracle| <= 1e-12; an all-zero oracle
+trace requires an all-zero GPU trace.
+
+FP32 path (assert_fp32_close), the one rule every FP32 test applies:
+  * per station E-field trace (both polarisation components): max over both
+    components and samples of |E_gpu - E_oracle|, divided by the larger
+    component peak, <= 1e-5 ("relative to peak trace amplitude");
+  * per component, normalised by that component's own peak, <= 1e-5 for
+    every component carrying at least 10 % of the station's peak.
+Why per station: the FP32 solve E = H^-1 X mixes both channels, so its
+rounding error (input, interpolation and inverse rounding amplified by
+kappa = ||H||_F^2 / |det|) is of order kappa * u * |E|, |E| the field
+vector's magnitude, in *both* components; a component with share s of the
+peak then carries a relative error of order kappa * u / s, which no FP32
+design keeps below 1e-5 for weak components.  Strong components keep the
+per-component bar.
 """
 import numpy as np
 
@@ -16,6 +25,8 @@ from paper_1507_07733_amd import synth as S
 
 TOL_FP64 = 1e-12
 TOL_FP32 = 1e-5
+STRONG_SHARE = 0.1          # components at least this share of the station peak keep the per-component bar
+U32 = 2.0 ** -24            # unit roundoff of float32
 
 
 def trace_errors(got, ref):
@@ -52,3 +63,46 @@ def oracle_unfold(grid, table, volt, dirs, units=None, singular_rel=1e-12):
     """Oracle on the same values the GPU saw (float32 inputs promoted exactly)."""
     return O.unfold(grid, np.asarray(table).astype(np.complex128), np.asarray(volt, dtype=np.float64),
                     dirs, S.FS_HZ, S.BAND_LO_HZ, S.BAND_HI_HZ, singular_rel=singular_rel, units=units)
+
+
+def fp32_errors(got, ref):
+    """(per-station r [..], per-component r [..][2], strong-component mask [..][2]) of [..][2][N] traces."""
+    ref = np.asarray(ref, dtype=np.float64)
+    rs = station_errors(got, ref)
+    r = trace_errors(got, ref)
+    pk = np.max(np.abs(ref), axis=-1)
+    strong = pk >= STRONG_SHARE * np.max(pk, axis=-1, keepdims=True)
+    return rs, r, strong
+
+
+def assert_fp32_close(got, ref, tol=TOL_FP32, what=""):
+    """The FP32 rule (module docstring): per station <= tol and per strong component <= tol."""
+    rs, r, strong = fp32_errors(got, ref)
+    ws = float(np.max(rs)) if rs.size else 0.0
+    wc = float(np.max(r[strong])) if np.any(strong) else 0.0
+    assert ws <= tol, "%s: max per-station error %.3e > %.1e" % (what, ws, tol)
+    assert wc <= tol, "%s: max strong-component error %.3e > %.1e" % (what, wc, tol)
+    return rs, r
+
+
+def assert_close(got, ref, fp32, what=""):
+    """FP64 per-trace bar or the FP32 rule."""
+    if fp32:
+        return assert_fp32_close(got, ref, TOL_FP32, what)
+    return assert_traces_close(got, ref, TOL_FP64, what)
+
+
+def oracle_kappa(grid, table, n, dirs):
+    """kappa per direction: max over in-band bins of ||H||_F^2 / |det H|, H from the oracle's interpolation."""
+    t = np.asarray(table).astype(np.complex128)
+    ks = S.band_bins(n)
+    out = np.zeros(len(dirs))
+    for i, (z, a) in enumerate(np.asarray(dirs, dtype=np.float64).reshape(-1, 2)):
+        kap = 0.0
+        for k in ks:
+            h = O.pattern_at_bin(grid, t, int(k), n, S.FS_HZ, float(z), float(a))
+            det = abs(h[0, 0] * h[1, 1] - h[0, 1] * h[1, 0])
+            f2 = float(np.sum(np.abs(h) ** 2))
+            kap = max(kap, np.inf if det == 0 else f2 / det)
+        out[i] = kap
+    return out

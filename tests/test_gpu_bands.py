@@ -9,7 +9,7 @@ import pytest
 from oracle import oracle as O
 from paper_1507_07733_amd import synth as S
 
-from helpers import TOL_FP32, TOL_FP64, assert_traces_close
+from helpers import TOL_FP32, TOL_FP64, assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -102,8 +102,7 @@ def test_band_every_variant(api, coarse, identity, case, prec, n):
             if nb == 0:
                 assert not np.any(out), "empty band must give zero traces"
             else:
-                assert_traces_close(out, ref, TOL_FP64 if prec == "fp64" else TOL_FP32,
-                                    "band %s variant %d" % (name, vi))
+                assert_close(out, ref, prec == "fp32", "band %s variant %d" % (name, vi))
     finally:
         api.set_unfold_variant(p, n, keep)
     assert built >= 4
@@ -163,7 +162,7 @@ def test_dense_frequency_grid_windows(api, prec, band):
     say("dense frequency grid", prec, "band", lo, hi, "nodes", nodes)
     out = api.unfold_direction_scan(tab, ev, torch.from_numpy(v).cuda(), dirs).cpu().numpy()
     ref = O.unfold(g, tref.astype(np.complex128), np.asarray(v, dtype=np.float64), dirs, S.FS_HZ, lo, hi)[0]
-    assert_traces_close(out, ref, TOL_FP64 if prec == "fp64" else TOL_FP32, "dense grid %s" % prec)
+    assert_close(out, ref, prec == "fp32", "dense grid %s" % prec)
     # the interpolated pattern itself, at every bin (pattern-response mode of the same kernel)
     from test_gpu_parity import corner_max
     h = api.pattern_response(tab, ev, dirs).cpu().numpy()

@@ -1,14 +1,18 @@
 """GPU parity of the device direction fit (au_direction_fit) against the
 oracle, level by level:
   - the station times behind each level's scores are the envelope-scan
-    maxima of that level's candidates (checked valid against the oracle's
-    envelopes on the coarse level);
+    maxima of that level's candidates, each checked to be a valid maximum of
+    the oracle's total-field envelope at every level (all candidates, or a
+    sample of the coarse level at full size);
   - each score equals the oracle's score of the same times (1e-10 relative);
   - each best index is the first minimum of the GPU's scores;
   - each refinement grid equals the oracle's grid around the GPU's previous
     best exactly (both evaluate it in plain double);
-and where every level chose the same candidate as the oracle's fit, the
-result equals the oracle's exactly."""
+and, unconditionally for FP64, against the oracle's own fit: level by level
+the grids are equal and the scores agree while both picked the same
+candidate; where the picks differ, the oracle's score at the GPU's pick
+equals the oracle's minimum within rounding (a tie), and when every level
+picked the same candidate the results are equal."""
 import numpy as np
 import pytest
 
@@ -33,7 +37,16 @@ def api():
     return A
 
 
-def check_fit(api, tab, g, t, ev, v, dv, pos, coarse, fit, levels, k, step, tol, check_times=True):
+def check_times_valid(g, t, v, pos, dirs, tt, tol, sel):
+    """tt [D][S]: each GPU time is a maximum of the oracle's total-field envelope (directions sel)."""
+    units = np.array([[d, s] for d in sel for s in range(len(pos))])
+    e, _, _ = oracle_unfold(g, t, v, dirs, units=units)
+    for u, (d, s) in enumerate(units):
+        env = np.sqrt(O.envelope(e[u, 0]) ** 2 + O.envelope(e[u, 1]) ** 2)
+        assert env[tt[d, s]] >= env.max() * (1 - 2 * tol), (d, s)
+
+
+def check_fit(api, tab, g, t, ev, v, dv, pos, coarse, fit, levels, k, step, tol, coarse_sample=None):
     level_dirs = [np.asarray(coarse, dtype=np.float64)] + [fit["level_dirs"][i] for i in range(levels)]
     off = 0
     prev = None
@@ -44,12 +57,10 @@ def check_fit(api, tab, g, t, ev, v, dv, pos, coarse, fit, levels, k, step, tol,
         peak, arg, _ = api.unfold_envelope_scan(tab, ev, dv, dirs)
         pk = peak[..., 2].double().cpu().numpy()
         tt = arg[..., 2].cpu().numpy()
-        if check_times and lv == 0:
-            e, _, _ = oracle_unfold(g, t, v, dirs)
-            for d in range(len(dirs)):
-                for s in range(len(pos)):
-                    env = np.sqrt(O.envelope(e[d, s, 0]) ** 2 + O.envelope(e[d, s, 1]) ** 2)
-                    assert env[tt[d, s]] >= env.max() * (1 - 2 * tol), (d, s)
+        sel = range(len(dirs))
+        if lv == 0 and coarse_sample is not None:
+            sel = np.random.default_rng(5).choice(len(dirs), coarse_sample, replace=False)
+        check_times_valid(g, t, v, pos, dirs, tt, tol, sel)
         chi2_ref, pw_ref = O.direction_objective(pos, dirs, tt, S.FS_HZ, peaks=pk)
         n = len(dirs)
         got = fit["chi2"][off:off + n]
@@ -59,6 +70,24 @@ def check_fit(api, tab, g, t, ev, v, dv, pos, coarse, fit, levels, k, step, tol,
         prev = dirs[fit["best"][lv]]
         off += n
     assert np.array_equal(fit["result"], prev)
+
+
+def compare_with_oracle_fit(ref, fit, coarse, levels, k):
+    """Level by level against the oracle's own fit (see the module docstring); returns levels compared."""
+    off = 0
+    for lv in range(levels + 1):
+        n = len(coarse) if lv == 0 else k * k
+        if lv > 0:
+            assert np.array_equal(ref["level_dirs"][lv - 1], fit["level_dirs"][lv - 1]), lv
+        rc = ref["chi2"][off:off + n]
+        assert np.allclose(fit["chi2"][off:off + n], rc, rtol=1e-10, atol=1e-9), lv
+        if ref["best"][lv] != fit["best"][lv]:
+            gb = int(fit["best"][lv])
+            assert rc[gb] <= rc.min() * (1 + 1e-9) + 1e-9, (lv, rc[gb], rc.min())
+            return lv
+        off += n
+    assert np.array_equal(ref["result"], fit["result"])
+    return levels + 1
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -88,9 +117,8 @@ def test_direction_fit_matches_oracle(api, prec):
     if prec == "fp64":
         ref = O.direction_fit(g, t, v, pos, coarse, S.FS_HZ, S.BAND_LO_HZ, S.BAND_HI_HZ, levels=levels, k=k,
                               step=step)
-        if np.array_equal(ref["best"], fit["best"]):
-            assert np.array_equal(ref["result"], fit["result"])
-            assert np.allclose(ref["chi2"], fit["chi2"], rtol=1e-10, atol=1e-9)
+        n_same = compare_with_oracle_fit(ref, fit, coarse, levels, k)
+        print("levels matching the oracle's fit pick for pick: %d of %d" % (n_same, levels + 1))
 
 
 def test_direction_fit_full_station_count_and_errors(api):
@@ -107,7 +135,7 @@ def test_direction_fit_full_station_count_and_errors(api):
     nb = api.direction_fit_workspace_bytes(tab, ev, len(coarse), 4, 5)
     work = torch.empty(nb, dtype=torch.uint8, device="cuda")
     fit = api.direction_fit(tab, ev, dv, pos, coarse, levels=4, k=5, step=(90 / 16, 360 / 32), work=work)
-    check_fit(api, tab, g, t, ev, v, dv, pos, coarse, fit, 4, 5, (90 / 16, 360 / 32), TOL_FP64, check_times=False)
+    check_fit(api, tab, g, t, ev, v, dv, pos, coarse, fit, 4, 5, (90 / 16, 360 / 32), TOL_FP64, coarse_sample=12)
     z, a = fit["result"]
     assert abs(z - 52.0) < 1.0 and min(abs(a - 140.0), 360 - abs(a - 140.0)) < 2.0
     fit0 = api.direction_fit(tab, ev, dv, pos, coarse, levels=0, k=5)

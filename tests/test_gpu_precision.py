@@ -1,30 +1,55 @@
-"""FP32 path near singular geometry (the precision form): FP32 with the FP64
-determinant fallback against the FP64 path on the same float32 inputs, over
-the horizon stress directions.
+"""The FP32 precision form (FP32 with the FP64 determinant fallback) against
+the oracle and the FP64 path, on the same float32 traces and complex64 table
+values (promoted exactly for the FP64 sides).
 
-Reading of the error budget: the fallback removes cancellation in the FP32
-determinant, not the rounding of the FP32 inputs, which the inverse
-amplifies by kappa = ||H||_F^2 / |det|; so the 1e-5 bar (relative to the
-station's E-field peak over both components) is asserted for kappa <= 100
-and the error beyond is measured and reported, per station and per
-component."""
+Error model behind the bars (the single-precision estimate of the paper's
+section 3 carried through the solve): the FP32 solve E = H^-1 X turns the
+rounding of its inputs (FFT of the traces, the interpolated H, the 2x2
+inverse) into a field error of order kappa * u * |E| in both components,
+kappa = ||H||_F^2 / |det| (the Frobenius condition number of the 2x2 H) and
+u = 2^-24.  The fallback removes the cancellation of the FP32 determinant,
+not the input rounding.  So:
+  * for kappa <= 100 (every direction the workloads use has kappa <= 30) the
+    1e-5 rule holds (per station, and per component for strong components);
+  * near the horizon (kappa 1e3 .. 1e6) the per-station error is bounded by
+    C_KAPPA * kappa * u, C_KAPPA = 4: a few roundings per input, amplified by
+    kappa (measured well inside it);
+  * where the fallback is forced for every bin (fallback_rel = 1) the results
+    still meet the 1e-5 rule against the oracle, and the fallback counter
+    counts every (direction, in-band bin) pair;
+  * a table scaled by a power of two gives bitwise the same field scaled by
+    the inverse power (every decision is taken on H scaled exactly), and
+    tables of order 1e-12 and 1e12 meet the same bars as order one.
+"""
 import numpy as np
 import pytest
 
+from oracle import oracle as O
 from paper_1507_07733_amd import synth as S
 
-from helpers import station_errors, trace_errors
+from helpers import (TOL_FP32, TOL_FP64, U32, assert_fp32_close, assert_traces_close, fp32_errors, oracle_kappa,
+                     oracle_unfold, station_errors, trace_errors)
 
 pytestmark = pytest.mark.gpu
+
+C_KAPPA = 4.0
 
 
 def say(*a):
     print("[case]", *a, flush=True)
 
 
-def test_horizon_stress_fp32_vs_fp64():
+@pytest.fixture(scope="module")
+def api():
     import torch
-    from paper_1507_07733_amd import api
+    from paper_1507_07733_amd import api as A
+    A.lib()
+    torch.cuda.init()
+    return A
+
+
+def test_horizon_stress_fp32_vs_fp64(api):
+    import torch
     g = S.GRID_FINE
     t32 = S.pattern_table(g, cfg=2).astype(np.complex64)
     tab32 = api.Table(g, t32)
@@ -40,20 +65,18 @@ def test_horizon_stress_fp32_vs_fp64():
     e32 = api.unfold_direction_scan(tab32, ev32, v, dirs, counts=c32).cpu().numpy()
     say("stress fp64")
     e64 = api.unfold_direction_scan(tab64, ev64, v, dirs, counts=c64).cpu().numpy()
-    h = api.pattern_response(tab64, ev64, dirs).cpu().numpy()
-    det = h[:, :, 0, 0] * h[:, :, 1, 1] - h[:, :, 0, 1] * h[:, :, 1, 0]
-    fro2 = np.sum(np.abs(h) ** 2, axis=(-1, -2))
-    with np.errstate(divide="ignore"):
-        kappa = np.max(fro2 / np.abs(det), axis=-1)
-    r = trace_errors(e32, e64)                       # [D][S][2]
-    rs = station_errors(e32, e64)                    # [D][S]
+    kappa = oracle_kappa(g, t32, n, dirs)
+    rs, r, strong = fp32_errors(e32, e64)            # [D][S], [D][S][2]
     nb = api.band_bins(ev32)[1]
     zen = dirs[:, 0]
     for di in range(len(dirs)):
-        print("zen %.5f az %.3f kappa %.3g max r per station %.3e per component %.3e"
-              % (zen[di], dirs[di, 1], kappa[di], rs[di].max(), r[di].max()))
+        print("zen %.5f az %.3f kappa %.3g max r per station %.3e per strong component %.3e per component %.3e"
+              % (zen[di], dirs[di, 1], kappa[di], rs[di].max(), r[di][strong[di]].max() if strong[di].any() else 0,
+                 r[di].max()))
         if kappa[di] <= 100:
-            assert rs[di].max() <= 1e-5
+            assert_fp32_close(e32[di], e64[di], TOL_FP32, "zen %g az %g" % tuple(dirs[di]))
+        elif np.isfinite(kappa[di]):
+            assert rs[di].max() <= C_KAPPA * kappa[di] * U32, (dirs[di], kappa[di], rs[di].max())
         assert np.all(np.isfinite(e32[di]))
     horizon = zen == 90.0
     assert np.all(e32[horizon] == 0) and np.all(e64[horizon] == 0)
@@ -63,3 +86,127 @@ def test_horizon_stress_fp32_vs_fp64():
     # the fallback fires where |det| < 1e-6 ||H||^2 in float: within ~6e-5 deg of the horizon
     near = (kappa > 2e6) & ~horizon
     assert near.any() and fb >= int(horizon.sum()) * nb + 1
+
+
+def test_forced_fallback_matches_oracle(api):
+    """fallback_rel = 1 sends every in-band bin through the FP64 determinant and inverse."""
+    import torch
+    g = S.GRID_FINE
+    t32 = S.pattern_table(g, cfg=2).astype(np.complex64)
+    tab32 = api.Table(g, t32)
+    s, n = 6, 2048
+    v = S.traces(s, n, cfg=5, event=7, dtype=np.float32)
+    dv = torch.from_numpy(v).cuda()
+    zs = np.array([5.0, 17.5, 33.0, 48.25, 61.0, 72.5, 80.0, 87.0])
+    az = np.array([0.0, 41.3, 122.0, 179.5, 233.7, 301.0, 347.2, 359.6])
+    dirs = np.stack([zs, az], axis=1)
+    ev_fb = api.make_event(s, n, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, fallback_rel=1.0)
+    ev = api.make_event(s, n, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32)
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    cnt0 = torch.zeros(2, dtype=torch.int64, device="cuda")
+    say("forced fallback fp32 S 6 N 2048 D 8")
+    out = api.unfold_direction_scan(tab32, ev_fb, dv, dirs, counts=cnt).cpu().numpy()
+    out0 = api.unfold_direction_scan(tab32, ev, dv, dirs, counts=cnt0).cpu().numpy()
+    nb = api.band_bins(ev)[1]
+    assert cnt.cpu().tolist() == [len(dirs) * nb, 0]
+    assert cnt0.cpu().tolist() == [0, 0]
+    ref, sing, _ = oracle_unfold(g, t32, v, dirs)
+    assert not np.any(sing)
+    rs, r = assert_fp32_close(out, ref, TOL_FP32, "forced fallback")
+    rs0, r0 = assert_fp32_close(out0, ref, TOL_FP32, "float inverse")
+    print("forced fallback: per station %.3e, per component %.3e; float inverse: %.3e, %.3e"
+          % (rs.max(), r.max(), rs0.max(), r0.max()))
+    # the double inverse is at least as close as the float one, within rounding of the rest of the path
+    assert rs.max() <= max(rs0.max(), 1e-7) * 2
+
+
+def test_near_horizon_kappa_bound(api):
+    """kappa 1e3 .. 1e6 (0.05 deg .. 6e-5 deg from the horizon): per-station error <= C_KAPPA * kappa * u
+    against the oracle, both without and with the fallback forced."""
+    import torch
+    g = S.GRID_FINE
+    t32 = S.pattern_table(g, cfg=2).astype(np.complex64)
+    tab32 = api.Table(g, t32)
+    s, n = 4, 2048
+    v = S.traces(s, n, cfg=5, event=11, dtype=np.float32)
+    dv = torch.from_numpy(v).cuda()
+    zs = np.array([89.95, 89.99, 89.995, 89.999, 89.9995, 89.9999])
+    dirs = np.stack([zs, np.array([10.0, 95.5, 180.0, 271.25, 359.5, 44.0])], axis=1)
+    kappa = oracle_kappa(g, t32, n, dirs)
+    assert np.all((kappa > 1e3) & (kappa < 2e6)), kappa
+    ref, sing, _ = oracle_unfold(g, t32, v, dirs)
+    assert not np.any(sing)
+    for fb in (1e-6, 1.0):
+        ev = api.make_event(s, n, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, fallback_rel=fb)
+        say("near horizon fp32 fallback_rel", fb)
+        out = api.unfold_direction_scan(tab32, ev, dv, dirs).cpu().numpy()
+        rs = station_errors(out, ref)
+        for di in range(len(dirs)):
+            print("fallback_rel %g zen %.4f kappa %.3g per-station r %.3e bound %.3e"
+                  % (fb, zs[di], kappa[di], rs[di].max(), C_KAPPA * kappa[di] * U32))
+            assert rs[di].max() <= C_KAPPA * kappa[di] * U32, (fb, dirs[di], kappa[di], rs[di].max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_table_scale_invariance(api, prec):
+    """Tables of any units: scaled by 2^+-40 the field is bitwise 2^-+40 times the unscaled one; scaled by
+    1e-12 and 1e12 (not powers of two) the path meets its bar against the oracle on the scaled table."""
+    import torch
+    g = S.GRID_COARSE
+    fp32 = prec == "fp32"
+    base = S.pattern_table(g, cfg=0)
+    if fp32:
+        base = base.astype(np.complex64)
+    s, n = 4, 1024
+    dt = np.float32 if fp32 else np.float64
+    v = S.traces(s, n, cfg=0, event=3, dtype=dt)
+    dv = torch.from_numpy(v).cuda()
+    dirs = np.array([[12.5, 7.0], [40.0, 120.0], [66.0, 358.0], [85.0, 200.0]])
+    ev = api.make_event(s, n, prec=api.AU_PREC_FP32 if fp32 else api.AU_PREC_FP64,
+                        trace_dtype=api.AU_F32 if fp32 else api.AU_F64)
+    say("table scale", prec, "unscaled")
+    e0 = api.unfold_direction_scan(api.Table(g, base), ev, dv, dirs).cpu().numpy()
+    for p2 in (40, -40):
+        tp = (base * (2.0 ** p2)).astype(base.dtype)
+        say("table scale", prec, "2^%d" % p2)
+        cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+        ep = api.unfold_direction_scan(api.Table(g, tp), ev, dv, dirs, counts=cnt).cpu().numpy()
+        assert np.array_equal(ep, (e0 * (2.0 ** -p2)).astype(e0.dtype)), p2
+        assert cnt.cpu().tolist() == [0, 0]
+    for sc in (1e-12, 1e12):
+        ts = (base * sc).astype(base.dtype)
+        say("table scale", prec, "%g" % sc)
+        cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+        es = api.unfold_direction_scan(api.Table(g, ts), ev, dv, dirs, counts=cnt).cpu().numpy()
+        assert cnt.cpu().tolist() == [0, 0]
+        ref, sing, _ = oracle_unfold(g, ts, v, dirs)
+        assert not np.any(sing)
+        if fp32:
+            assert_fp32_close(es, ref, TOL_FP32, "table x %g" % sc)
+        else:
+            assert_traces_close(es, ref, TOL_FP64, "table x %g" % sc)
+
+
+def test_frequency_range_validated(api):
+    """The bin-to-node split needs |k fs - f0 N| < 2^53: a band reaching past it is rejected before any
+    launch; just inside it the path still matches the oracle (bins of 3.9 GHz on a 100 GHz grid)."""
+    import torch
+    g = S.Grid(101, 19, 72, 0, 100_000_000_000, 0.0, 5.0, 0.0, 5.0)
+    t = S.pattern_table(g, cfg=0)
+    tab = api.Table(g, t)
+    fs, lo, hi = 8_000_000_000_000, 2_500_000_000_000, 3_500_000_000_000
+    # N = 4096: k fs reaches 1792 * 8e12 = 1.43e16 > 2^53
+    v4 = torch.zeros((1, 2, 4096), dtype=torch.float64, device="cuda")
+    ev4 = api.make_event(1, 4096, fs_hz=fs, band_lo_hz=lo, band_hi_hz=hi)
+    say("frequency range: rejected case")
+    with pytest.raises(api.AuError):
+        api.unfold_direction_scan(tab, ev4, v4, [[40.0, 120.0]])
+    # N = 2048: 896 * 8e12 = 7.2e15 < 2^53
+    v = S.traces(2, 2048, cfg=0, event=5)
+    ev = api.make_event(2, 2048, fs_hz=fs, band_lo_hz=lo, band_hi_hz=hi)
+    dirs = [[40.0, 120.0], [63.0, 301.5]]
+    say("frequency range: accepted case")
+    out = api.unfold_direction_scan(tab, ev, torch.from_numpy(v).cuda(), dirs).cpu().numpy()
+    ref, _, _ = O.unfold(g, t, v, dirs, fs, lo, hi)
+    assert np.any(ref)
+    assert_traces_close(out, ref, TOL_FP64, "bins near the 2^53 limit")
