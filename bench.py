@@ -64,12 +64,49 @@ def gen_traces(specs, offsets, total, seed_cfg=2):
     return volt
 
 
+def cgroup_cpu_quota():
+    """CPUs granted by the cgroup's CPU quota (None if unlimited or unknown)."""
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, p = f.read().split()[:2]
+        if q != "max":
+            return float(q) / float(p)
+    except (OSError, ValueError):
+        pass
+    try:
+        with open("/sys/fs/cgroup/cpu/cpu.cfs_quota_us") as f:
+            q = float(f.read())
+        with open("/sys/fs/cgroup/cpu/cpu.cfs_period_us") as f:
+            p = float(f.read())
+        if q > 0:
+            return q / p
+    except (OSError, ValueError):
+        pass
+    return None
+
+
 def cpu_threads():
+    """Every host core this process may use: its CPU affinity, bounded by the cgroup's CPU quota
+    (a GPU machine grants each job a share of its cores)."""
     try:
         n = len(os.sched_getaffinity(0))
     except Exception:
         n = os.cpu_count() or 1
-    return max(1, min(16, n))
+    q = cgroup_cpu_quota()
+    if q is not None:
+        n = min(n, max(1, int(q)))
+    return max(1, n)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(grid, table_c64, specs, plan, volt_host, budget_s=12.0):
@@ -122,6 +159,8 @@ def cpu_baseline(grid, table_c64, specs, plan, volt_host, budget_s=12.0):
         i += 1
     wall1 = time.perf_counter() - t1
     return {"value": done / wall, "unit": "station-unfolds/s", "cores": threads, "kind": "oracle",
+            "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cgroup_cpus": cgroup_cpu_quota(),
+            "cpu_model": cpu_model(),
             "sample": "%d random (event, direction, station) units of the batched workload "
                       "(%d at N=2048, %d at N=4096), FP64 on the float32 inputs, %.1f s wall on %d threads"
                       % (done, n_by.get(2048, 0), n_by.get(4096, 0), wall, threads),
@@ -150,6 +189,7 @@ def parity_sample(grid, table_c64, specs, plan, volt_host, efield, n_units=8):
 
 
 KAPPA_EDGES = (1.0, 3.0, 10.0, 30.0, 100.0, 1e3, float("inf"))
+SHARE_EDGES = (0.0, 0.01, 0.1, 1.0 + 1e-12)
 
 
 def fp32_error_report(api, plan, specs, efield, tab64, volt, dev):
@@ -162,6 +202,7 @@ def fp32_error_report(api, plan, specs, efield, tab64, volt, dev):
     import torch
     buckets = {i: [] for i in range(len(KAPPA_EDGES) - 1)}
     sbuckets = {i: [] for i in range(len(KAPPA_EDGES) - 1)}
+    shbuckets = {i: [] for i in range(len(SHARE_EDGES) - 1)}
     worst = worst_s = 0.0
     n_tr = 0
     for e, (s, n, dirs) in enumerate(specs):
@@ -186,6 +227,11 @@ def fp32_error_report(api, plan, specs, efield, tab64, volt, dev):
         for di in range(len(dirs)):
             buckets[int(kb[di])].append(err_d[di])
             sbuckets[int(kb[di])].append(err_sd[di])
+        share = (ref / torch.where(ref_s > 0, ref_s, torch.ones_like(ref_s)).unsqueeze(-1)).reshape(-1)
+        sb = torch.bucketize(share, torch.tensor(SHARE_EDGES[1:-1], dtype=share.dtype, device=share.device))
+        ef, sb = err.reshape(-1).cpu().numpy(), sb.cpu().numpy()
+        for i in range(len(SHARE_EDGES) - 1):
+            shbuckets[i].append(ef[sb == i])
         worst = max(worst, float(err.max()))
         worst_s = max(worst_s, float(err_s.max()))
         n_tr += err.numel()
@@ -199,10 +245,20 @@ def fp32_error_report(api, plan, specs, efield, tab64, volt, dev):
         out.append({"kappa": [KAPPA_EDGES[i], KAPPA_EDGES[i + 1]], "traces": int(a.size),
                     "max": float(a.max()), "p99": float(np.percentile(a, 99)), "median": float(np.median(a)),
                     "max_station": float(b.max())})
-    return {"traces": n_tr, "max": worst, "max_station": worst_s, "by_kappa": out,
+    by_share = []
+    for i, lst in shbuckets.items():
+        a = np.concatenate(lst) if lst else np.zeros(0)
+        if not a.size:
+            continue
+        by_share.append({"share": [SHARE_EDGES[i], SHARE_EDGES[i + 1]], "traces": int(a.size),
+                         "max": float(a.max()), "p99": float(np.percentile(a, 99)), "median": float(np.median(a)),
+                         "over_1e-5": int(np.sum(a > 1e-5))})
+    return {"traces": n_tr, "max": worst, "max_station": worst_s, "by_kappa": out, "by_component_share": by_share,
             "reference": "FP64 direction scan on the same float32 traces (complex128 table)",
             "normalisation": "max/p99/median: per component trace, max|E32-E64| / max|E64| of that component; "
-                             "max_station: per station, over both components, divided by the larger peak"}
+                             "max_station: per station, over both components, divided by the larger peak; "
+                             "by_component_share: per component, bucketed by the component's peak over the "
+                             "station's peak (the FP32 rule: per station, and per component from share 0.1)"}
 
 
 # FP32 vector FMA rate without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
@@ -387,67 +443,142 @@ def large_batch_rate(api, synth, tab32, dev, n_events=10000, n_st=124, n=4096, n
     return res
 
 
-def serving_benchmark(api, synth, tab32, tab64, rate_hz=2000.0, duration_s=3.0, warm_s=0.5,
-                      plain_s=1.5, pool=48):
-    """Open-loop Poisson stream of events (stations U{3..124}, 2048 float32
-    samples, 8x8 directions) served by the continuous-batching server, and the
-    same stream by a plain FP64 per-event loop.  Latency = completion time -
-    scheduled arrival time (no coordinated omission); the first warm_s
-    seconds are discarded."""
-    import threading
+def single_event_latency(api, synth, dev, calls=300, warm=20):
+    """The plain FP64 single-event call (10 stations x 2 channels x 2048 float64 samples, one
+    direction (40, 120) deg, complex128 table 1 MHz / 5 deg): wall time per call including the wait
+    for its completion (the latency a caller sees), and the device time of its launches (HIP events
+    on the call's stream)."""
     import torch
-    r = synth.rng(3, synth.STREAM_EVENTS)
-    sizes = r.integers(3, 125, size=pool)
-    vols = [synth.traces(int(sz), 2048, cfg=3, event=i, dtype=np.float32) for i, sz in enumerate(sizes)]
-    dirs = synth.direction_grid(8, 8)
-    arrivals = synth.poisson_arrivals(rate_hz, duration_s, cfg=3)
+    g = synth.GRID_COARSE
+    tb = api.Table(g, synth.pattern_table(g, cfg=0))
+    v = torch.from_numpy(synth.traces(10, 2048, cfg=0, event=0)).to(dev)
+    ev = api.make_event(10, 2048, prec=api.AU_PREC_FP64, trace_dtype=api.AU_F64)
+    out = torch.empty((10, 2, 2048), dtype=torch.float64, device=dev)
+    work = torch.empty(api.workspace_bytes(tb, ev, 1), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    wall, gpu = [], []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for i in range(warm + calls):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        api.unfold_event(tb, ev, v, 40.0, 120.0, out=out, work=work)
+        e1.record(stream)
+        e1.synchronize()
+        t1 = time.perf_counter()
+        if i >= warm:
+            wall.append((t1 - t0) * 1e6)
+            gpu.append(e0.elapsed_time(e1) * 1e3)
+    wall, gpu = np.array(wall), np.array(gpu)
+    return {"us_per_call_median": float(np.median(wall)), "us_per_call_min": float(wall.min()),
+            "device_us_median": float(np.median(gpu)), "device_us_min": float(gpu.min()), "calls": calls,
+            "workload": "plain FP64 au_unfold_event: 10 stations x 2 x 2048 float64 samples at 200 MHz, one "
+                        "direction (40, 120) deg, complex128 table 1 MHz/5 deg; wall time per call until complete"}
+
+
+def serve_stream(api, sv, vols, dirs, arrivals, warm_s):
+    """Submit each event at its scheduled arrival (open loop: a producer thread spins to the arrival
+    time, so a slow server never delays later arrivals), wait for every result in order, and return
+    latency statistics over the events arriving after warm_s."""
+    import threading
     n_ev = len(arrivals)
-    sv = api.Server(tab32, hbm_budget_bytes=48 << 30, staging_bytes=4 << 30, max_inflight=256,
-                    n_streams=4, max_batch_events=16, tick_s=0.0)
+    pool = len(vols)
     tickets = [None] * n_ev
     t_start = sv.now() + 0.2
     rejected = [0]
+    failure = []
 
     def producer():
-        for i, a in enumerate(arrivals):
-            target = t_start + a
-            while sv.now() < target:
-                pass
-            while True:
-                try:
-                    tickets[i] = sv.submit(vols[i % pool], dirs, t_arrival=target)
-                    break
-                except api.AuError as e:
-                    if e.status != api.AU_EAGAIN:
-                        raise
-                    rejected[0] += 1
-                    time.sleep(1e-4)
+        try:
+            for i, a in enumerate(arrivals):
+                target = t_start + a
+                while sv.now() < target:
+                    pass
+                while True:
+                    try:
+                        tickets[i] = sv.submit(vols[i % pool], dirs, t_arrival=target)
+                        break
+                    except api.AuError as e:
+                        if e.status != api.AU_EAGAIN:
+                            raise
+                        rejected[0] += 1
+                        time.sleep(1e-4)
+        except Exception as e:  # reported by the consumer below
+            failure.append(e)
 
     th = threading.Thread(target=producer)
     th.start()
-    lat, batch, done_t, units = [], [], [], 0
+    lat, batch, done_t, parts, units = [], [], [], [], 0
     for i in range(n_ev):
         while tickets[i] is None:
-            time.sleep(5e-5)
-        res = sv.wait(tickets[i], timeout_s=120, sleep_s=5e-5)
+            if failure:
+                th.join()
+                raise failure[0]
+            time.sleep(2e-5)
+        res = sv.wait(tickets[i], timeout_s=120)
         if arrivals[i] >= warm_s:
             lat.append(res.t_complete - res.t_arrival)
+            parts.append((res.t_submit - res.t_arrival, res.t_admit - res.t_submit, res.t_launch - res.t_admit,
+                          res.t_complete - res.t_launch))
             batch.append(res.batch_events)
             done_t.append(res.t_complete)
             units += res.n_stations * res.n_dirs
         sv.release(tickets[i])
     th.join()
     st = sv.stats()
-    sv.close()
     lat = np.array(lat) * 1e3
+    parts = np.array(parts) * 1e3
     span = max(done_t) - (t_start + warm_s)
-    served = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-              "max_ms": float(lat.max()), "events": len(lat), "offered_events_per_s": rate_hz,
-              "events_per_s": len(lat) / span, "station_unfolds_per_s": units / span,
-              "mean_batch_events": float(np.mean(batch)), "submit_retries": rejected[0],
-              "arena_peak_GB": st["arena_peak"] / 1e9,
-              "workload": "Poisson %.0f events/s for %.1f s (first %.1f s discarded), stations U{3..124}, "
-                          "2048 float32 samples, 8x8 directions, FP32 server, 4 streams" % (rate_hz, duration_s, warm_s)}
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()), "events": len(lat),
+            "events_per_s": len(lat) / span, "station_unfolds_per_s": units / span,
+            "mean_batch_events": float(np.mean(batch)), "max_batch_events": int(np.max(batch)),
+            "submit_retries": rejected[0], "arena_peak_GB": st["arena_peak"] / 1e9,
+            "median_ms": {"arrival_to_submit_return": float(np.median(parts[:, 0] + parts[:, 1])),
+                          "submit_to_admit": float(np.median(parts[:, 1])),
+                          "admit_to_launch": float(np.median(parts[:, 2])),
+                          "launch_to_complete": float(np.median(parts[:, 3]))}}
+
+
+def serving_benchmark(api, synth, tab32, tab64, rate_hz=2000.0, duration_s=3.0, warm_s=0.5,
+                      plain_s=1.5, pool=48, burst_rate_hz=40000.0, burst_s=0.5):
+    """Open-loop Poisson stream of events (stations U{3..124}, 2048 float32
+    samples, 8x8 directions) served by the continuous-batching server, and the
+    same stream by a plain FP64 per-event loop.  Latency = completion time -
+    scheduled arrival time (no coordinated omission); the first warm_s
+    seconds are discarded.  Traces are submitted from pinned host memory, as
+    the plain loop copies them.  A second, saturated load point offers
+    burst_rate_hz (beyond what the device serves) with a 1 ms batching tick,
+    so events are grouped into shared launches."""
+    import torch
+    r = synth.rng(3, synth.STREAM_EVENTS)
+    sizes = r.integers(3, 125, size=pool)
+    vols = [synth.traces(int(sz), 2048, cfg=3, event=i, dtype=np.float32) for i, sz in enumerate(sizes)]
+    vols_pinned = [torch.from_numpy(v).pin_memory() for v in vols]
+    dirs = synth.direction_grid(8, 8)
+    arrivals = synth.poisson_arrivals(rate_hz, duration_s, cfg=3)
+    sv = api.Server(tab32, hbm_budget_bytes=48 << 30, staging_bytes=4 << 30, max_inflight=256,
+                    n_streams=4, max_batch_events=16, tick_s=0.0)
+    try:
+        served = serve_stream(api, sv, vols_pinned, dirs, arrivals, warm_s)
+    finally:
+        sv.close()
+    served.update({"offered_events_per_s": rate_hz, "tick_s": 0.0,
+                   "workload": "Poisson %.0f events/s for %.1f s (first %.1f s discarded), stations U{3..124}, "
+                               "2048 float32 samples, 8x8 directions, FP32 server, 4 streams, traces submitted "
+                               "from pinned host memory" % (rate_hz, duration_s, warm_s)})
+    # saturated point: more offered than served, micro-batches gathered over a 1 ms tick
+    arr_b = np.sort(synth.rng(3, synth.STREAM_ARRIVALS, 1).uniform(0.0, burst_s, int(burst_rate_hz * burst_s)))
+    sv = api.Server(tab32, hbm_budget_bytes=48 << 30, staging_bytes=2 << 30, max_inflight=512,
+                    n_streams=4, max_batch_events=16, tick_s=1e-3)
+    try:
+        sat = serve_stream(api, sv, vols_pinned, dirs, arr_b, 0.1)
+    finally:
+        sv.close()
+    sat.update({"offered_events_per_s": burst_rate_hz, "tick_s": 1e-3,
+                "workload": "uniform arrivals at %.0f events/s for %.1f s (first 0.1 s discarded), same events, "
+                            "max 16 events per batch, 1 ms tick" % (burst_rate_hz, burst_s)})
+    served["saturated"] = sat
 
     # plain FP64 per-event loop on the same arrival stream
     dev = torch.device("cuda:0")
@@ -644,6 +775,10 @@ def main():
         log("fp32 vs fp64 over %d traces: max %.3e per component, %.3e per station; %s"
             % (precision["traces"], precision["max"], precision["max_station"],
             ", ".join("kappa %g-%g: max %.2e" % (b["kappa"][0], b["kappa"][1], b["max"]) for b in precision["by_kappa"])))
+        log("fp32 vs fp64 per component by share of the station peak: %s"
+            % ", ".join("%g-%g: max %.2e (%d of %d over 1e-5)" % (b["share"][0], min(b["share"][1], 1.0), b["max"],
+                                                                 b["over_1e-5"], b["traces"])
+                        for b in precision["by_component_share"]))
         del tab64f
         torch.cuda.empty_cache()
 
@@ -680,6 +815,10 @@ def main():
                 "station_unfolds": su1,
                 "output_GBs": su1 * 2 * n1 * 8 / (ms1 / 1e3) / 1e9}
         log("fp64 plain scan: %.3f ms/call, %.1f M station-unfolds/s" % (ms1, fp64["value"] / 1e6))
+        fp64["single_event"] = single_event_latency(api, synth, dev)
+        log("single event (10 x 2048 FP64, one direction): median %.1f us per call (min %.1f), device %.1f us"
+            % (fp64["single_event"]["us_per_call_median"], fp64["single_event"]["us_per_call_min"],
+               fp64["single_event"]["device_us_median"]))
         del out1
         torch.cuda.empty_cache()
         # envelope-peak timing over the same scan (two inverse FFTs per station-unfold, 6 values out)
@@ -717,9 +856,17 @@ def main():
     if not args.no_serving:
         tab64f = api.Table(grid, synth.pattern_table(grid, cfg=2))
         serving = serving_benchmark(api, synth, tab, tab64f, duration_s=args.serve_seconds)
-        log("serving: p50 %.3f ms p99 %.3f ms at %.0f events/s; plain fp64 loop p50 %.3f p99 %.3f ms"
-            % (serving["p50_ms"], serving["p99_ms"], serving["events_per_s"],
+        log("serving: p50 %.3f ms p99 %.3f ms at %.0f events/s (batch %.2f; median ms submit %.3f, "
+            "admit->launch %.3f, launch->complete %.3f); plain fp64 loop p50 %.3f p99 %.3f ms"
+            % (serving["p50_ms"], serving["p99_ms"], serving["events_per_s"], serving["mean_batch_events"],
+               serving["median_ms"]["arrival_to_submit_return"], serving["median_ms"]["admit_to_launch"],
+               serving["median_ms"]["launch_to_complete"],
                serving["plain_fp64_loop"]["p50_ms"], serving["plain_fp64_loop"]["p99_ms"]))
+        sat = serving["saturated"]
+        log("serving saturated: %.0f of %.0f events/s offered, %.1f M station-unfolds/s, mean batch %.2f (max %d), "
+            "p50 %.3f ms p99 %.3f ms" % (sat["events_per_s"], sat["offered_events_per_s"],
+                                          sat["station_unfolds_per_s"] / 1e6, sat["mean_batch_events"],
+                                          sat["max_batch_events"], sat["p50_ms"], sat["p99_ms"]))
         del tab64f
 
     # ---------------- CPU oracle baseline ---------------------------------

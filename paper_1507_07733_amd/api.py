@@ -76,7 +76,7 @@ class AuResult(C.Structure):
     _fields_ = [("d_efield", C.c_void_p), ("efield_bytes", C.c_uint64), ("n_stations", C.c_int32),
                 ("n_samples", C.c_int32), ("n_dirs", C.c_int32), ("batch_events", C.c_int32),
                 ("t_arrival", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
-                ("t_launch", C.c_double), ("t_complete", C.c_double)]
+                ("t_launch", C.c_double), ("t_complete", C.c_double), ("batch_id", C.c_uint64)]
 
 
 class AuServerStats(C.Structure):
@@ -149,6 +149,8 @@ _SIG = {
     "au_server_now": (C.c_int32, [_VP, C.POINTER(C.c_double)]),
     "au_submit": (C.c_int32, [_VP, C.POINTER(AuRequest), C.POINTER(C.c_uint64)]),
     "au_poll": (C.c_int32, [_VP, C.c_uint64, C.POINTER(AuResult)]),
+    "au_wait": (C.c_int32, [_VP, C.c_uint64, C.c_double, C.POINTER(AuResult)]),
+    "au_server_request_bytes": (C.c_int32, [_VP, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_uint64)]),
     "au_copy_result": (C.c_int32, [_VP, C.c_uint64, _VP, C.c_uint64]),
     "au_release": (C.c_int32, [_VP, C.c_uint64]),
     "au_server_stats": (C.c_int32, [_VP, C.POINTER(AuServerStats)]),
@@ -651,20 +653,36 @@ class Server:
         _check(lib().au_server_now(self.handle, C.byref(t)))
         return t.value
 
-    def submit(self, volt: np.ndarray, dirs, t_arrival: float = 0.0) -> int:
-        """Queue one event (host traces [S][2][N]); returns its ticket.  Raises AuError
-        with status AU_EAGAIN when the staging area is full."""
+    def submit(self, volt, dirs, t_arrival: float = 0.0) -> int:
+        """Queue one event (host traces [S][2][N]: a numpy array, or a CPU torch tensor, e.g. in
+        pinned memory); returns its ticket.  Raises AuError with status AU_EAGAIN when the staging
+        area is full."""
         want = np.float64 if self.trace_dtype == AU_F64 else np.float32
-        v = np.ascontiguousarray(volt, dtype=want)
         d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 2))
-        s, two, n = v.shape
+        if hasattr(volt, "data_ptr"):
+            import torch
+            tw = torch.float64 if self.trace_dtype == AU_F64 else torch.float32
+            if volt.device.type != "cpu" or volt.dtype != tw or not volt.is_contiguous() or volt.dim() != 3:
+                raise ValueError("traces must be a contiguous CPU tensor [S][2][N] of the server's dtype")
+            s, two, n = volt.shape
+            ptr = C.c_void_p(volt.data_ptr())
+        else:
+            v = np.ascontiguousarray(volt, dtype=want)
+            s, two, n = v.shape
+            ptr = v.ctypes.data_as(C.c_void_p)
         if two != 2:
             raise ValueError("traces must have shape [S][2][N]")
-        rq = AuRequest(s, n, len(d), 0, v.ctypes.data_as(C.c_void_p), d.ctypes.data_as(C.POINTER(C.c_double)),
-                       float(t_arrival))
+        rq = AuRequest(s, n, len(d), 0, ptr, d.ctypes.data_as(C.POINTER(C.c_double)), float(t_arrival))
         t = C.c_uint64()
         _check(lib().au_submit(self.handle, C.byref(rq), C.byref(t)))
         return t.value
+
+    def request_bytes(self, n_stations: int, n_samples: int, n_dirs: int) -> int:
+        """Arena bytes one request of these sizes occupies."""
+        b = C.c_uint64()
+        _check(lib().au_server_request_bytes(self.handle, int(n_stations), int(n_samples), int(n_dirs),
+                                             C.byref(b)))
+        return b.value
 
     def poll(self, ticket: int):
         """AuResult when complete, None while pending."""
@@ -675,16 +693,14 @@ class Server:
         _check(rc)
         return r
 
-    def wait(self, ticket: int, timeout_s: float = 60.0, sleep_s: float = 1e-4):
-        import time
-        t_end = time.perf_counter() + timeout_s
-        while True:
-            r = self.poll(ticket)
-            if r is not None:
-                return r
-            if time.perf_counter() > t_end:
-                raise TimeoutError("ticket %d not complete after %.1f s" % (ticket, timeout_s))
-            time.sleep(sleep_s)
+    def wait(self, ticket: int, timeout_s: float = 60.0):
+        """Block until the ticket completes (au_wait); TimeoutError after timeout_s."""
+        r = AuResult()
+        rc = lib().au_wait(self.handle, C.c_uint64(ticket), float(timeout_s), C.byref(r))
+        if rc == AU_EAGAIN:
+            raise TimeoutError("ticket %d not complete after %.1f s" % (ticket, timeout_s))
+        _check(rc)
+        return r
 
     def result(self, ticket: int) -> np.ndarray:
         """Copy a completed result to a host array [D][S][2][N]."""

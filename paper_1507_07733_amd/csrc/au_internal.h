@@ -72,6 +72,17 @@ au_status enqueue_class(const au_table* tb, int prec, int tin, int64_t fs, doubl
                         const double* dirs, hipStream_t st, uint64_t* d_counts,
                         hipEvent_t* stage_events);
 
+// Byte sizes of the three parts of the single-event workspace, in order:
+// in-band spectra, coefficients, directions (each a multiple of 256).
+void workspace_layout(const EvParams& p, int prec, int n_dir, size_t* x_bytes, size_t* m_bytes,
+                      size_t* dir_bytes);
+
+// Enqueue the single-event path (spectrum, coefficient and unfold launches,
+// the event passed by value) on `st`: d_work is laid out as workspace_layout
+// says, its direction part already holding the n_dir directions.
+au_status enqueue_event(const au_table* tb, const au_event* ev, const EvParams& p, const void* d_volt,
+                        int n_dir, void* d_efield, void* d_work, hipStream_t st, uint64_t* d_counts);
+
 // Persistent grid size for the unfold kernel of (prec, N, variant).
 int persistent_blocks(int prec, int n, int variant, int device);
 
