@@ -597,7 +597,7 @@ template <typename T, int E, int TWMODE, bool PAIR, bool PP>
 constexpr int unfold_min_waves()
 {
     if (sizeof(T) == 4 && E == 8 && (PAIR || PP)) return 4;
-    if (sizeof(T) == 8 && E == 8 && TWMODE == TW_HYB && !PAIR && !PP) return 4;
+    if (sizeof(T) == 8 && E == 8 && tw_lds_early(TWMODE) && !PAIR && !PP) return 4;
     return 1;
 }
 
@@ -618,7 +618,7 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
     // early twiddles live in LDS have the registers for it; in FP64 the
     // two-buffer shape, at two waves per SIMD (one workgroup per CU, which
     // its LDS allows anyway)
-    constexpr int PF = (TWMODE == TW_HYB && E <= 8 && !PAIR && !WAVE && (sizeof(T) == 4 || PP)) ? AU_UNFOLD_PF : 0;
+    constexpr int PF = (tw_lds_early(TWMODE) && E <= 8 && !PAIR && !WAVE && (sizeof(T) == 4 || PP)) ? AU_UNFOLD_PF : 0;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sh_u;
     __shared__ int sh_list;
@@ -633,8 +633,8 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
     C2<T>* ltw = reinterpret_cast<C2<T>*>(smem) + G * (PP ? 2 : 1) * lds_elems<N>();
     C2<T> w[tw_count<N, E, RMAX, TWMODE>()];
     load_twiddles<T, N, E, RMAX, TWMODE, +1>(w, tw, t);
-    if constexpr (TWMODE == TW_HYB) fill_lds_twiddles<T, N, E, RMAX, +1>(ltw, tw, threadIdx.x, blockDim.x);
-    if constexpr (PF > 0) {  // (PF > 0 implies TW_HYB: the barrier below orders it)
+    if constexpr (tw_lds_early(TWMODE)) fill_lds_twiddles<T, N, E, RMAX, +1, TWMODE>(ltw, tw, threadIdx.x, blockDim.x);
+    if constexpr (PF > 0) {  // (PF > 0 implies an LDS twiddle table: the barrier below orders it)
         if (threadIdx.x < (PP ? 2 : 1) * G) zero_slot_clear<T, N>(smem, threadIdx.x);
     }
     // Wait for the twiddle loads here, once.  Left to the compiler, the wait
@@ -642,7 +642,7 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
     // completions are counted in issue order: every station would then wait
     // for all stores of the station before it.
     vmem_wait_all();
-    if constexpr (TWMODE == TW_HYB) lds_barrier();
+    if constexpr (tw_lds_early(TWMODE)) lds_barrier();
     // XCD-aware placement (xcd_off != nullptr): the unit array holds 8 lists,
     // list x = [xcd_off[x], xcd_off[x+1]), built so that all units of one
     // event -- which share its spectrum rows, and per direction a coefficient
@@ -1183,8 +1183,9 @@ constexpr UnfoldVariant kUnfoldVariants[] = {
     {8, 8, TW_REG, false, true, false},    {16, 16, TW_REG, false, true, false},
     {8, 8, TW_REG, false, false, true},    {16, 16, TW_REG, false, false, true},
     {8, 8, TW_HYB, false, false, true},    {8, 8, TW_HYB, false, false, false},
+    {8, 8, TW_LF, false, false, true},     {8, 8, TW_LF, false, false, false},
 };
-constexpr int kNumVariants = 14;
+constexpr int kNumVariants = 16;
 
 // LDS one workgroup may allocate on gfx950 (the whole 160 KiB of a CU).
 constexpr int kMaxLdsPerBlock = 163840;
@@ -1222,7 +1223,8 @@ struct UShape {
     static constexpr int G = groups_per_block<T, N, E, BUFS>();
     static constexpr int BLOCK = G * TT;
     static constexpr size_t LDS =
-        ((size_t)G * BUFS * lds_elems<N>() + (TWMODE == TW_HYB ? ltw_count<N, E, RMAX>() : 0)) * sizeof(C2<T>);
+        ((size_t)G * BUFS * lds_elems<N>() + (tw_lds_early(TWMODE) ? ltw_count<N, E, RMAX, TWMODE>() : 0)) *
+        sizeof(C2<T>);
 };
 
 static int ilog2(int n)
@@ -1320,7 +1322,7 @@ static hipError_t launch_unfold_n(int v, hipStream_t st, const EvDesc& ev0, cons
     switch (v) {
 #define V_(VV) \
     case VV: return launch_unfold_nv<T, N, VV>(st, ev0, evs, units, n_units, spw, X, M, efield, tw, counter, persistent_blocks, xcd_off, xcd_max_list);
-        V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11) V_(12) V_(13)
+        V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11) V_(12) V_(13) V_(14) V_(15)
 #undef V_
     }
     return hipErrorInvalidValue;
@@ -1396,6 +1398,8 @@ static int persistent_blocks_for(int n, int v, int device)
             case 11: per_cu = occupancy_nv<T, NN, 11>(); break;                                 \
             case 12: per_cu = occupancy_nv<T, NN, 12>(); break;                                 \
             case 13: per_cu = occupancy_nv<T, NN, 13>(); break;                                 \
+            case 14: per_cu = occupancy_nv<T, NN, 14>(); break;                                 \
+            case 15: per_cu = occupancy_nv<T, NN, 15>(); break;                                 \
         }                                                                                       \
         break;
         AU_FOR_EACH_N(X_)
@@ -1444,19 +1448,35 @@ static au_status ensure_twiddles(int dev)
     if (dev < 0 || dev >= kMaxDev) return fail(AU_EDEVICE, "device index out of range");
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_tw32[dev] != nullptr) return AU_OK;
-    std::vector<C2<float>> h32(kTwN);
-    std::vector<C2<double>> h64(kTwN);
+    // kTwN roots exp(-2 pi i q / kTwN), then the (tangent, cosine) table of
+    // the fused multiply-add butterflies (see lf_tab)
+    constexpr int n_tw = kTwN + 4 * kLfQ;
+    std::vector<C2<float>> h32(n_tw);
+    std::vector<C2<double>> h64(n_tw);
     for (int q = 0; q < kTwN; ++q) {
         long double c, s;
         unit_root(q, kTwN, c, s);
         h64[q] = C2<double>{(double)c, (double)-s};
         h32[q] = C2<float>{(float)c, (float)-s};
     }
+    for (int q = 0; q < kLfQ; ++q) {
+        const int angle[4] = {q, 2 * q, 4 * q, q + kTwN / 8};  // a, 2a, 4a, a + pi/4 in units of 2 pi / kTwN
+        for (int e = 0; e < 4; ++e) {
+            long double c, s;
+            unit_root(angle[e], kTwN, c, s);
+            // +-90 deg: a tiny cosine keeps the tangent finite; its size is far
+            // below each precision's rounding (2^-40 against 2^-24 for float,
+            // 2^-90 against 2^-53 for double) and its tangent far below the range
+            const long double c32 = c == 0.0L ? 0x1p-40L : c, c64 = c == 0.0L ? 0x1p-90L : c;
+            h64[kTwN + 4 * q + e] = C2<double>{(double)(s / c64), (double)c64};
+            h32[kTwN + 4 * q + e] = C2<float>{(float)(s / c32), (float)c32};
+        }
+    }
     void *p32 = nullptr, *p64 = nullptr;
-    HIP_TRY(hipMalloc(&p32, sizeof(C2<float>) * kTwN));
-    HIP_TRY(hipMalloc(&p64, sizeof(C2<double>) * kTwN));
-    HIP_TRY(hipMemcpy(p32, h32.data(), sizeof(C2<float>) * kTwN, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(p64, h64.data(), sizeof(C2<double>) * kTwN, hipMemcpyHostToDevice));
+    HIP_TRY(hipMalloc(&p32, sizeof(C2<float>) * n_tw));
+    HIP_TRY(hipMalloc(&p64, sizeof(C2<double>) * n_tw));
+    HIP_TRY(hipMemcpy(p32, h32.data(), sizeof(C2<float>) * n_tw, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p64, h64.data(), sizeof(C2<double>) * n_tw, hipMemcpyHostToDevice));
     g_tw32[dev] = (C2<float>*)p32;
     g_tw64[dev] = (C2<double>*)p64;
     return AU_OK;

@@ -139,6 +139,78 @@ struct Dft<1, SIGN, T> {
     static __device__ __forceinline__ void run(C2<T>*) {}
 };
 
+// Fused multiply-add butterflies (the tangent form of Linzer and Feig,
+// "Modified FFTs for fused multiply-add architectures", Math. Comp. 60,
+// 1993).  With a twiddle w = c (1 + i t),
+//   a +- rot w b = a +- c rot u,   u = b (1 + i t) = (b.re - t b.im, b.im + t b.re),
+// two FMAs give u and one FMA each output component: 6 operations where a
+// complex multiply and two complex additions take 8.  rot is 1, +i or -i
+// (ROT 0, +1, -1), an exchange of components that costs nothing.  A cosine
+// that is exactly zero (+-90 deg) is stored as 2^-40 (float) or 2^-90
+// (double): c u then differs from the exact product by that fraction of
+// |b.re|, far below the rounding of the result, and t stays finite (the
+// rounding of u, of relative size u (1 + |t|) |b|, shrinks by |c| in c u,
+// so the tangent's size costs no accuracy).
+// Leaves a + rot w b in a and a - rot w b in b.
+template <int ROT, typename T>
+__device__ __forceinline__ void lf_pair(C2<T>& a, C2<T>& b, const C2<T> tc)
+{
+    const T t = tc.re, c = tc.im;
+    const T ur = fma(-t, b.im, b.re);
+    const T ui = fma(t, b.re, b.im);
+    const T pr = ROT == 0 ? ur : (ROT > 0 ? -ui : ui);
+    const T pi = ROT == 0 ? ui : (ROT > 0 ? ur : -ur);
+    const C2<T> hi{fma(c, pr, a.re), fma(c, pi, a.im)};
+    const C2<T> lo{fma(-c, pr, a.re), fma(-c, pi, a.im)};
+    a = hi;
+    b = lo;
+}
+
+// Radix-R butterfly of a Stockham pass with its input twiddles w^r (w =
+// exp(SIGN 2 pi i k / (NS R))) folded in:
+//   v[q] <- sum_r v[r] w^r exp(SIGN 2 pi i r q / R),
+// with L the (tangent, cosine) pairs of w (R = 2); w, w^2 (R = 4); w, w^2,
+// w^4 and w exp(SIGN i pi / 4) (R = 8).  Split r = r1 + (R/2) r2: the first
+// radix-2 stage pairs v[r1] with v[r1 + R/2] through w^(R/2); the sums feed
+// the even outputs as an R/2-point transform twiddled by w, the differences
+// the odd outputs as one twiddled by w exp(SIGN 2 pi i / R); inside the
+// 4-point transforms the factors SIGN i of exp(SIGN 2 pi i / 4) are
+// exchanges of components (ROT).  72 operations for R = 8 against 82 for
+// seven complex multiplies and an 8-point transform.
+template <int R, int SIGN, typename T>
+__device__ __forceinline__ void lf_dft(C2<T>* v, const C2<T>* L)
+{
+    static_assert(R == 2 || R == 4 || R == 8, "fused multiply-add butterflies: radix 2, 4 or 8");
+    if constexpr (R == 2) {
+        lf_pair<0>(v[0], v[1], L[0]);
+    } else if constexpr (R == 4) {
+        lf_pair<0>(v[0], v[2], L[1]);
+        lf_pair<0>(v[1], v[3], L[1]);
+        lf_pair<0>(v[0], v[1], L[0]);
+        lf_pair<SIGN>(v[2], v[3], L[0]);
+        const C2<T> y1 = v[2], y2 = v[1];
+        v[1] = y1;
+        v[2] = y2;
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) lf_pair<0>(v[r], v[r + 4], L[2]);
+        // even outputs: 4-point transform of the sums, twiddle w
+        lf_pair<0>(v[0], v[2], L[1]);
+        lf_pair<0>(v[1], v[3], L[1]);
+        lf_pair<0>(v[0], v[1], L[0]);
+        lf_pair<SIGN>(v[2], v[3], L[0]);
+        // odd outputs: of the differences, twiddle w exp(SIGN i pi / 4), whose
+        // square is (SIGN i) w^2
+        lf_pair<SIGN>(v[4], v[6], L[1]);
+        lf_pair<SIGN>(v[5], v[7], L[1]);
+        lf_pair<0>(v[4], v[5], L[3]);
+        lf_pair<SIGN>(v[6], v[7], L[3]);
+        const C2<T> y[8] = {v[0], v[4], v[2], v[6], v[1], v[5], v[3], v[7]};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = y[q];
+    }
+}
+
 // Twiddle table: tw[q] = exp(-2 pi i q / kTwN), q in [0, kTwN).  Any
 // N-point transform with N | kTwN indexes it with stride kTwN / N.
 constexpr int kTwN = 4096;
@@ -266,7 +338,18 @@ constexpr int lds_zero_slot() { return N + 1; }
 //             table of NS (R-1) entries per pass; the passes with NS >= TT
 //             keep theirs in registers as TW_REG.  Saves the registers of
 //             the early passes for one LDS read per factor.
-enum { TW_TABLE = 0, TW_REG = 1, TW_SPLIT = 2, TW_HYB = 3 };
+//   TW_LF:    TW_HYB's placement (an LDS table for NS < TT, registers for
+//             NS >= TT) for the fused multiply-add butterflies of lf_dft:
+//             per (pass, k) the (tangent, cosine) pairs of the angles the
+//             radix-R butterfly needs (lf_entries) instead of R-1 roots.
+enum { TW_TABLE = 0, TW_REG = 1, TW_SPLIT = 2, TW_HYB = 3, TW_LF = 4 };
+
+// Twiddles of the early passes in a per-workgroup LDS table.
+constexpr bool tw_lds_early(int mode) { return mode == TW_HYB || mode == TW_LF; }
+// (tangent, cosine) pairs per butterfly of a radix-R pass in TW_LF.
+constexpr int lf_entries(int r) { return r == 8 ? 4 : (r == 4 ? 2 : 1); }
+// Twiddle entries per butterfly of a radix-R pass.
+constexpr int tw_per(int mode, int r) { return mode == TW_LF ? lf_entries(r) : r - 1; }
 
 template <int N, int RMAX>
 constexpr int pass_radix(int ns) { return (N / ns < RMAX) ? N / ns : RMAX; }
@@ -278,28 +361,42 @@ constexpr int tw_offset(int ns_target)
     for (int ns = 1; ns < ns_target && ns < N; ns *= pass_radix<N, RMAX>(ns)) {
         if (ns == 1) continue;
         const int r = pass_radix<N, RMAX>(ns);
-        if (TWMODE == TW_HYB && ns < N / E) continue;
-        off += (TWMODE == TW_REG || TWMODE == TW_HYB) ? (E / r) * (r - 1) : (r - 1);
+        if (tw_lds_early(TWMODE) && ns < N / E) continue;
+        off += (TWMODE == TW_REG || tw_lds_early(TWMODE)) ? (E / r) * tw_per(TWMODE, r) : (r - 1);
     }
     return off;
 }
 
-// Offset of pass NS in the TW_HYB LDS table, and the table's length.
-template <int N, int E, int RMAX>
+// Offset of pass NS in the TW_HYB / TW_LF LDS table, and the table's length.
+template <int N, int E, int RMAX, int TWMODE = TW_HYB>
 constexpr int ltw_offset(int ns_target)
 {
     int off = 0;
     for (int ns = 1; ns < ns_target && ns < N; ns *= pass_radix<N, RMAX>(ns)) {
         if (ns == 1) continue;
         if (ns >= N / E) break;
-        off += ns * (pass_radix<N, RMAX>(ns) - 1);
+        off += ns * tw_per(TWMODE, pass_radix<N, RMAX>(ns));
     }
     return off;
 }
-template <int N, int E, int RMAX>
+template <int N, int E, int RMAX, int TWMODE = TW_HYB>
 constexpr int ltw_count()
 {
-    return ltw_offset<N, E, RMAX>(N);
+    return ltw_offset<N, E, RMAX, TWMODE>(N);
+}
+
+// The fused multiply-add twiddle table follows the kTwN roots in the same
+// allocation: entry 4 q + e (q < kTwN / 2) holds (tan a_e, cos a_e) for the
+// angles a_0 = 2 pi q / kTwN, a_1 = 2 a_0, a_2 = 4 a_0, a_3 = a_0 + pi / 4
+// (exp(+i ...) convention; a cosine that is exactly zero is stored as a tiny
+// value of its sign, see lf_pair).  For the exp(-i ...) transform every
+// tangent changes sign.
+constexpr int kLfQ = 2048;
+template <int SIGN, typename T>
+__device__ __forceinline__ C2<T> lf_tab(const C2<T>* __restrict__ tw, int q, int e)
+{
+    const C2<T> v = tw[kTwN + 4 * q + e];
+    return SIGN > 0 ? v : C2<T>{-v.re, v.im};
 }
 
 template <int N, int E, int RMAX, int TWMODE>
@@ -316,8 +413,16 @@ __device__ __forceinline__ void load_twiddles_from(C2<T>* __restrict__ w, const 
         if constexpr (NS > 1) {
             constexpr int TT = N / E, B = E / R, STRIDE = kTwN / (NS * R);
             constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
-            if constexpr (TWMODE == TW_HYB && NS < TT) {
+            if constexpr (tw_lds_early(TWMODE) && NS < TT) {
                 // in the LDS table (fill_lds_twiddles)
+            } else if constexpr (TWMODE == TW_LF) {
+                constexpr int LE = lf_entries(R);
+#pragma unroll
+                for (int m = 0; m < B; ++m) {
+                    const int k = (t + TT * m) & (NS - 1);
+#pragma unroll
+                    for (int e = 0; e < LE; ++e) w[OFF + m * LE + e] = lf_tab<SIGN>(tw, k * STRIDE, e);
+                }
             } else if constexpr (TWMODE == TW_REG || TWMODE == TW_HYB) {
 #pragma unroll
                 for (int m = 0; m < B; ++m) {
@@ -344,7 +449,7 @@ __device__ __forceinline__ void load_twiddles(C2<T>* __restrict__ w, const C2<T>
 
 // The TW_HYB LDS table: entry LOFF(NS) + k (R-1) + r - 1 = exp(SIGN 2 pi i r k / (NS R))
 // for every pass with 1 < NS < TT; filled cooperatively by nthr threads.
-template <typename T, int N, int E, int RMAX, int NS, int SIGN>
+template <typename T, int N, int E, int RMAX, int TWMODE, int NS, int SIGN>
 __device__ __forceinline__ void fill_lds_twiddles_from(C2<T>* __restrict__ ltw, const C2<T>* __restrict__ tw,
                                                        int tid, int nthr)
 {
@@ -352,21 +457,25 @@ __device__ __forceinline__ void fill_lds_twiddles_from(C2<T>* __restrict__ ltw, 
         constexpr int R = pass_radix<N, RMAX>(NS);
         if constexpr (NS > 1) {
             constexpr int STRIDE = kTwN / (NS * R);
-            constexpr int LOFF = ltw_offset<N, E, RMAX>(NS);
-            for (int i = tid; i < NS * (R - 1); i += nthr) {
-                const int k = i / (R - 1), r = i - k * (R - 1) + 1;
-                ltw[LOFF + i] = twiddle_tab<SIGN>(tw, r * k * STRIDE);
+            constexpr int LOFF = ltw_offset<N, E, RMAX, TWMODE>(NS);
+            constexpr int PER = tw_per(TWMODE, R);
+            for (int i = tid; i < NS * PER; i += nthr) {
+                const int k = i / PER, e = i - k * PER;
+                if constexpr (TWMODE == TW_LF)
+                    ltw[LOFF + i] = lf_tab<SIGN>(tw, k * STRIDE, e);
+                else
+                    ltw[LOFF + i] = twiddle_tab<SIGN>(tw, (e + 1) * k * STRIDE);
             }
         }
-        fill_lds_twiddles_from<T, N, E, RMAX, NS * R, SIGN>(ltw, tw, tid, nthr);
+        fill_lds_twiddles_from<T, N, E, RMAX, TWMODE, NS * R, SIGN>(ltw, tw, tid, nthr);
     }
 }
 
-template <typename T, int N, int E, int RMAX, int SIGN>
+template <typename T, int N, int E, int RMAX, int SIGN, int TWMODE = TW_HYB>
 __device__ __forceinline__ void fill_lds_twiddles(C2<T>* __restrict__ ltw, const C2<T>* __restrict__ tw, int tid,
                                                   int nthr)
 {
-    fill_lds_twiddles_from<T, N, E, (RMAX < E ? RMAX : E), 1, SIGN>(ltw, tw, tid, nthr);
+    fill_lds_twiddles_from<T, N, E, (RMAX < E ? RMAX : E), TWMODE, 1, SIGN>(ltw, tw, tid, nthr);
 }
 
 // Buffer-resource access to one range the whole wavefront addresses alike (a
@@ -467,33 +576,43 @@ __device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
         C2<T> v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = x[m + r * B];
-        if constexpr (NS > 1) {
-            constexpr int STRIDE = kTwN / (NS * R);
+        if constexpr (TWMODE == TW_LF && NS > 1) {
+            constexpr int LE = lf_entries(R);
             constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
+            C2<T> L[LE];
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                C2<T> wr;
-                if constexpr (TWMODE == TW_TABLE) {
-                    wr = twiddle_tab<SIGN>(tw, r * k * STRIDE);
-                } else if constexpr (TWMODE == TW_REG || (TWMODE == TW_HYB && NS >= TT)) {
-                    wr = w[OFF + m * (R - 1) + r - 1];
-                } else if constexpr (TWMODE == TW_HYB) {
-                    wr = ltw[ltw_offset<N, E, RMAX>(NS) + k * (R - 1) + r - 1];
-                } else {
-                    wr = w[OFF + r - 1];
-                    if constexpr (NS > TT) {
-                        const int p = (r * ((TT * m) % NS)) % (NS * R);
-                        if (p != 0) {
-                            constexpr int Q = NS * R;
-                            const CxRoot cr = cx_root(SIGN > 0 ? p : Q - p, Q);
-                            wr = cmul(wr, C2<T>{(T)cr.c, (T)cr.s});
+            for (int e = 0; e < LE; ++e)
+                L[e] = NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + k * LE + e] : w[OFF + m * LE + e];
+            lf_dft<R, SIGN>(v, L);
+        } else {
+            if constexpr (NS > 1) {
+                constexpr int STRIDE = kTwN / (NS * R);
+                constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C2<T> wr;
+                    if constexpr (TWMODE == TW_TABLE) {
+                        wr = twiddle_tab<SIGN>(tw, r * k * STRIDE);
+                    } else if constexpr (TWMODE == TW_REG || (TWMODE == TW_HYB && NS >= TT)) {
+                        wr = w[OFF + m * (R - 1) + r - 1];
+                    } else if constexpr (TWMODE == TW_HYB) {
+                        wr = ltw[ltw_offset<N, E, RMAX>(NS) + k * (R - 1) + r - 1];
+                    } else {
+                        wr = w[OFF + r - 1];
+                        if constexpr (NS > TT) {
+                            const int p = (r * ((TT * m) % NS)) % (NS * R);
+                            if (p != 0) {
+                                constexpr int Q = NS * R;
+                                const CxRoot cr = cx_root(SIGN > 0 ? p : Q - p, Q);
+                                wr = cmul(wr, C2<T>{(T)cr.c, (T)cr.s});
+                            }
                         }
                     }
+                    v[r] = cmul(v[r], wr);
                 }
-                v[r] = cmul(v[r], wr);
             }
+            Dft<R, SIGN, T>::run(v);
         }
-        Dft<R, SIGN, T>::run(v);
         if constexpr (LAST) {
 #pragma unroll
             for (int r = 0; r < R; ++r) x[m + r * B] = v[r];
@@ -543,33 +662,43 @@ __device__ __forceinline__ void fft_pass_pp(C2<T> (&x)[E], C2<T>* __restrict__ l
         C2<T> v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = x[m + r * B];
-        if constexpr (NS > 1) {
-            constexpr int STRIDE = kTwN / (NS * R);
+        if constexpr (TWMODE == TW_LF && NS > 1) {
+            constexpr int LE = lf_entries(R);
             constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
+            C2<T> L[LE];
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                C2<T> wr;
-                if constexpr (TWMODE == TW_TABLE) {
-                    wr = twiddle_tab<SIGN>(tw, r * k * STRIDE);
-                } else if constexpr (TWMODE == TW_REG || (TWMODE == TW_HYB && NS >= TT)) {
-                    wr = w[OFF + m * (R - 1) + r - 1];
-                } else if constexpr (TWMODE == TW_HYB) {
-                    wr = ltw[ltw_offset<N, E, RMAX>(NS) + k * (R - 1) + r - 1];
-                } else {
-                    wr = w[OFF + r - 1];
-                    if constexpr (NS > TT) {
-                        const int p = (r * ((TT * m) % NS)) % (NS * R);
-                        if (p != 0) {
-                            constexpr int Q = NS * R;
-                            const CxRoot cr = cx_root(SIGN > 0 ? p : Q - p, Q);
-                            wr = cmul(wr, C2<T>{(T)cr.c, (T)cr.s});
+            for (int e = 0; e < LE; ++e)
+                L[e] = NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + k * LE + e] : w[OFF + m * LE + e];
+            lf_dft<R, SIGN>(v, L);
+        } else {
+            if constexpr (NS > 1) {
+                constexpr int STRIDE = kTwN / (NS * R);
+                constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C2<T> wr;
+                    if constexpr (TWMODE == TW_TABLE) {
+                        wr = twiddle_tab<SIGN>(tw, r * k * STRIDE);
+                    } else if constexpr (TWMODE == TW_REG || (TWMODE == TW_HYB && NS >= TT)) {
+                        wr = w[OFF + m * (R - 1) + r - 1];
+                    } else if constexpr (TWMODE == TW_HYB) {
+                        wr = ltw[ltw_offset<N, E, RMAX>(NS) + k * (R - 1) + r - 1];
+                    } else {
+                        wr = w[OFF + r - 1];
+                        if constexpr (NS > TT) {
+                            const int p = (r * ((TT * m) % NS)) % (NS * R);
+                            if (p != 0) {
+                                constexpr int Q = NS * R;
+                                const CxRoot cr = cx_root(SIGN > 0 ? p : Q - p, Q);
+                                wr = cmul(wr, C2<T>{(T)cr.c, (T)cr.s});
+                            }
                         }
                     }
+                    v[r] = cmul(v[r], wr);
                 }
-                v[r] = cmul(v[r], wr);
             }
+            Dft<R, SIGN, T>::run(v);
         }
-        Dft<R, SIGN, T>::run(v);
         if constexpr (LAST) {
 #pragma unroll
             for (int r = 0; r < R; ++r) x[m + r * B] = v[r];
@@ -612,24 +741,35 @@ __device__ __forceinline__ void fft_pass2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* _
             u[r] = x[m + r * B];
             v[r] = y[m + r * B];
         }
-        if constexpr (NS > 1) {
-            constexpr int STRIDE = kTwN / (NS * R);
+        if constexpr (TWMODE == TW_LF && NS > 1) {
+            constexpr int LE = lf_entries(R);
             constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
+            C2<T> L[LE];
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                C2<T> wr;
-                if constexpr (TWMODE == TW_TABLE)
-                    wr = twiddle_tab<SIGN>(tw, r * k * STRIDE);
-                else if constexpr (TWMODE == TW_HYB && NS < TT)
-                    wr = ltw[ltw_offset<N, E, RMAX>(NS) + k * (R - 1) + r - 1];
-                else
-                    wr = w[OFF + m * (R - 1) + r - 1];
-                u[r] = cmul(u[r], wr);
-                v[r] = cmul(v[r], wr);
+            for (int e = 0; e < LE; ++e)
+                L[e] = NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + k * LE + e] : w[OFF + m * LE + e];
+            lf_dft<R, SIGN>(u, L);
+            lf_dft<R, SIGN>(v, L);
+        } else {
+            if constexpr (NS > 1) {
+                constexpr int STRIDE = kTwN / (NS * R);
+                constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C2<T> wr;
+                    if constexpr (TWMODE == TW_TABLE)
+                        wr = twiddle_tab<SIGN>(tw, r * k * STRIDE);
+                    else if constexpr (TWMODE == TW_HYB && NS < TT)
+                        wr = ltw[ltw_offset<N, E, RMAX>(NS) + k * (R - 1) + r - 1];
+                    else
+                        wr = w[OFF + m * (R - 1) + r - 1];
+                    u[r] = cmul(u[r], wr);
+                    v[r] = cmul(v[r], wr);
+                }
             }
+            Dft<R, SIGN, T>::run(u);
+            Dft<R, SIGN, T>::run(v);
         }
-        Dft<R, SIGN, T>::run(u);
-        Dft<R, SIGN, T>::run(v);
         if constexpr (LAST) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
