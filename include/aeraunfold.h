@@ -169,6 +169,29 @@ au_status au_unfold_direction_scan(const au_table* table, const au_event* ev, co
                                    uint64_t* d_counts);
 
 /*
+ * au_unfold_direction_scan for callers that cannot allocate memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and results (bitwise), with the work space
+ * (the stations' in-band spectra and the directions' coefficients) in a
+ * fixed 32 MiB device array of the library instead of d_work or a pool.
+ * The call allocates nothing and enqueues no host-to-device copy.
+ *   d_dirs:   DEVICE [n_dir][2] (zenith, azimuth) in degrees (caller-owned).
+ *   d_efield: [n_dir][S][2][N] output.
+ * Limit: the spectra, S * n_band * 16 B (FP32) or 32 B (FP64), plus one
+ * direction's coefficients, n_band * 32 B (FP32) or 64 B (FP64), must fit
+ * 32 MiB (at N = 4096 and fs = 200 MHz, 30-80 MHz: up to 2 046 stations
+ * FP32, 1 022 FP64); directions are processed in chunks that fit, so n_dir
+ * is not limited.  Larger events: AU_EINVAL, nothing enqueued.
+ * The array is shared by every call on a device and keeps the last call's
+ * contents (every byte a call reads it has written first): calls on one
+ * device that may overlap (different streams, or threads without ordering)
+ * race and must not be issued; calls on one stream are ordered.
+ */
+au_status au_unfold_direction_scan_noalloc(const au_table* table, const au_event* ev, const void* d_volt,
+                                           int32_t n_dir, const double* d_dirs, void* d_efield, void* stream,
+                                           uint64_t* d_counts);
+
+/*
  * Direction scan reduced to station timing: the E-field trace's Hilbert
  * envelope env = sqrt(e^2 + H(e)^2) (section 4) and its maximum, whose
  * sample is the updated station time (section 2, Fig. 1).  For every

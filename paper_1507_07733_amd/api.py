@@ -148,6 +148,7 @@ _SIG = {
     "au_server_destroy": (C.c_int32, [_VP]),
     "au_server_now": (C.c_int32, [_VP, C.POINTER(C.c_double)]),
     "au_submit": (C.c_int32, [_VP, C.POINTER(AuRequest), C.POINTER(C.c_uint64)]),
+    "au_unfold_direction_scan_noalloc": (C.c_int32, [_VP, C.POINTER(AuEvent), _VP, C.c_int32, _VP, _VP, _VP, _VP]),
     "au_poll": (C.c_int32, [_VP, C.c_uint64, C.POINTER(AuResult)]),
     "au_wait": (C.c_int32, [_VP, C.c_uint64, C.c_double, C.POINTER(AuResult)]),
     "au_server_request_bytes": (C.c_int32, [_VP, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_uint64)]),
@@ -308,6 +309,24 @@ def unfold_direction_scan(table: Table, ev: AuEvent, volt, dirs, out=None, work=
     _check(lib().au_unfold_direction_scan(table.handle, C.byref(ev), _ptr(volt), len(d),
                                           d.ctypes.data_as(C.POINTER(C.c_double)), _ptr(out), wp, wb,
                                           _stream_handle(stream), _ptr(counts)))
+    return out
+
+
+def unfold_direction_scan_noalloc(table: Table, ev: AuEvent, volt, d_dirs, out, counts=None, stream=None):
+    """au_unfold_direction_scan_noalloc: directions d_dirs [D][2] float64 and the output out [D][S][2][N]
+    are device tensors the caller allocated; the call itself allocates nothing."""
+    _check_traces(volt, ev)
+    n_dir = int(d_dirs.shape[0])
+    if d_dirs.dim() != 2 or d_dirs.shape[1] != 2 or not d_dirs.is_contiguous() or not d_dirs.is_cuda:
+        raise ValueError("d_dirs must be a contiguous device tensor [D][2]")
+    import torch
+    if d_dirs.dtype != torch.float64:
+        raise ValueError("d_dirs must be float64")
+    want = (n_dir, ev.n_stations, 2, ev.n_samples)
+    if tuple(out.shape) != want or out.dtype != out_dtype(ev.prec) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous %s tensor of shape %s" % (out_dtype(ev.prec), want))
+    _check(lib().au_unfold_direction_scan_noalloc(table.handle, C.byref(ev), _ptr(volt), n_dir, _ptr(d_dirs),
+                                                  _ptr(out), _stream_handle(stream), _ptr(counts)))
     return out
 
 

@@ -1828,6 +1828,115 @@ extern "C" au_status au_unfold_direction_scan(const au_table* tb, const au_event
                          stream, d_counts);
 }
 
+// ---------------------------------------------------------------------------
+// direction scan without allocation: the spectra and coefficients live in a
+// file-scope device array
+// ---------------------------------------------------------------------------
+
+// Work space of au_unfold_direction_scan_noalloc: the event's in-band spectra
+// and one chunk of directions' coefficients.  Each device holds its own copy
+// from module load until the process ends.  In host code the array's name
+// is a host-side stand-in; its device address comes from
+// hipGetSymbolAddress, taken once per device (scratch_address).
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch[kMaxDev];
+
+static au_status scratch_address(int dev, unsigned char** out)
+{
+    if (dev < 0 || dev >= kMaxDev) return fail(AU_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev] == nullptr) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));  // the current device's copy
+        if (e != hipSuccess || ptr == nullptr)
+            return fail(AU_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch[dev] = (unsigned char*)ptr;
+    }
+    *out = g_scratch[dev];
+    return AU_OK;
+}
+
+// Spectra once, then the directions in chunks whose coefficients fit the
+// rest of the scratch array: per chunk one coefficient and one unfold launch
+// (the same kernels and per-unit arithmetic as the workspace path).
+template <typename T>
+static au_status run_scan_scratch(const au_table* tb, const au_event* ev, const EvParams& p, const void* d_volt,
+                                  int n_dir, const double* d_dirs, void* d_efield, unsigned char* base,
+                                  size_t x_bytes, int chunk, hipStream_t st, uint64_t* d_counts)
+{
+    const int variant = unfold_variant(ev->prec, p.N);
+    XBin<T>* X = (XBin<T>*)base;
+    MBin<T>* M = (MBin<T>*)(base + x_bytes);
+    EvDesc ev0{};
+    ev0.S = p.S;
+    ev0.N = p.N;
+    ev0.k_lo = p.k_lo;
+    ev0.nb = p.nb;
+    const C2<T>* tw = twiddles<T>(tb->device);
+    if (tw == nullptr) return fail(AU_EDEVICE, "twiddle tables missing on this device");
+    hipError_t e;
+    if (ev->trace_dtype == AU_F64)
+        e = launch_spectrum<double, T>(p.N, st, (const double*)d_volt, ev0, nullptr, nullptr, p.S, ev0.nb, X, tw);
+    else
+        e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, ev0.nb, X, tw);
+    if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
+    unsigned long long* cnt = (unsigned long long*)d_counts;
+    const int chunks = (p.S + kStationsPerUnit - 1) / kStationsPerUnit;
+    for (int d0 = 0; d0 < n_dir; d0 += chunk) {
+        const int nd = std::min(chunk, n_dir - d0);
+        ev0.D = nd;
+        if (tb->dtype == AU_F64)
+            launch_coef<double, T>(st, tb, ev0, nullptr, nullptr, nd, d_dirs + 2 * (size_t)d0, 0.0, 0.0, ev->fs_hz,
+                                   ev->fallback_rel, ev->singular_rel, M, cnt);
+        else
+            launch_coef<float, T>(st, tb, ev0, nullptr, nullptr, nd, d_dirs + 2 * (size_t)d0, 0.0, 0.0, ev->fs_hz,
+                                  ev->fallback_rel, ev->singular_rel, M, cnt);
+        e = hipGetLastError();
+        if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_coef: ") + hipGetErrorString(e));
+        const int64_t n_units = (int64_t)nd * chunks;
+        if (n_units > (int64_t)0x7fffffff) return fail(AU_EINVAL, "too many work units");
+        T* out = (T*)d_efield + (size_t)d0 * p.S * 2 * p.N;
+        e = launch_unfold<T>(p.N, variant, st, ev0, nullptr, nullptr, (int)n_units, kStationsPerUnit, X, M, out, tw,
+                             nullptr, 0);
+        if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_unfold: ") + hipGetErrorString(e));
+    }
+    return AU_OK;
+}
+
+extern "C" au_status au_unfold_direction_scan_noalloc(const au_table* tb, const au_event* ev, const void* d_volt,
+                                                      int32_t n_dir, const double* d_dirs, void* d_efield,
+                                                      void* stream, uint64_t* d_counts)
+{
+    EvParams p;
+    au_status s = check_event(tb, ev, &p);
+    if (s != AU_OK) return s;
+    if (!d_volt || !d_efield || !d_dirs) return fail(AU_EINVAL, "null trace, direction or output pointer");
+    if (n_dir < 1) return fail(AU_EINVAL, "n_dir must be >= 1");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != tb->device) return fail(AU_EINVAL, "table lives on another device");
+    const size_t xb = ev->prec == AU_PREC_FP64 ? sizeof(XBin<double>) : sizeof(XBin<float>);
+    const size_t mb = ev->prec == AU_PREC_FP64 ? sizeof(MBin<double>) : sizeof(MBin<float>);
+    const size_t x_bytes = align256((size_t)p.S * p.nb * xb);
+    const size_t m_dir = (size_t)p.nb * mb;  // one direction's coefficients
+    if (x_bytes + m_dir > kScratchBytes)
+        return fail(AU_EINVAL, "event too large for the 32 MiB scratch: n_stations * n_band spectra (" +
+                                   std::to_string(x_bytes) + " B) plus one direction's coefficients (" +
+                                   std::to_string(m_dir) + " B) must fit");
+    const size_t fit = m_dir ? (kScratchBytes - x_bytes) / m_dir : (size_t)n_dir;
+    const int chunk = (int)std::min<size_t>(fit, (size_t)n_dir);
+    unsigned char* base = nullptr;
+    s = scratch_address(dev, &base);
+    if (s != AU_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if (ev->prec == AU_PREC_FP64)
+        return run_scan_scratch<double>(tb, ev, p, d_volt, n_dir, d_dirs, d_efield, base, x_bytes, chunk, st,
+                                        d_counts);
+    return run_scan_scratch<float>(tb, ev, p, d_volt, n_dir, d_dirs, d_efield, base, x_bytes, chunk, st, d_counts);
+}
+
 static au_status pattern_response(const au_table* tb, const au_event* ev, int32_t n_dir, const double* h_dirs,
                                   void* d_resp, void* stream, double wq)
 {
