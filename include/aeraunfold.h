@@ -346,10 +346,21 @@ au_status au_pattern_response_quantized(const au_table* table, const au_event* e
  * one of the 8 XCDs (8 unit lists balanced by work; workgroup b takes units
  * from list b mod 8, then steals) so that the event's spectrum rows and its
  * directions' coefficient rows are fetched into one XCD's L2 only.
+ * With AU_PLAN_FUSED, trace-length classes (FP32, 2048 or 4096 samples,
+ * bands of at most N/4 bins) whose events all have at most 64 directions
+ * run fused (section 4's
+ * dual-domain container: the spectrum of a station is formed once and kept
+ * on chip while every direction is unfolded from it): one kernel per class
+ * takes units of (event, 16 stations, every direction), transforms each
+ * station forward and unfolds all directions from the spectrum it keeps in
+ * registers, so no spectrum rows are written or read (and none allocated);
+ * these classes always use a persistent grid.  Results are bitwise those
+ * of the separate stages.
  */
 #define AU_PLAN_GRAPH 1
 #define AU_PLAN_PERSISTENT 2
 #define AU_PLAN_XCD 4
+#define AU_PLAN_FUSED 8    /* fuse the spectrum into the unfold for classes with few directions */
 typedef struct {
     int32_t n_events;
     int32_t prec;

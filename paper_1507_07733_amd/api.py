@@ -30,6 +30,7 @@ AU_PREC_FP32 = 1
 AU_PLAN_GRAPH = 1
 AU_PLAN_PERSISTENT = 2
 AU_PLAN_XCD = 4
+AU_PLAN_FUSED = 8
 
 FS_HZ = 200_000_000
 BAND_LO_HZ = 30_000_000

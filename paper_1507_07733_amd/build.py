@@ -17,6 +17,9 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libaeraunfold.so")
 SOURCES = ["aeraunfold.hip", "au_server.hip"]
+# the device generator of the synthetic trace stream: a library of its own
+SYNTH_LIB = os.path.join(PKG, "libausynth.so")
+SYNTH_SOURCES = ["au_synth.hip"]
 ARCH = "gfx950"
 
 
@@ -36,11 +39,18 @@ def flags(debug: bool = False):
 
 
 def build(verbose: bool = True, jobs: int = 4) -> str:
+    """Build the unfolding library and the synthetic-stream generator library."""
+    build_lib(LIB, SOURCES, verbose)
+    build_lib(SYNTH_LIB, SYNTH_SOURCES, verbose)
+    return LIB
+
+
+def build_lib(lib_path: str, sources, verbose: bool = True) -> str:
     """Compile every source to an object in parallel, then link the shared library."""
     cc = hipcc()
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = [s for s in sources if os.path.exists(os.path.join(CSRC, s))]
     procs = []
     objs = []
     for s in srcs:
@@ -61,13 +71,13 @@ def build(verbose: bool = True, jobs: int = 4) -> str:
             failed.append(s)
     if failed:
         raise RuntimeError("hipcc failed for " + ", ".join(failed))
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib_path + ".tmp%d" % os.getpid()
     cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

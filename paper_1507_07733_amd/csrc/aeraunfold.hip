@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -224,11 +225,19 @@ __device__ __forceinline__ int invert2(const C2<T> h[4], T inv_n, double singula
 // The packed spectrum of one bin from its packed coefficients: zp = Z[k] and
 // zq = conj Z[N - k] (see MBin); at k = 0 the packed value is (E_theta.re,
 // E_phi.re) = ((zp + zq).re / 2, (zp - zq).im / 2).
+// a0 b0 + a1 b1 as one chain of fused multiply-adds per component.
+template <typename T>
+__device__ __forceinline__ C2<T> cdot2(C2<T> a0, C2<T> b0, C2<T> a1, C2<T> b1)
+{
+    return C2<T>{fma(a0.re, b0.re, fma(-a0.im, b0.im, fma(a1.re, b1.re, -a1.im * b1.im))),
+                 fma(a0.re, b0.im, fma(a0.im, b0.re, fma(a1.re, b1.im, a1.im * b1.re)))};
+}
+
 template <typename T>
 __device__ __forceinline__ void packed_bin(const MBin<T>& m, const XBin<T>& xb, C2<T>& zp, C2<T>& zq)
 {
-    zp = cadd(cmul(m.p0, xb.x0), cmul(m.p1, xb.x1));
-    zq = cadd(cmul(m.q0, xb.x0), cmul(m.q1, xb.x1));
+    zp = cdot2(m.p0, xb.x0, m.p1, xb.x1);
+    zq = cdot2(m.q0, xb.x0, m.q1, xb.x1);
 }
 template <typename T>
 __device__ __forceinline__ C2<T> packed_dc(const C2<T>& zp, const C2<T>& zq)
@@ -300,7 +309,8 @@ constexpr int kSpecStreamBins = 2;
 // current one, so that their latency hides behind the transform.  Nothing in
 // the station loop waits for a load issued after the previous station's
 // stores (vector-memory completions count in issue order): the early passes'
-// twiddles sit in an LDS table and the last pass's in registers, both set
+// twiddles (fused multiply-add form, TW_LF) sit in an LDS table and the last
+// pass's in registers, both set
 // once, and every thread issues a fixed number of spectrum stores, the lanes
 // past the band storing out of range of the row (dropped).
 template <typename Tin, int N>
@@ -317,9 +327,9 @@ __global__ __launch_bounds__(N / 8) void k_spectrum_stream(const Tin* __restrict
     C2<T>* lds = reinterpret_cast<C2<T>*>(smem);
     C2<T>* ltw = lds + lds_elems<N>();
     const int t = threadIdx.x;
-    C2<T> w[tw_count<N, E, RMAX, TW_HYB>()];
-    load_twiddles<T, N, E, RMAX, TW_HYB, -1>(w, tw, t);
-    fill_lds_twiddles<T, N, E, RMAX, -1>(ltw, tw, t, TT);
+    C2<T> w[tw_count<N, E, RMAX, TW_LF>()];
+    load_twiddles<T, N, E, RMAX, TW_LF, -1>(w, tw, t);
+    fill_lds_twiddles<T, N, E, RMAX, -1, TW_LF>(ltw, tw, t, TT);
     vmem_wait_all();
     lds_barrier();
     // the host launches at most n_units workgroups; a station's trace pair,
@@ -368,7 +378,7 @@ __global__ __launch_bounds__(N / 8) void k_spectrum_stream(const Tin* __restrict
                 b[i] = next.v[N + t + TT * i];
             }
         }
-        fft<T, N, E, -1, TW_HYB, RMAX>(x, lds, tw, t, w, ltw);
+        fft<T, N, E, -1, TW_LF, RMAX>(x, lds, tw, t, w, ltw);
 #pragma unroll
         for (int i = 0; i < E; ++i) lds[lpad<T>(t + TT * i)] = x[i];
         lds_barrier();
@@ -883,18 +893,232 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
 // the peak is the root of the largest square).  Optionally the traces are
 // stored too.  A
 // non-null skip flag that reads nonzero turns the launch into a no-op.
+// Two complex floats: one 16-byte record of a coefficient row.
+template <typename T>
+struct alignas(16) C2x2 {
+    C2<T> a, b;
+};
+
+// One float or double at byte offset voff + soff of a buffer range.
+template <typename V>
+__device__ __forceinline__ V buffer_load_scalar(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff)
+{
+    if constexpr (sizeof(V) == 4) {
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
+    } else {
+        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Spectrum and unfold fused, for events with few directions (FP32)
+// ---------------------------------------------------------------------------
+
+// Events with at most this many directions take the fused kernel in batched
+// plans (their work units then cover every direction of a station range).
+constexpr int kFusedMaxDirs = 64;
+// Stations per work unit of the fused kernel.
+constexpr int kFusedStations = 16;
+
+// One work unit (event, stations [s0, s1)) with ALL of the event's directions
+// per workgroup (persistent grid, units taken as in k_unfold).  Per station:
+//   1. its two channel traces (loaded ahead, before the previous station's
+//      last stores) go through the forward transform, computed as
+//      conj(F+(conj z)), z = V_0 + i V_1, with the inverse-direction
+//      twiddles the kernel holds anyway: every operation of that transform
+//      is the conjugate of the one of F-(z), so the spectrum Z = F-(z) and
+//      the in-band split X_0 = (Z[k] + conj Z[N-k]) / 2, X_1 = (Z[k] -
+//      conj Z[N-k]) / 2i are bitwise those of the spectrum kernels;
+//   2. each thread keeps X of its bins k_lo + t + TT q (q < 2) in registers
+//      (the same bins the unfold stages);
+//   3. per direction: the packed coefficients of those bins (loaded ahead,
+//      before the previous direction's stores) times X, staged in LDS, the
+//      inverse transform, and the stores -- the operations of k_unfold.
+// The spectra never reach HBM and each station is transformed forward once.
+// Needs one transform per workgroup (N >= 2048) and bands of at most 2 TT
+// bins (30-80 MHz at 200 MHz is N/4 bins).
+template <typename Tin, int N>
+__global__ __launch_bounds__(N / 8) __attribute__((amdgpu_waves_per_eu(4))) void k_unfold_fused(
+    const Tin* __restrict__ volt, const EvDesc* __restrict__ evs, const int4* __restrict__ units, int n_units,
+    const MBin<float>* __restrict__ M, float* __restrict__ efield, const C2<float>* __restrict__ tw,
+    unsigned int* __restrict__ counter, const int* __restrict__ xcd_off)
+{
+    using T = float;
+    constexpr int E = 8, RMAX = 8, TT = N / E, PF = 2;
+    static_assert(TT >= 256 && PF * TT <= N, "one transform per workgroup");
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int sh_u;
+    __shared__ int sh_list;
+    const int t = threadIdx.x;
+    // la: staging and the inverse transform's second exchange; lb: the other
+    C2<T>* la = reinterpret_cast<C2<T>*>(smem);
+    C2<T>* lb = la + lds_elems<N>();
+    C2<T>* ltw = lb + lds_elems<N>();
+    C2<T> w[tw_count<N, E, RMAX, TW_LF>()];
+    load_twiddles<T, N, E, RMAX, TW_LF, +1>(w, tw, t);
+    fill_lds_twiddles<T, N, E, RMAX, +1, TW_LF>(ltw, tw, t, TT);
+    if (t == 0) zero_slot_clear<T, N>(smem, 0);
+    vmem_wait_all();
+    lds_barrier();
+    if (t == 0) sh_list = blockIdx.x & 7;
+    for (;;) {
+        // the next unit: from this XCD's list, then from the others (as k_unfold)
+        if (t == 0) {
+            int got = n_units;
+            if (xcd_off != nullptr) {
+                for (int k = 0; k < 8; ++k) {
+                    const int x = (sh_list + k) & 7;
+                    const unsigned cnt = (unsigned)(xcd_off[x + 1] - xcd_off[x]);
+                    if (cnt == 0) continue;
+                    const unsigned i = atomicAdd(&counter[x], 1u);
+                    if (i < cnt) {
+                        got = xcd_off[x] + (int)i;
+                        sh_list = x;
+                        break;
+                    }
+                }
+            } else {
+                got = (int)atomicAdd(counter, 1u);
+            }
+            sh_u = got;
+        }
+        lds_barrier();
+        // the unit index is uniform: stated so, the unit and its event are read
+        // by scalar loads
+        const int u = __builtin_amdgcn_readfirstlane(sh_u);
+        lds_barrier();
+        if (u >= n_units) break;
+        const int4 wu = units[u];  // (event, -, first station, end station)
+        const EvDesc ev = evs[wu.x];
+        const int s0 = wu.z, s1 = wu.w, D = ev.D;
+        const unsigned nb = (unsigned)ev.nb, k_lo = (unsigned)ev.k_lo;
+        const MBin<T>* __restrict__ Me = M + ev.m_off;
+        const Tin* __restrict__ Ve = volt + ev.volt_off;
+        // byte offsets of this thread's bins in a coefficient row, clamped to a
+        // valid bin past the band (to the first record of the twiddle table
+        // when the band is empty)
+        unsigned jq[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+            jq[q] = min((unsigned)(t + TT * q), nb > 0 ? nb - 1 : 0u) * (unsigned)sizeof(MBin<T>);
+        // rows and traces as buffer ranges with scalar bases (uniform
+        // direction and station): 32-bit lane offsets, no 64-bit addresses
+        auto load_coef = [&](int d, MBin<T> (&pm)[PF]) {
+            const __amdgpu_buffer_rsrc_t r = nb > 0 ? buffer_range(Me + (int64_t)d * nb, nb * (unsigned)sizeof(MBin<T>))
+                                                    : buffer_range(tw, (unsigned)sizeof(MBin<T>));
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const C2x2<T> lo = buffer_load16<C2x2<T>>(r, jq[q]);
+                const C2x2<T> hi = buffer_load16<C2x2<T>>(r, jq[q] + 16u);
+                pm[q].p0 = lo.a;
+                pm[q].p1 = lo.b;
+                pm[q].q0 = hi.a;
+                pm[q].q1 = hi.b;
+            }
+        };
+        Tin a[E], b[E];
+        const unsigned toff_in = (unsigned)t * (unsigned)sizeof(Tin);
+        auto load_traces = [&](int s) {
+            const __amdgpu_buffer_rsrc_t r = buffer_range(Ve + (int64_t)s * 2 * N, 2 * N * (unsigned)sizeof(Tin));
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                a[i] = buffer_load_scalar<Tin>(r, toff_in, (int)(TT * i * sizeof(Tin)));
+                b[i] = buffer_load_scalar<Tin>(r, toff_in, (int)((N + TT * i) * sizeof(Tin)));
+            }
+        };
+        MBin<T> pm[PF];
+        load_traces(s0);
+        load_coef(0, pm);
+        for (int s = s0; s < s1; ++s) {
+            // 1. forward transform of the station, conj(F+(conj z)), through the
+            // buffers in the inverse transforms' order (lb, la, lb: the same LDS
+            // addresses); lb was gathered last, so every thread first passes a barrier
+            C2<T> x[E];
+#pragma unroll
+            for (int i = 0; i < E; ++i) x[i] = C2<T>{(T)a[i], -(T)b[i]};
+            lds_barrier();
+            fft_pp<T, N, E, +1, TW_LF, RMAX, false>(x, lb, la, tw, t, w, ltw);
+            // 2. the in-band split of this thread's bins, through la (natural
+            // order; gathered last before the transform's final exchange)
+#pragma unroll
+            for (int i = 0; i < E; ++i) la[lpad<T>(t + TT * i)] = x[i];
+            lds_barrier();
+            XBin<T> px[PF];
+#pragma unroll
+            for (int q = 0; q < PF; ++q) {
+                const unsigned j = (unsigned)(t + TT * q);
+                const unsigned k = k_lo + j;
+                const C2<T> ya = la[j < nb ? lpad<T>(k) : lds_pad_slot<N>()];
+                const C2<T> yb = la[(j < nb && k != 0) ? lpad<T>(N - k) : lds_pad_slot<N>()];
+                // Z = conj y: the spectrum kernels' split of (conj ya, conj yb)
+                const C2<T> za{ya.re, -ya.im}, zb{yb.re, -yb.im};
+                px[q].x0 = C2<T>{(T)0.5 * (za.re + zb.re), (T)0.5 * (za.im - zb.im)};
+                px[q].x1 = C2<T>{(T)0.5 * (za.im + zb.im), (T)0.5 * (zb.re - za.re)};
+            }
+            lds_barrier();  // every split read done before the staging writes la
+            // 3. every direction of the event
+            for (int d = 0; d < D; ++d) {
+                // staging into la, as k_unfold (branch-free; lanes with nothing
+                // to write write the pad slot)
+#pragma unroll
+                for (int q = 0; q < PF; ++q) {
+                    const unsigned j = t + TT * q;
+                    const unsigned k = k_lo + j;
+                    const bool ok = j < nb;
+                    C2<T> zp, zq;
+                    packed_bin(pm[q], px[q], zp, zq);
+                    la[ok ? lpad<T>(k) : lds_pad_slot<N>()] = zp;
+                    la[(ok && k != 0) ? lpad<T>(N - k) : lds_pad_slot<N>()] = C2<T>{zq.re, -zq.im};
+                    if (q == 0 && k_lo == 0u && ok && k == 0) la[0] = packed_dc(zp, zq);
+                }
+                __builtin_amdgcn_s_setprio(0);
+                lds_barrier();
+#pragma unroll
+                for (int i = 0; i < E; ++i) {
+                    const unsigned k = t + TT * i;
+                    const unsigned kk = (k <= N / 2) ? k : N - k;
+                    const bool inb = (kk - k_lo) < nb;
+                    x[i] = la[inb ? lpad<T>(k) : lds_zero_slot<N>()];
+                }
+                fft_pp<T, N, E, +1, TW_LF, RMAX, false>(x, lb, la, tw, t, w, ltw);
+                __builtin_amdgcn_s_setprio(2);
+                // loads for what comes next, ahead of the stores: the next
+                // direction's coefficients, or the next station's traces and
+                // its first direction's coefficients
+                if (d + 1 < D) {
+                    load_coef(d + 1, pm);
+                } else if (s + 1 < s1) {
+                    load_traces(s + 1);
+                    load_coef(0, pm);
+                }
+                const __amdgpu_buffer_rsrc_t r =
+                    buffer_range(efield + ev.efield_off + ((int64_t)d * ev.S + s) * 2 * N, 2 * N * (unsigned)sizeof(T));
+                const unsigned toff = (unsigned)t * (unsigned)sizeof(T);
+#pragma unroll
+                for (int i = 0; i < E; ++i) {
+                    buffer_store_nt(x[i].re, r, toff, (int)(TT * i * sizeof(T)));
+                    buffer_store_nt(x[i].im, r, toff, (int)((N + TT * i) * sizeof(T)));
+                }
+            }
+        }
+        __builtin_amdgcn_s_setprio(0);
+    }
+}
+
 // Shape of the envelope kernel.  FP32, and FP64 at 8 values per thread: the
 // two transforms run in lockstep (fft2) through two LDS buffers, with the
-// early passes' twiddles from the LDS table and the rest in registers
-// (TW_HYB) at 8 values per thread.  FP64 at 16 values per thread (N < 1024):
+// early passes' twiddles from the LDS table and the rest in registers, as
+// (tangent, cosine) pairs for the fused multiply-add butterflies (TW_LF) at
+// 8 values per thread.  FP64 at 16 values per thread (N < 1024):
 // the registers do not hold two transforms, so they run one after the other
 // through one buffer with table twiddles.
 template <typename T, int E>
 constexpr bool env_dual() { return sizeof(T) == 4 || E <= 8; }
 template <typename T, int E>
-constexpr int env_twmode() { return env_dual<T, E>() && E <= 8 ? TW_HYB : TW_TABLE; }
+constexpr int env_twmode() { return env_dual<T, E>() && E <= 8 ? TW_LF : TW_TABLE; }
 template <typename T, int N, int E>
-constexpr int env_ltw() { return env_twmode<T, E>() == TW_HYB ? ltw_count<N, E, E>() : 0; }
+constexpr int env_ltw() { return tw_lds_early(env_twmode<T, E>()) ? ltw_count<N, E, E, env_twmode<T, E>()>() : 0; }
 template <typename T, int E>
 constexpr int env_bufs() { return env_dual<T, E>() ? 2 : 1; }
 
@@ -939,8 +1163,8 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
     C2<T>* ltw = reinterpret_cast<C2<T>*>(smem) + G * env_bufs<T, E>() * lds_elems<N>();
     C2<T> w[tw_count<N, E, E, TWM>()];
     load_twiddles<T, N, E, E, TWM, +1>(w, tw, t);
-    if constexpr (TWM == TW_HYB) {
-        fill_lds_twiddles<T, N, E, E, +1>(ltw, tw, threadIdx.x, blockDim.x);
+    if constexpr (tw_lds_early(TWM)) {
+        fill_lds_twiddles<T, N, E, E, +1, TWM>(ltw, tw, threadIdx.x, blockDim.x);
         lds_barrier();
     }
     const unsigned nb = (unsigned)ev.nb, k_lo = (unsigned)ev.k_lo;
@@ -1255,7 +1479,7 @@ template <typename Tin, int N>
 static int spectrum_stream_blocks()
 {
     static const int blocks = [] {
-        constexpr size_t lds = (lds_elems<N>() + ltw_count<N, 8, 8>()) * sizeof(C2<float>);
+        constexpr size_t lds = (lds_elems<N>() + ltw_count<N, 8, 8, TW_LF>()) * sizeof(C2<float>);
         int dev = 0, cus = 0, occ = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -1277,7 +1501,7 @@ static hipError_t launch_spectrum_n(hipStream_t st, const Tin* volt, const EvDes
     if constexpr (sizeof(T) == 4 && N >= 1024) {
         const int blocks = spectrum_stream_blocks<Tin, N>();
         if (max_nb <= kSpecStreamBins * (N / 8) && blocks > 0) {
-            constexpr size_t lds = (lds_elems<N>() + ltw_count<N, 8, 8>()) * sizeof(C2<float>);
+            constexpr size_t lds = (lds_elems<N>() + ltw_count<N, 8, 8, TW_LF>()) * sizeof(C2<float>);
             hipLaunchKernelGGL((k_spectrum_stream<Tin, N>), dim3(std::min(n_units, blocks)), dim3(N / 8), lds,
                                st, volt, ev0, evs, units, n_units, X, tw);
             return hipGetLastError();
@@ -1287,6 +1511,52 @@ static hipError_t launch_spectrum_n(hipStream_t st, const Tin* volt, const EvDes
     hipLaunchKernelGGL((k_spectrum<Tin, T, N, S::E>), dim3(grid), dim3(S::BLOCK), S::LDS, st, volt,
                        ev0, evs, units, n_units, X, tw);
     return hipGetLastError();
+}
+
+// Persistent grid of the fused kernel: as many workgroups as the device holds.
+template <typename Tin, int N>
+static int fused_blocks()
+{
+    static const int blocks = [] {
+        constexpr size_t lds = (2 * lds_elems<N>() + ltw_count<N, 8, 8, TW_LF>()) * sizeof(C2<float>);
+        int dev = 0, cus = 0, occ = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_unfold_fused<Tin, N>, N / 8, lds) != hipSuccess)
+            return 0;
+        return cus * occ;
+    }();
+    return blocks;
+}
+
+// Whether a class of N-sample events with up to max_dirs directions and
+// bands of up to max_nb bins takes the fused kernel.
+static bool fused_eligible(int prec, int n, int max_dirs, int max_nb)
+{
+    return prec == AU_PREC_FP32 && (n == 2048 || n == 4096) && max_dirs <= kFusedMaxDirs && max_nb <= 2 * (n / 8);
+}
+
+template <typename Tin>
+static hipError_t launch_fused(int n, hipStream_t st, const Tin* volt, const EvDesc* evs, const int4* units,
+                               int n_units, const MBin<float>* M, float* efield, const C2<float>* tw,
+                               unsigned int* counter, const int* xcd_off)
+{
+    if (n_units <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counter, 8);
+    switch (n) {
+#define F_(NN)                                                                                                  \
+    case NN: {                                                                                                  \
+        constexpr size_t lds = (2 * lds_elems<NN>() + ltw_count<NN, 8, 8, TW_LF>()) * sizeof(C2<float>);       \
+        const int blocks = fused_blocks<Tin, NN>();                                                             \
+        if (blocks <= 0) return hipErrorInvalidValue;                                                           \
+        hipLaunchKernelGGL((k_unfold_fused<Tin, NN>), dim3(std::min(n_units, blocks)), dim3(NN / 8), lds, st,  \
+                           volt, evs, units, n_units, M, efield, tw, counter, xcd_off);                         \
+        return hipGetLastError();                                                                               \
+    }
+        F_(2048) F_(4096)
+#undef F_
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int N, int V>
@@ -2007,6 +2277,7 @@ struct ClassPlan {
     int* d_xcd_off = nullptr;
     int xcd_max_list = 0;
     int max_nb = 0;  // largest band of the class's events (bins)
+    bool fused = false;  // spectrum and unfold in k_unfold_fused (units: event, station range)
 };
 
 struct au_plan {
@@ -2047,6 +2318,30 @@ static au_status enqueue_class_t(const au_table* tb, int tin, int64_t fs, double
     MBin<T>* M = (MBin<T>*)Mv;
     EvDesc ev0{};
     hipError_t e;
+    if constexpr (sizeof(T) == 4) {
+        if (c.fused) {
+            // no spectrum stage: coefficients, then the fused kernel
+            if (stage_events) HIP_TRY(hipEventRecord(stage_events[0], st));
+            if (tb->dtype == AU_F64)
+                launch_coef<double, T>(st, tb, ev0, c.d_evs, c.d_cunits, c.n_cunits, dirs, 0, 0, fs, fb, sg, M,
+                                       (unsigned long long*)d_counts);
+            else
+                launch_coef<float, T>(st, tb, ev0, c.d_evs, c.d_cunits, c.n_cunits, dirs, 0, 0, fs, fb, sg, M,
+                                      (unsigned long long*)d_counts);
+            e = hipGetLastError();
+            if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_coef: ") + hipGetErrorString(e));
+            if (stage_events) HIP_TRY(hipEventRecord(stage_events[1], st));
+            if (tin == AU_F64)
+                e = launch_fused<double>(c.N, st, (const double*)volt, c.d_evs, c.d_uunits, c.n_uunits, M,
+                                         (float*)efield, tw, c.d_counter, c.d_xcd_off);
+            else
+                e = launch_fused<float>(c.N, st, (const float*)volt, c.d_evs, c.d_uunits, c.n_uunits, M,
+                                        (float*)efield, tw, c.d_counter, c.d_xcd_off);
+            if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_unfold_fused: ") + hipGetErrorString(e));
+            if (stage_events) HIP_TRY(hipEventRecord(stage_events[2], st));
+            return AU_OK;
+        }
+    }
     if (tin == AU_F64)
         e = launch_spectrum<double, T>(c.N, st, (const double*)volt, ev0, c.d_evs, c.d_sunits, c.n_sunits, c.max_nb, X, tw);
     else
@@ -2106,7 +2401,8 @@ static au_status plan_enqueue(au_plan* pl, const void* d_volt, void* d_efield, h
         c.n_cunits = cp.n_cunits;
         c.d_uunits = cp.d_uunits;
         c.n_uunits = cp.n_uunits;
-        c.d_counter = pers ? cp.d_counter : nullptr;
+        c.d_counter = (pers || cp.fused) ? cp.d_counter : nullptr;
+        c.fused = cp.fused;
         c.persistent_blocks = cp.persistent_blocks;
         c.d_xcd_off = cp.d_xcd_off;
         c.xcd_max_list = cp.xcd_max_list;
@@ -2149,7 +2445,8 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
     if (b->n_events < 1 || !b->n_stations || !b->n_samples || !b->n_dirs || !b->h_dirs ||
         !b->volt_offset || !b->efield_offset)
         return fail(AU_EINVAL, "batch arrays missing");
-    if (b->flags & ~(AU_PLAN_GRAPH | AU_PLAN_PERSISTENT | AU_PLAN_XCD)) return fail(AU_EINVAL, "unknown plan flags");
+    if (b->flags & ~(AU_PLAN_GRAPH | AU_PLAN_PERSISTENT | AU_PLAN_XCD | AU_PLAN_FUSED))
+        return fail(AU_EINVAL, "unknown plan flags");
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (dev != tb->device) return fail(AU_EINVAL, "table lives on another device");
@@ -2167,11 +2464,25 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
         if (b->n_dirs[e] < 1) return fail(AU_EINVAL, "event " + std::to_string(e) + ": n_dirs must be >= 1");
         if (b->volt_offset[e] < 0 || b->efield_offset[e] < 0)
             return fail(AU_EINVAL, "negative buffer offset");
+    }
+    // trace-length classes whose events all have few directions take the
+    // fused spectrum + unfold kernel (no spectrum rows in the plan's memory)
+    std::map<int, std::pair<int, int>> cls_max;  // N -> (most directions, widest band)
+    for (int e = 0; e < E; ++e) {
+        auto& m = cls_max[ps[e].N];
+        m.first = std::max(m.first, b->n_dirs[e]);
+        m.second = std::max(m.second, ps[e].nb);
+    }
+    auto class_fused = [&](int n) {
+        const auto& m = cls_max[n];
+        return (b->flags & AU_PLAN_FUSED) && fused_eligible(b->prec, n, m.first, m.second);
+    };
+    for (int e = 0; e < E; ++e) {
         EvDesc& d = descs[e];
         d = EvDesc{};
         d.volt_off = b->volt_offset[e];
         d.efield_off = b->efield_offset[e];
-        d.x_off = x_total;
+        d.x_off = class_fused(ps[e].N) ? 0 : x_total;
         d.m_off = m_total;
         d.dir_off = dir_total;
         d.S = ps[e].S;
@@ -2179,7 +2490,7 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
         d.D = b->n_dirs[e];
         d.k_lo = ps[e].k_lo;
         d.nb = ps[e].nb;
-        x_total += (int64_t)d.S * d.nb;
+        if (!class_fused(ps[e].N)) x_total += (int64_t)d.S * d.nb;
         m_total += (int64_t)d.D * d.nb;
         dir_total += d.D;
         su += (uint64_t)d.S * d.D;
@@ -2192,6 +2503,7 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
     std::sort(ns.begin(), ns.end(), std::greater<int>());
     struct HostClass {
         int N;
+        bool fused = false;
         std::vector<EvDesc> evs;
         std::vector<int2> su, cu;
         std::vector<int4> uu;
@@ -2202,10 +2514,18 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
     for (int n : ns) {
         HostClass c;
         c.N = n;
+        c.fused = class_fused(n);
         for (int e = 0; e < E; ++e) {
             if (descs[e].N != n) continue;
             const int ci = (int)c.evs.size();
             c.evs.push_back(descs[e]);
+            if (c.fused) {
+                // units (event, -, station range) covering every direction
+                for (int d = 0; d < descs[e].D; ++d) c.cu.push_back(int2{ci, d});
+                for (int s0 = 0; s0 < descs[e].S; s0 += kFusedStations)
+                    c.uu.push_back(int4{ci, 0, s0, std::min(descs[e].S, s0 + kFusedStations)});
+                continue;
+            }
             for (int st = 0; st < descs[e].S; ++st) c.su.push_back(int2{ci, st});
             for (int d = 0; d < descs[e].D; ++d) {
                 c.cu.push_back(int2{ci, d});
@@ -2301,6 +2621,7 @@ extern "C" au_status au_plan_create(const au_table* tb, const au_batch* b, au_pl
     for (size_t i = 0; i < hc.size(); ++i) {
         ClassPlan c;
         c.N = hc[i].N;
+        c.fused = hc[i].fused;
         for (const EvDesc& d : hc[i].evs) {
             c.station_unfolds += (uint64_t)d.S * d.D;
             c.max_nb = std::max(c.max_nb, d.nb);
@@ -2438,6 +2759,12 @@ extern "C" au_status au_plan_autotune(au_plan* pl, const void* d_volt, void* d_e
     au_status rc = AU_OK;
     for (size_t i = 0; i < pl->classes.size() && rc == AU_OK; ++i) {
         ClassPlan& cp = pl->classes[i];
+        if (cp.fused) {  // one fixed shape: nothing to tune
+            if (ms)
+                for (int v = 0; v < kNumVariants; ++v) ms[i * kNumVariants + v] = -1.0;
+            if (best) best[i] = -1;
+            continue;
+        }
         double best_ms = 1e300;
         int best_v = cp.variant;
         for (int v = 0; v < kNumVariants && rc == AU_OK; ++v) {

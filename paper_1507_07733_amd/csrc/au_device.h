@@ -460,11 +460,15 @@ __device__ __forceinline__ void fill_lds_twiddles_from(C2<T>* __restrict__ ltw, 
             constexpr int LOFF = ltw_offset<N, E, RMAX, TWMODE>(NS);
             constexpr int PER = tw_per(TWMODE, R);
             for (int i = tid; i < NS * PER; i += nthr) {
-                const int k = i / PER, e = i - k * PER;
-                if constexpr (TWMODE == TW_LF)
+                if constexpr (TWMODE == TW_LF) {
+                    // entry-major (entry e of every k, then e + 1): the lanes of a
+                    // wave, k = t mod NS, then read consecutive elements
+                    const int e = i / NS, k = i - e * NS;
                     ltw[LOFF + i] = lf_tab<SIGN>(tw, k * STRIDE, e);
-                else
+                } else {
+                    const int k = i / PER, e = i - k * PER;
                     ltw[LOFF + i] = twiddle_tab<SIGN>(tw, (e + 1) * k * STRIDE);
+                }
             }
         }
         fill_lds_twiddles_from<T, N, E, RMAX, TWMODE, NS * R, SIGN>(ltw, tw, tid, nthr);
@@ -582,7 +586,7 @@ __device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
             C2<T> L[LE];
 #pragma unroll
             for (int e = 0; e < LE; ++e)
-                L[e] = NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + k * LE + e] : w[OFF + m * LE + e];
+                L[e] = NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k] : w[OFF + m * LE + e];
             lf_dft<R, SIGN>(v, L);
         } else {
             if constexpr (NS > 1) {
@@ -668,7 +672,7 @@ __device__ __forceinline__ void fft_pass_pp(C2<T> (&x)[E], C2<T>* __restrict__ l
             C2<T> L[LE];
 #pragma unroll
             for (int e = 0; e < LE; ++e)
-                L[e] = NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + k * LE + e] : w[OFF + m * LE + e];
+                L[e] = NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k] : w[OFF + m * LE + e];
             lf_dft<R, SIGN>(v, L);
         } else {
             if constexpr (NS > 1) {
@@ -747,7 +751,7 @@ __device__ __forceinline__ void fft_pass2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* _
             C2<T> L[LE];
 #pragma unroll
             for (int e = 0; e < LE; ++e)
-                L[e] = NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + k * LE + e] : w[OFF + m * LE + e];
+                L[e] = NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k] : w[OFF + m * LE + e];
             lf_dft<R, SIGN>(u, L);
             lf_dft<R, SIGN>(v, L);
         } else {

@@ -61,6 +61,8 @@ struct ClassLaunch {
     const int* d_xcd_off = nullptr;     // non-null: 8 per-XCD unit lists (9 boundaries)
     int xcd_max_list = 0;               // longest of the 8 lists
     int max_nb = 1 << 30;               // largest band of the events, in bins (default: unknown)
+    bool fused = false;                 // spectrum + unfold in one kernel (units: event, station range,
+                                        // every direction); needs d_counter
 };
 
 // Enqueue spectrum, coefficient and unfold launches of one class on `st`.

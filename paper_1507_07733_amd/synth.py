@@ -277,3 +277,112 @@ def plane_wave_traces(positions: np.ndarray, n: int, zen_deg: float, az_deg: flo
     amp = r.uniform(amp_range[0], amp_range[1], size=(s, 2))
     v = r.standard_normal((s, 2, n)) * noise_sigma + pulse(n, np.broadcast_to(t0[:, None], (s, 2)), amp)
     return np.ascontiguousarray(v.astype(dtype)), t0
+
+
+# ---------------------------------------------------------------------------
+# Counter-based trace stream for workloads too large to generate on the host
+# (10 000 events x 124 stations x 2 x 4096 float32 samples = 40.6 GB).  The
+# same definition is implemented here (numpy, for the sampled events the
+# oracle checks) and as a device kernel (csrc/au_synth.hip, for the whole
+# stream); every step is integer arithmetic or a single IEEE float32
+# operation, so both give bit-identical traces.
+#
+#   r = Philox4x32-10(counter, key)  (Salmon, Moraes, Dror, Shaw, "Parallel
+#       random numbers: as easy as 1, 2, 3", SC'11): 10 rounds of
+#       (L0, R0, L1, R1) <- (hi(M1 R1) ^ L1... see philox4x32 below), the
+#       key bumped by the Weyl constants between rounds;
+#   key = (seed, 0x7733);
+#   noise[n] = (sum of four 22-bit uniforms of r(counter = (n, 2 s + c, e, 0))
+#              - 2) * f32(sqrt(3))   (Irwin-Hall: mean 0, variance 1, exact sums);
+#   per (e, s): t0 = r(0, s, e, 1)[0] mod N (integer sample), per (e, s, c):
+#   A = 5 + 15 u, u = 24-bit uniform of r(0, 2 s + c, e, 2)[0];
+#   V[e][s][c][n] = noise[n] + A * D[(n - t0) mod N], D the unit-amplitude
+#   in-band pulse (Dirichlet kernel of the 30-80 MHz bins, float32 table).
+# ---------------------------------------------------------------------------
+PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+STREAM_KEY1 = 0x7733
+
+
+def philox4x32(c0, c1, c2, c3, k0, k1):
+    """Philox4x32-10 of uint32 counter words (numpy arrays, broadcast) and a key; returns four uint32 arrays."""
+    c0, c1, c2, c3 = (np.asarray(x, dtype=np.uint64) & 0xFFFFFFFF for x in (c0, c1, c2, c3))
+    k0 = np.uint64(k0 & 0xFFFFFFFF)
+    k1 = np.uint64(k1 & 0xFFFFFFFF)
+    m0, m1 = np.uint64(PHILOX_M[0]), np.uint64(PHILOX_M[1])
+    mask = np.uint64(0xFFFFFFFF)
+    for rnd in range(10):
+        if rnd:
+            k0 = (k0 + np.uint64(PHILOX_W[0])) & mask
+            k1 = (k1 + np.uint64(PHILOX_W[1])) & mask
+        p0 = m0 * c0
+        p1 = m1 * c2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
+        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
+        c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+    return tuple(x.astype(np.uint32) for x in (c0, c1, c2, c3))
+
+
+def dirichlet_table(n: int) -> np.ndarray:
+    """Unit-amplitude in-band pulse D[m] = (1/|K|) sum_{k in K} cos(2 pi k m / n), float32."""
+    return pulse(n, np.zeros(()), np.ones(()))[...].astype(np.float32)
+
+
+def stream_traces(events, n_st: int, n: int, seed: int = 7733, stations=None) -> np.ndarray:
+    """Traces [len(events)][S][2][N] float32 of the counter-based stream (see above); with ``stations``
+    (a list of station indices) only those, [len(events)][len(stations)][2][N]."""
+    ev = np.asarray(events, dtype=np.int64).reshape(-1)
+    st = list(range(n_st)) if stations is None else [int(x) for x in stations]
+    d = dirichlet_table(n)
+    sqrt3 = np.float32(np.sqrt(3.0))
+    out = np.empty((len(ev), len(st), 2, n), dtype=np.float32)
+    smp = np.arange(n, dtype=np.uint64)
+    for i, e in enumerate(ev):
+        for si, s in enumerate(st):
+            t0 = int(philox4x32(0, s, e, 1, seed, STREAM_KEY1)[0]) & (n - 1)
+            for c in range(2):
+                r = philox4x32(smp, 2 * s + c, e, 0, seed, STREAM_KEY1)
+                u = [(x >> np.uint32(10)).astype(np.float32) * np.float32(2.0 ** -22) for x in r]
+                noise = (((u[0] + u[1]) + (u[2] + u[3])) - np.float32(2.0)) * sqrt3
+                ua = np.float32(int(philox4x32(0, 2 * s + c, e, 2, seed, STREAM_KEY1)[0]) >> 8) * np.float32(2.0 ** -24)
+                a = np.float32(np.float32(5.0) + np.float32(np.float32(15.0) * ua))
+                idx = (np.arange(n) - t0) & (n - 1)
+                out[i, si, c] = noise + a * d[idx]
+    return out
+
+
+_synth_lib = None
+
+
+def synth_lib():
+    """The device generator library (built beside the unfolding library)."""
+    global _synth_lib
+    if _synth_lib is None:
+        import ctypes as C
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libausynth.so")
+        if not os.path.exists(path):
+            raise RuntimeError("libausynth.so is not built; run __graft_entry__.build()")
+        lib = C.CDLL(path)
+        lib.ausynth_traces.restype = C.c_int32
+        lib.ausynth_traces.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint32,
+                                       C.c_void_p, C.c_void_p]
+        _synth_lib = lib
+    return _synth_lib
+
+
+def device_stream_traces(out, event0: int, n_events: int, n_st: int, n: int, seed: int = 7733, stream=None):
+    """Fill the device tensor out [n_events][S][2][N] float32 with events event0 .. event0 + n_events - 1 of
+    the counter-based stream (the same values as stream_traces)."""
+    import ctypes as C
+    import torch
+    assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+    assert out.numel() == n_events * n_st * 2 * n
+    d = torch.from_numpy(dirichlet_table(n)).to(out.device)
+    st = torch.cuda.current_stream() if stream is None else stream
+    rc = synth_lib().ausynth_traces(C.c_void_p(out.data_ptr()), int(n_events), int(event0), int(n_st), int(n),
+                                    int(seed) & 0xFFFFFFFF, C.c_void_p(d.data_ptr()), C.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise RuntimeError("ausynth_traces failed with %d" % rc)
+    torch.cuda.current_stream().synchronize() if stream is None else st.synchronize()
+    return out

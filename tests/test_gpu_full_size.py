@@ -5,11 +5,12 @@ benchmark times, on sampled outputs the oracle computes one by one:
   - the batched FP32 plan: 256 events, stations U{3..124}, N in {2048, 4096},
     16 x 16 directions, complex64 table at 0.5 MHz / 1 deg, persistent +
     XCD-aware + hipGraph (105 GB of output);
-  - the large batch: 10 000 events x 124 stations x 4096 float32 samples x
-    4 x 4 directions through the same plan form.  Its 650 GB of output exceed
-    HBM, so 9 900 events recycle one output ring (and 100 distinct input
-    events are shared round-robin); 100 events keep their own output slots
-    and are the ones sampled.
+  - the large batch: 10 000 distinct events x 124 stations x 4096 float32
+    samples (generated on the device by the counter-based stream, checked
+    bitwise against its host definition) x 4 x 4 directions through the same
+    plan form.  Its 650 GB of output exceed HBM, so 9 900 events recycle one
+    output ring; 100 events keep their own output slots and are the ones
+    sampled.
 FP64: per-trace r <= 1e-12; FP32: per station E-field trace r <= 1e-5 (both
 components, the larger peak) and per component where a component carries at
 least 10 % of the station's peak."""
@@ -101,30 +102,54 @@ def test_batched_fp32_plan_full_size(api):
     torch.cuda.empty_cache()
 
 
+def test_device_stream_matches_host_stream(api):
+    """The device generator of the large batch's input stream gives bit-identical traces to the numpy
+    definition (events far apart, first and last stations, a short and the full trace length)."""
+    import torch
+    for n_st, n, ev0, k in ((3, 256, 0, 2), (124, 4096, 9998, 2)):
+        say("device stream: events %d..%d, %d stations, N %d" % (ev0, ev0 + k - 1, n_st, n))
+        dv = torch.empty(k * n_st * 2 * n, dtype=torch.float32, device="cuda")
+        S.device_stream_traces(dv, ev0, k, n_st, n)
+        got = dv.view(k, n_st, 2, n).cpu().numpy()
+        st = [0, n_st - 1] if n_st > 2 else None
+        ref = S.stream_traces(range(ev0, ev0 + k), n_st, n, stations=st)
+        sel = got if st is None else got[:, st]
+        assert np.array_equal(sel, ref)
+        assert abs(float(got.std()) - 1.6) < 0.6            # unit noise plus the pulse
+
+
 def test_large_batch_fp32_ring(api):
+    """10 000 distinct events (40.6 GB of input generated on the device); the first 100 own their output
+    slots and are sampled against the oracle, which takes the same traces regenerated on the host."""
     import torch
     g = S.GRID_FINE
-    t32 = S.pattern_table(g, cfg=4).astype(np.complex64)
+    t32 = S.pattern_table(g, cfg=2).astype(np.complex64)
     tab = api.Table(g, t32)
-    s, n, n_ev, n_inputs, n_kept, ring = 124, 4096, 10000, 100, 100, 100
+    s, n, n_ev, n_kept, ring = 124, 4096, 10000, 100, 100
     dirs = S.direction_grid(4, 4)
     specs = [(s, n, dirs)] * n_ev
     vsz = s * 2 * n
     esz = len(dirs) * s * 2 * n
-    volt_off = (np.arange(n_ev) % n_inputs).astype(np.int64) * vsz
+    volt_off = np.arange(n_ev, dtype=np.int64) * vsz
     # the first n_kept events own their output slots; the rest recycle a ring after them
     eff = np.where(np.arange(n_ev) < n_kept, np.arange(n_ev), n_kept + (np.arange(n_ev) % ring)).astype(np.int64)
     plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=7, volt_offsets=volt_off,
                     efield_offsets=eff * esz)
     assert plan.station_unfolds == n_ev * s * len(dirs)
-    volt = np.empty(n_inputs * vsz, dtype=np.float32)
-    for i in range(n_inputs):
-        volt[i * vsz:(i + 1) * vsz] = S.traces(s, n, cfg=4, event=i, dtype=np.float32).ravel()
-    say("full size: large batch 10000 x 124 x 4096 x 16 directions (ring of %d)" % ring)
-    dv = torch.from_numpy(volt).cuda()
+    say("full size: large batch 10000 distinct events x 124 x 4096 x 16 directions (ring of %d)" % ring)
+    dv = torch.empty(n_ev * vsz, dtype=torch.float32, device="cuda")
+    for e0 in range(0, n_ev, 500):
+        S.device_stream_traces(dv[e0 * vsz:(e0 + 500) * vsz], e0, 500, s, n)
     out = torch.empty(plan.efield_elems, dtype=torch.float32, device="cuda")
     plan.run(dv, out)
     torch.cuda.synchronize()
-    _batched_check(api, g, t32, specs, plan, volt, out, [0, 37, 99], 8, seed=23)
+    r = np.random.default_rng(23)
+    for e in (0, 37, 99):
+        units = np.stack([r.integers(0, len(dirs), 6), r.integers(0, s, 6)], 1)
+        got = np.stack([plan.event_output(out, e)[d, st].cpu().numpy() for d, st in units])
+        v = S.stream_traces([e], s, n, stations=units[:, 1])[0]          # [6][2][N]: one station per unit
+        ref, _, _ = O.unfold(g, t32.astype(np.complex128), v.astype(np.float64), dirs, S.FS_HZ, S.BAND_LO_HZ,
+                             S.BAND_HI_HZ, units=np.stack([units[:, 0], np.arange(6)], 1))
+        check_fp32_units(got, ref)
     del out, dv
     torch.cuda.empty_cache()

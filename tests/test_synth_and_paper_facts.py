@@ -72,3 +72,35 @@ def test_event_mix_shapes():
     assert s.min() >= 3 and s.max() <= 124
     assert set(n.tolist()) <= {2048, 4096}
     assert 0.35 < np.mean(n == 2048) < 0.65
+
+
+def test_counter_stream_properties():
+    """The counter-based trace stream: deterministic, independent of which stations are asked for, noise of
+    unit variance (Irwin-Hall sums), distinct events and channels, and the pulse where the stream puts it."""
+    from paper_1507_07733_amd import synth as S
+    a = S.stream_traces([3, 1000], 4, 1024)
+    b = S.stream_traces([3, 1000], 4, 1024)
+    assert a.dtype == np.float32 and a.shape == (2, 4, 2, 1024) and np.array_equal(a, b)
+    sub = S.stream_traces([1000], 4, 1024, stations=[2, 0])[0]
+    assert np.array_equal(sub[0], a[1, 2]) and np.array_equal(sub[1], a[1, 0])
+    assert not np.array_equal(a[0], a[1]) and not np.array_equal(a[0, 0, 0], a[0, 0, 1])
+    # 32-bit words of Philox are close to uniform: mean of 2^32-scaled words ~ 1/2
+    r = S.philox4x32(np.arange(20000, dtype=np.uint64), 1, 2, 3, 7733, 0x7733)
+    u = np.concatenate(r).astype(np.float64) / 2.0 ** 32
+    assert abs(u.mean() - 0.5) < 0.005 and abs(u.var() - 1.0 / 12) < 0.002
+    # noise alone (the pulse table zeroed) has mean 0 and variance 1
+    d = S.dirichlet_table(1024)
+    assert d[0] == np.float32(1.0) and abs(float(np.sum(d))) < 1e-3
+    big = S.stream_traces(range(8), 8, 1024)
+    resid = big.astype(np.float64)
+    e_amp = []
+    for e in range(8):
+        for s in range(8):
+            t0 = int(S.philox4x32(0, s, e, 1, 7733, 0x7733)[0]) & 1023
+            for c in range(2):
+                ua = np.float32(int(S.philox4x32(0, 2 * s + c, e, 2, 7733, 0x7733)[0]) >> 8) * np.float32(2.0 ** -24)
+                amp = np.float32(np.float32(5.0) + np.float32(np.float32(15.0) * ua))
+                e_amp.append(amp)
+                resid[e, s, c] -= amp * np.roll(d, t0)
+    assert min(e_amp) >= 5.0 and max(e_amp) < 20.0
+    assert abs(resid.mean()) < 0.02 and abs(resid.var() - 1.0) < 0.03
