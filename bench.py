@@ -421,8 +421,8 @@ def large_batch_rate(api, synth, tab32, grid, table_c64, dev, n_events=10000, n_
     volt_off = np.arange(n_events, dtype=np.int64) * vsz
     idx = np.arange(n_events)
     eff = np.where(idx < kept, idx, kept + (idx % ring)).astype(np.int64) * esz
-    plan = api.Plan(tab32, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=7, volt_offsets=volt_off,
-                    efield_offsets=eff)
+    plan = api.Plan(tab32, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=7 | api.AU_PLAN_FUSED,
+                    volt_offsets=volt_off, efield_offsets=eff)
     t0 = time.perf_counter()
     dv = torch.empty(n_events * vsz, dtype=torch.float32, device=dev)
     chunk = 500
@@ -441,6 +441,20 @@ def large_batch_rate(api, synth, tab32, grid, table_c64, dev, n_events=10000, n_
     torch.cuda.synchronize()
     ms = e0_.elapsed_time(e1_) / steps
     su = plan.station_unfolds
+    # the same workload with separate spectrum and unfold stages, for comparison
+    plan_sep = api.Plan(tab32, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=7, volt_offsets=volt_off,
+                        efield_offsets=eff)
+    plan_sep.run(dv, out)
+    torch.cuda.synchronize()
+    e0_.record()
+    for _ in range(steps):
+        plan_sep.run(dv, out)
+    e1_.record()
+    torch.cuda.synchronize()
+    ms_sep = e0_.elapsed_time(e1_) / steps
+    del plan_sep
+    plan.run(dv, out)                    # the kept slots hold the fused plan's output again
+    torch.cuda.synchronize()
     # 1 % sample against the oracle (the kept events' own slots hold their last run's output)
     r = np.random.default_rng(41)
     t128 = np.asarray(table_c64).astype(np.complex128)
@@ -462,13 +476,14 @@ def large_batch_rate(api, synth, tab32, grid, table_c64, dev, n_events=10000, n_
     res = {"value": su / (ms / 1e3), "unit": "station-unfolds/s", "ms_per_step": ms, "station_unfolds": su,
            "output_GBs": su * 2 * n * 4 / (ms / 1e3) / 1e9,
            "input_GB": n_events * vsz * 4 / 1e9, "generation_s": gen_s,
+           "separate_stages_ms_per_step": ms_sep,
            "fp32_error_vs_oracle": {"units": n_units, "events": kept, "max_station": worst_s,
                                     "max_strong_component": worst_c,
                                     "sample": "%d random (direction, station) units of each of the %d events that "
                                               "own their output slots (1 %% of the events)" % (sample_units, kept)},
            "workload": "%d distinct events x %d stations x %d float32 samples (generated on the device) x 16 "
-                       "directions, complex64 table, hipGraph; outputs of %d events kept, the rest recycled "
-                       "through a %d-event ring" % (n_events, n_st, n, kept, ring)}
+                       "directions, complex64 table, hipGraph, fused spectrum + unfold; outputs of %d events "
+                       "kept, the rest recycled through a %d-event ring" % (n_events, n_st, n, kept, ring)}
     del out, dv, plan
     torch.cuda.empty_cache()
     return res
@@ -879,9 +894,11 @@ def main():
     large = None
     if not args.no_large_batch:
         large = large_batch_rate(api, synth, tab, grid, table, dev)
-        log("large batch: %.3f ms/step, %.1f M station-unfolds/s, %.0f GB/s out (%.1f GB of distinct inputs "
-            "generated in %.1f s); FP32 vs oracle on %d units: %.2e per station, %.2e per strong component"
-            % (large["ms_per_step"], large["value"] / 1e6, large["output_GBs"], large["input_GB"],
+        log("large batch: %.3f ms/step (separate stages %.3f), %.1f M station-unfolds/s, %.0f GB/s out (%.1f GB of "
+            "distinct inputs generated in %.1f s); FP32 vs oracle on %d units: %.2e per station, %.2e per strong "
+            "component"
+            % (large["ms_per_step"], large["separate_stages_ms_per_step"], large["value"] / 1e6, large["output_GBs"],
+               large["input_GB"],
                large["generation_s"], large["fp32_error_vs_oracle"]["units"],
                large["fp32_error_vs_oracle"]["max_station"], large["fp32_error_vs_oracle"]["max_strong_component"]))
 

@@ -354,8 +354,10 @@ au_status au_pattern_response_quantized(const au_table* table, const au_event* e
  * takes units of (event, 16 stations, every direction), transforms each
  * station forward and unfolds all directions from the spectrum it keeps in
  * registers, so no spectrum rows are written or read (and none allocated);
- * these classes always use a persistent grid.  Results are bitwise those
- * of the separate stages.
+ * these classes always use a persistent grid.  The operations are those of
+ * the separate stages; the results agree with them to rounding (the
+ * compiler contracts some products into fused multiply-adds differently in
+ * the two kernels).
  */
 #define AU_PLAN_GRAPH 1
 #define AU_PLAN_PERSISTENT 2

@@ -328,8 +328,8 @@ __global__ __launch_bounds__(N / 8) void k_spectrum_stream(const Tin* __restrict
     C2<T>* ltw = lds + lds_elems<N>();
     const int t = threadIdx.x;
     C2<T> w[tw_count<N, E, RMAX, TW_LF>()];
-    load_twiddles<T, N, E, RMAX, TW_LF, -1>(w, tw, t);
-    fill_lds_twiddles<T, N, E, RMAX, -1, TW_LF>(ltw, tw, t, TT);
+    load_twiddles<T, N, E, RMAX, TW_LF, +1>(w, tw, t);  // TW_LF entries serve both directions
+    fill_lds_twiddles<T, N, E, RMAX, +1, TW_LF>(ltw, tw, t, TT);
     vmem_wait_all();
     lds_barrier();
     // the host launches at most n_units workgroups; a station's trace pair,
@@ -923,13 +923,13 @@ constexpr int kFusedStations = 16;
 
 // One work unit (event, stations [s0, s1)) with ALL of the event's directions
 // per workgroup (persistent grid, units taken as in k_unfold).  Per station:
-//   1. its two channel traces (loaded ahead, before the previous station's
-//      last stores) go through the forward transform, computed as
-//      conj(F+(conj z)), z = V_0 + i V_1, with the inverse-direction
-//      twiddles the kernel holds anyway: every operation of that transform
-//      is the conjugate of the one of F-(z), so the spectrum Z = F-(z) and
-//      the in-band split X_0 = (Z[k] + conj Z[N-k]) / 2, X_1 = (Z[k] -
-//      conj Z[N-k]) / 2i are bitwise those of the spectrum kernels;
+//   1. its two channel traces (loaded ahead, after the previous station's
+//      last staging and before its last stores) go through the forward
+//      transform Z = F-(z), z = V_0 + i V_1, with the twiddles the inverse
+//      transforms use (TW_LF entries serve both directions), and the
+//      in-band split X_0 = (Z[k] + conj Z[N-k]) / 2, X_1 = (Z[k] -
+//      conj Z[N-k]) / 2i: the operations of the streaming spectrum kernel
+//      (up to the compiler's choice of which products it fuses into FMAs);
 //   2. each thread keeps X of its bins k_lo + t + TT q (q < 2) in registers
 //      (the same bins the unfold stages);
 //   3. per direction: the packed coefficients of those bins (loaded ahead,
@@ -1029,16 +1029,18 @@ __global__ __launch_bounds__(N / 8) __attribute__((amdgpu_waves_per_eu(4))) void
         };
         MBin<T> pm[PF];
         load_traces(s0);
-        load_coef(0, pm);
         for (int s = s0; s < s1; ++s) {
             // 1. forward transform of the station, conj(F+(conj z)), through the
             // buffers in the inverse transforms' order (lb, la, lb: the same LDS
             // addresses); lb was gathered last, so every thread first passes a barrier
             C2<T> x[E];
 #pragma unroll
-            for (int i = 0; i < E; ++i) x[i] = C2<T>{(T)a[i], -(T)b[i]};
+            for (int i = 0; i < E; ++i) x[i] = C2<T>{(T)a[i], (T)b[i]};
             lds_barrier();
-            fft_pp<T, N, E, +1, TW_LF, RMAX, false>(x, lb, la, tw, t, w, ltw);
+            fft_pp<T, N, E, -1, TW_LF, RMAX, false>(x, lb, la, tw, t, w, ltw);
+            // the first direction's coefficients (issued after the previous
+            // station's last stores, a transform and the split ago)
+            load_coef(0, pm);
             // 2. the in-band split of this thread's bins, through la (natural
             // order; gathered last before the transform's final exchange)
 #pragma unroll
@@ -1049,16 +1051,16 @@ __global__ __launch_bounds__(N / 8) __attribute__((amdgpu_waves_per_eu(4))) void
             for (int q = 0; q < PF; ++q) {
                 const unsigned j = (unsigned)(t + TT * q);
                 const unsigned k = k_lo + j;
-                const C2<T> ya = la[j < nb ? lpad<T>(k) : lds_pad_slot<N>()];
-                const C2<T> yb = la[(j < nb && k != 0) ? lpad<T>(N - k) : lds_pad_slot<N>()];
-                // Z = conj y: the spectrum kernels' split of (conj ya, conj yb)
-                const C2<T> za{ya.re, -ya.im}, zb{yb.re, -yb.im};
+                const C2<T> za = la[j < nb ? lpad<T>(k) : lds_pad_slot<N>()];
+                const C2<T> zb = la[(j < nb && k != 0) ? lpad<T>(N - k) : lds_pad_slot<N>()];
                 px[q].x0 = C2<T>{(T)0.5 * (za.re + zb.re), (T)0.5 * (za.im - zb.im)};
                 px[q].x1 = C2<T>{(T)0.5 * (za.im + zb.im), (T)0.5 * (zb.re - za.re)};
             }
             lds_barrier();  // every split read done before the staging writes la
-            // 3. every direction of the event
-            for (int d = 0; d < D; ++d) {
+            // 3. every direction of the event; the last one is peeled off, so
+            // that the next station's traces, loaded only there, are not held
+            // in registers across the others
+            auto direction = [&](int d, bool last) {
                 // staging into la, as k_unfold (branch-free; lanes with nothing
                 // to write write the pad slot)
 #pragma unroll
@@ -1073,6 +1075,9 @@ __global__ __launch_bounds__(N / 8) __attribute__((amdgpu_waves_per_eu(4))) void
                     if (q == 0 && k_lo == 0u && ok && k == 0) la[0] = packed_dc(zp, zq);
                 }
                 __builtin_amdgcn_s_setprio(0);
+                // the last direction: the next station's traces (this station's
+                // X and coefficients are dead now), ahead of the stores
+                if (last && s + 1 < s1) load_traces(s + 1);
                 lds_barrier();
 #pragma unroll
                 for (int i = 0; i < E; ++i) {
@@ -1083,15 +1088,8 @@ __global__ __launch_bounds__(N / 8) __attribute__((amdgpu_waves_per_eu(4))) void
                 }
                 fft_pp<T, N, E, +1, TW_LF, RMAX, false>(x, lb, la, tw, t, w, ltw);
                 __builtin_amdgcn_s_setprio(2);
-                // loads for what comes next, ahead of the stores: the next
-                // direction's coefficients, or the next station's traces and
-                // its first direction's coefficients
-                if (d + 1 < D) {
-                    load_coef(d + 1, pm);
-                } else if (s + 1 < s1) {
-                    load_traces(s + 1);
-                    load_coef(0, pm);
-                }
+                // the next direction's coefficients, ahead of the stores
+                if (!last) load_coef(d + 1, pm);
                 const __amdgpu_buffer_rsrc_t r =
                     buffer_range(efield + ev.efield_off + ((int64_t)d * ev.S + s) * 2 * N, 2 * N * (unsigned)sizeof(T));
                 const unsigned toff = (unsigned)t * (unsigned)sizeof(T);
@@ -1100,7 +1098,9 @@ __global__ __launch_bounds__(N / 8) __attribute__((amdgpu_waves_per_eu(4))) void
                     buffer_store_nt(x[i].re, r, toff, (int)(TT * i * sizeof(T)));
                     buffer_store_nt(x[i].im, r, toff, (int)((N + TT * i) * sizeof(T)));
                 }
-            }
+            };
+            for (int d = 0; d + 1 < D; ++d) direction(d, false);
+            direction(D - 1, true);
         }
         __builtin_amdgcn_s_setprio(0);
     }

@@ -398,6 +398,14 @@ __device__ __forceinline__ C2<T> lf_tab(const C2<T>* __restrict__ tw, int q, int
     const C2<T> v = tw[kTwN + 4 * q + e];
     return SIGN > 0 ? v : C2<T>{-v.re, v.im};
 }
+// TW_LF registers and LDS tables hold the exp(+i ...) entries for either
+// direction; a transform in the other direction takes them with the tangent
+// negated (folded into the butterflies' FMAs), so one set serves both.
+template <int SIGN, typename T>
+__device__ __forceinline__ C2<T> lf_sign(const C2<T> v)
+{
+    return SIGN > 0 ? v : C2<T>{-v.re, v.im};
+}
 
 template <int N, int E, int RMAX, int TWMODE>
 constexpr int tw_count()
@@ -421,7 +429,7 @@ __device__ __forceinline__ void load_twiddles_from(C2<T>* __restrict__ w, const 
                 for (int m = 0; m < B; ++m) {
                     const int k = (t + TT * m) & (NS - 1);
 #pragma unroll
-                    for (int e = 0; e < LE; ++e) w[OFF + m * LE + e] = lf_tab<SIGN>(tw, k * STRIDE, e);
+                    for (int e = 0; e < LE; ++e) w[OFF + m * LE + e] = lf_tab<+1>(tw, k * STRIDE, e);
                 }
             } else if constexpr (TWMODE == TW_REG || TWMODE == TW_HYB) {
 #pragma unroll
@@ -464,7 +472,7 @@ __device__ __forceinline__ void fill_lds_twiddles_from(C2<T>* __restrict__ ltw, 
                     // entry-major (entry e of every k, then e + 1): the lanes of a
                     // wave, k = t mod NS, then read consecutive elements
                     const int e = i / NS, k = i - e * NS;
-                    ltw[LOFF + i] = lf_tab<SIGN>(tw, k * STRIDE, e);
+                    ltw[LOFF + i] = lf_tab<+1>(tw, k * STRIDE, e);
                 } else {
                     const int k = i / PER, e = i - k * PER;
                     ltw[LOFF + i] = twiddle_tab<SIGN>(tw, (e + 1) * k * STRIDE);
@@ -586,7 +594,8 @@ __device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
             C2<T> L[LE];
 #pragma unroll
             for (int e = 0; e < LE; ++e)
-                L[e] = NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k] : w[OFF + m * LE + e];
+                L[e] = lf_sign<SIGN>(NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k]
+                                             : w[OFF + m * LE + e]);
             lf_dft<R, SIGN>(v, L);
         } else {
             if constexpr (NS > 1) {
@@ -672,7 +681,8 @@ __device__ __forceinline__ void fft_pass_pp(C2<T> (&x)[E], C2<T>* __restrict__ l
             C2<T> L[LE];
 #pragma unroll
             for (int e = 0; e < LE; ++e)
-                L[e] = NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k] : w[OFF + m * LE + e];
+                L[e] = lf_sign<SIGN>(NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k]
+                                             : w[OFF + m * LE + e]);
             lf_dft<R, SIGN>(v, L);
         } else {
             if constexpr (NS > 1) {
@@ -751,7 +761,8 @@ __device__ __forceinline__ void fft_pass2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* _
             C2<T> L[LE];
 #pragma unroll
             for (int e = 0; e < LE; ++e)
-                L[e] = NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k] : w[OFF + m * LE + e];
+                L[e] = lf_sign<SIGN>(NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k]
+                                             : w[OFF + m * LE + e]);
             lf_dft<R, SIGN>(u, L);
             lf_dft<R, SIGN>(v, L);
         } else {

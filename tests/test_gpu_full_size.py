@@ -8,7 +8,7 @@ benchmark times, on sampled outputs the oracle computes one by one:
   - the large batch: 10 000 distinct events x 124 stations x 4096 float32
     samples (generated on the device by the counter-based stream, checked
     bitwise against its host definition) x 4 x 4 directions through the same
-    plan form.  Its 650 GB of output exceed HBM, so 9 900 events recycle one
+    plan form with the fused spectrum + unfold kernel.  Its 650 GB of output exceed HBM, so 9 900 events recycle one
     output ring; 100 events keep their own output slots and are the ones
     sampled.
 FP64: per-trace r <= 1e-12; FP32: per station E-field trace r <= 1e-5 (both
@@ -133,8 +133,8 @@ def test_large_batch_fp32_ring(api):
     volt_off = np.arange(n_ev, dtype=np.int64) * vsz
     # the first n_kept events own their output slots; the rest recycle a ring after them
     eff = np.where(np.arange(n_ev) < n_kept, np.arange(n_ev), n_kept + (np.arange(n_ev) % ring)).astype(np.int64)
-    plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=7, volt_offsets=volt_off,
-                    efield_offsets=eff * esz)
+    plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=7 | api.AU_PLAN_FUSED,
+                    volt_offsets=volt_off, efield_offsets=eff * esz)
     assert plan.station_unfolds == n_ev * s * len(dirs)
     say("full size: large batch 10000 distinct events x 124 x 4096 x 16 directions (ring of %d)" % ring)
     dv = torch.empty(n_ev * vsz, dtype=torch.float32, device="cuda")

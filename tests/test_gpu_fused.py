@@ -1,0 +1,106 @@
+"""Batched plans with the fused spectrum + unfold kernel (AU_PLAN_FUSED,
+FP32 classes of 2048 / 4096 samples whose events all have at most 64
+directions): equal to the same plan with separate spectrum and unfold
+stages up to rounding (the same operations: the forward transform and
+split of the streaming spectrum kernel, the staging and inverse transform of
+k_unfold; the compiler contracts some products into fused multiply-adds
+differently in the two kernels, which moves a spectrum value by an ulp), so
+per station within 1e-6 of the peak; the same fallback and singular counts;
+and within the FP32 rule of the oracle.  Every plan flag combination, float
+and double input traces, one direction, 64 directions, one station, station
+ranges that end inside a work unit, and a class that stays unfused (more
+than 64 directions) next to a fused one."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1507_07733_amd import synth as S
+
+from helpers import TOL_FP32, assert_fp32_close, station_errors
+
+pytestmark = pytest.mark.gpu
+
+GF = S.GRID_FINE
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    from paper_1507_07733_amd import api as A
+    A.lib()
+    torch.cuda.init()
+    return A
+
+
+@pytest.fixture(scope="module")
+def fine32(api):
+    t = S.pattern_table(GF, cfg=2).astype(np.complex64)
+    return t, api.Table(GF, t)
+
+
+def run_plan(api, tab, specs, flags, tin, seed):
+    import torch
+    dt = np.float64 if tin == api.AU_F64 else np.float32
+    plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=tin, flags=flags)
+    volt = np.zeros(plan.volt_elems, dtype=dt)
+    vs = []
+    for e, (s, n, _) in enumerate(specs):
+        v = S.traces(s, n, cfg=2, event=seed + e, dtype=dt)
+        vs.append(v)
+        volt[plan.volt_offsets[e]:plan.volt_offsets[e] + v.size] = v.ravel()
+    dv = torch.from_numpy(volt).cuda()
+    out = torch.full((plan.efield_elems,), float("nan"), dtype=torch.float32, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    plan.run(dv, out, cnt)
+    plan.run(dv, out, cnt)                       # a second run (graph replay when captured)
+    torch.cuda.synchronize()
+    return plan, vs, out, cnt
+
+
+SPECS = [(3, 2048, S.direction_grid(2, 3)), (17, 4096, S.direction_grid(1, 4)), (1, 2048, [[45.0, 45.0]]),
+         (40, 4096, S.direction_grid(8, 8)), (16, 2048, S.direction_grid(2, 2)), (33, 4096, [[10.0, 300.0]])]
+
+
+@pytest.mark.parametrize("flags", [0, 2, 3, 4, 7])
+@pytest.mark.parametrize("tin", ["f32", "f64"])
+def test_fused_plan_equals_separate_stages(api, fine32, flags, tin):
+    t, tab = fine32
+    tcode = api.AU_F32 if tin == "f32" else api.AU_F64
+    say("fused plan, flags", flags, "traces", tin)
+    p0, vs, out0, c0 = run_plan(api, tab, SPECS, flags, tcode, 60)
+    p1, _, out1, c1 = run_plan(api, tab, SPECS, flags | api.AU_PLAN_FUSED, tcode, 60)
+    assert p1.station_unfolds == p0.station_unfolds == sum(s * len(d) for s, _, d in SPECS)
+    assert not np.any(np.isnan(out1.cpu().numpy()))
+    for e in range(len(SPECS)):
+        assert station_errors(p1.event_output(out1, e).cpu().numpy(),
+                              p0.event_output(out0, e).cpu().numpy()).max() <= 1e-6, e
+    assert c0.cpu().tolist() == c1.cpu().tolist()
+    r = np.random.default_rng(flags + 10 * len(tin))
+    for e, (s, n, d) in enumerate(SPECS):
+        units = np.stack([r.integers(0, len(d), 3), r.integers(0, s, 3)], 1)
+        eo = p1.event_output(out1, e)
+        got = np.stack([eo[di, si].cpu().numpy() for di, si in units])
+        ref, _, _ = O.unfold(GF, t.astype(np.complex128), vs[e].astype(np.float64), np.asarray(d, dtype=np.float64),
+                             S.FS_HZ, S.BAND_LO_HZ, S.BAND_HI_HZ, units=units)
+        assert_fp32_close(got, ref, TOL_FP32, "fused event %d" % e)
+
+
+def test_fused_class_beside_an_unfused_one(api, fine32):
+    """2048 samples with 4 x 4 directions (fused) and 4096 samples with one event of 9 x 9 = 81 directions
+    (more than 64: the whole 4096 class stays on the separate stages)."""
+    t, tab = fine32
+    specs = [(12, 2048, S.direction_grid(4, 4)), (5, 4096, S.direction_grid(9, 9)), (7, 4096, [[20.0, 20.0]])]
+    say("fused 2048 class beside an unfused 4096 class")
+    p0, vs, out0, _ = run_plan(api, tab, specs, 7, api.AU_F32, 90)
+    p1, _, out1, _ = run_plan(api, tab, specs, 7 | api.AU_PLAN_FUSED, api.AU_F32, 90)
+    assert station_errors(p1.event_output(out1, 0).cpu().numpy(), p0.event_output(out0, 0).cpu().numpy()).max() <= 1e-6
+    for e in (1, 2):                           # the unfused class: the same kernels, bitwise
+        assert np.array_equal(p1.event_output(out1, e).cpu().numpy(), p0.event_output(out0, e).cpu().numpy())
+    ref, _, _ = O.unfold(GF, t.astype(np.complex128), vs[0].astype(np.float64), S.direction_grid(4, 4), S.FS_HZ,
+                         S.BAND_LO_HZ, S.BAND_HI_HZ, units=[[0, 0], [15, 11]])
+    eo = p1.event_output(out1, 0)
+    assert_fp32_close(np.stack([eo[0, 0].cpu().numpy(), eo[15, 11].cpu().numpy()]), ref, TOL_FP32, "fused 2048")
