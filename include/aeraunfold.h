@@ -503,11 +503,14 @@ au_status au_server_stats(au_server* server, au_server_counters* stats);
 /*
  * Kernel shapes and autotuning (the batched form picks its FFT radix
  * schedule per trace length and precision by measurement).  The unfold
- * kernel is built in au_unfold_variant_count() shapes, described by four
- * arrays (each may be NULL): e_values = values per thread (0: one wavefront
- * per transform, N/64 values per lane), rmax = largest radix per pass,
- * twmode = where the inverse FFT's twiddles live (0 table, 1 registers,
- * 2 registers times compile-time constants), wave = 1 if a single wavefront
+ * kernel is built in au_unfold_variant_count() shapes, described by six
+ * arrays of *count entries (each may be NULL; count is at most 32):
+ * e_values = values per thread (0: one wavefront per transform, N/64 values
+ * per lane), rmax = largest radix per pass, twmode = where the inverse FFT's
+ * twiddles live (0 table, 1 registers, 2 registers times compile-time
+ * constants, 3 an LDS table for the early passes and registers for the
+ * rest, 4 as 3 with (tangent, cosine) pairs for fused multiply-add
+ * butterflies), wave = 1 if a single wavefront
  * owns each transform (no workgroup barriers), pair = 1 if lanes L and L^32
  * hold mirror bins k and N-k so each in-band bin is solved once and its
  * mirror taken with a cross-lane swap, pp = 1 if each transform alternates

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <cmath>
 #include <cstdio>
@@ -540,7 +541,8 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
 //      coalesced writes.
 // With `counter` non-null the grid is persistent and blocks take units from
 // the atomic counter until the list is exhausted (every block leaves through
-// the same check); the per-thread twiddles are loaded once per block.
+// the same check); without, block b takes units b, b + grid, ...  Either way
+// the per-thread twiddles are loaded once per block.
 // Lane -> FFT thread index.  With PAIR, every wavefront plays FFT threads t
 // (lanes 0-31) and TT - t (lanes 32-63, the partner of lane L is lane L ^ 32),
 // so the mirror bin N - k of any bin k a lane holds lives in the partner
@@ -628,7 +630,7 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
     // early twiddles live in LDS have the registers for it; in FP64 the
     // two-buffer shape, at two waves per SIMD (one workgroup per CU, which
     // its LDS allows anyway)
-    constexpr int PF = (tw_lds_early(TWMODE) && E <= 8 && !PAIR && !WAVE && (sizeof(T) == 4 || PP)) ? AU_UNFOLD_PF : 0;
+    constexpr int PF = ((tw_lds_early(TWMODE) || TWMODE == TW_LFR) && E <= 8 && !PAIR && !WAVE && (sizeof(T) == 4 || PP)) ? AU_UNFOLD_PF : 0;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sh_u;
     __shared__ int sh_list;
@@ -644,7 +646,7 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
     C2<T> w[tw_count<N, E, RMAX, TWMODE>()];
     load_twiddles<T, N, E, RMAX, TWMODE, +1>(w, tw, t);
     if constexpr (tw_lds_early(TWMODE)) fill_lds_twiddles<T, N, E, RMAX, +1, TWMODE>(ltw, tw, threadIdx.x, blockDim.x);
-    if constexpr (PF > 0) {  // (PF > 0 implies an LDS twiddle table: the barrier below orders it)
+    if constexpr (PF > 0) {  // (ordered by the barrier below)
         if (threadIdx.x < (PP ? 2 : 1) * G) zero_slot_clear<T, N>(smem, threadIdx.x);
     }
     // Wait for the twiddle loads here, once.  Left to the compiler, the wait
@@ -652,7 +654,7 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
     // completions are counted in issue order: every station would then wait
     // for all stores of the station before it.
     vmem_wait_all();
-    if constexpr (tw_lds_early(TWMODE)) lds_barrier();
+    if constexpr (tw_lds_early(TWMODE) || PF > 0) lds_barrier();
     // XCD-aware placement (xcd_off != nullptr): the unit array holds 8 lists,
     // list x = [xcd_off[x], xcd_off[x+1]), built so that all units of one
     // event -- which share its spectrum rows, and per direction a coefficient
@@ -687,11 +689,15 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
             u = sh_u;
             lds_barrier();
         } else {
-            if (iter > 0) break;
-            u = blockIdx.x;
+            // without a counter, block b takes units b, b + grid, ... (of list
+            // b mod 8 with XCD lists, the grid then a multiple of 8)
             if (xcd_off != nullptr) {
-                const int x = blockIdx.x & 7, i = blockIdx.x >> 3;
-                u = (i < xcd_off[x + 1] - xcd_off[x]) ? xcd_off[x] + i : n_units;
+                const int x = blockIdx.x & 7;
+                const int64_t i = (int64_t)(blockIdx.x >> 3) + (int64_t)iter * (gridDim.x >> 3);
+                u = (i < xcd_off[x + 1] - xcd_off[x]) ? xcd_off[x] + (int)i : n_units;
+            } else {
+                const int64_t v = (int64_t)blockIdx.x + (int64_t)iter * gridDim.x;
+                u = v < n_units ? (int)v : n_units;
             }
         }
         if (u >= n_units) break;
@@ -919,7 +925,7 @@ __device__ __forceinline__ V buffer_load_scalar(__amdgpu_buffer_rsrc_t r, unsign
 // plans (their work units then cover every direction of a station range).
 constexpr int kFusedMaxDirs = 64;
 // Stations per work unit of the fused kernel.
-constexpr int kFusedStations = 16;
+constexpr int kFusedStations = 8;
 
 // One work unit (event, stations [s0, s1)) with ALL of the event's directions
 // per workgroup (persistent grid, units taken as in k_unfold).  Per station:
@@ -962,39 +968,67 @@ __global__ __launch_bounds__(N / 8) __attribute__((amdgpu_waves_per_eu(4))) void
     vmem_wait_all();
     lds_barrier();
     if (t == 0) sh_list = blockIdx.x & 7;
-    for (;;) {
-        // the next unit: from this XCD's list, then from the others (as k_unfold)
-        if (t == 0) {
-            int got = n_units;
-            if (xcd_off != nullptr) {
-                for (int k = 0; k < 8; ++k) {
-                    const int x = (sh_list + k) & 7;
-                    const unsigned cnt = (unsigned)(xcd_off[x + 1] - xcd_off[x]);
-                    if (cnt == 0) continue;
-                    const unsigned i = atomicAdd(&counter[x], 1u);
-                    if (i < cnt) {
-                        got = xcd_off[x] + (int)i;
-                        sh_list = x;
-                        break;
-                    }
+    // the next unit: from this XCD's list, then from the others (as k_unfold)
+    auto next_unit = [&]() {
+        int got = n_units;
+        if (xcd_off != nullptr) {
+            for (int k = 0; k < 8; ++k) {
+                const int x = (sh_list + k) & 7;
+                const unsigned cnt = (unsigned)(xcd_off[x + 1] - xcd_off[x]);
+                if (cnt == 0) continue;
+                const unsigned i = atomicAdd(&counter[x], 1u);
+                if (i < cnt) {
+                    got = xcd_off[x] + (int)i;
+                    sh_list = x;
+                    break;
                 }
-            } else {
-                got = (int)atomicAdd(counter, 1u);
             }
-            sh_u = got;
+        } else {
+            got = (int)atomicAdd(counter, 1u);
         }
+        return got;
+    };
+    Tin a[E], b[E];
+    const unsigned toff_in = (unsigned)t * (unsigned)sizeof(Tin);
+    // the two channel traces of one station (2 N samples from `base`)
+    auto load_traces = [&](const Tin* base) {
+        const __amdgpu_buffer_rsrc_t r = buffer_range(base, 2 * N * (unsigned)sizeof(Tin));
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            a[i] = buffer_load_scalar<Tin>(r, toff_in, (int)(TT * i * sizeof(Tin)));
+            b[i] = buffer_load_scalar<Tin>(r, toff_in, (int)((N + TT * i) * sizeof(Tin)));
+        }
+    };
+    // Units are reserved one ahead: the first station of the next unit is
+    // loaded like any next station (before the last stores of the current
+    // unit), so a unit start waits for no stores and small units (fewer
+    // events in flight per XCD, coefficient rows kept in L2) cost nothing.
+    if (t == 0) sh_u = next_unit();
+    lds_barrier();
+    // the unit index is uniform: stated so, the unit and its event are read by
+    // scalar loads
+    int u = __builtin_amdgcn_readfirstlane(sh_u);
+    if (u < n_units) {
+        const int4 w0 = units[u];
+        load_traces(volt + evs[w0.x].volt_off + (int64_t)w0.z * 2 * N);
+    }
+    while (u < n_units) {
+        lds_barrier();  // every wave has read sh_u
+        if (t == 0) sh_u = next_unit();
         lds_barrier();
-        // the unit index is uniform: stated so, the unit and its event are read
-        // by scalar loads
-        const int u = __builtin_amdgcn_readfirstlane(sh_u);
-        lds_barrier();
-        if (u >= n_units) break;
+        const int un = __builtin_amdgcn_readfirstlane(sh_u);
         const int4 wu = units[u];  // (event, -, first station, end station)
         const EvDesc ev = evs[wu.x];
         const int s0 = wu.z, s1 = wu.w, D = ev.D;
         const unsigned nb = (unsigned)ev.nb, k_lo = (unsigned)ev.k_lo;
         const MBin<T>* __restrict__ Me = M + ev.m_off;
         const Tin* __restrict__ Ve = volt + ev.volt_off;
+        // the first station of the next unit (null: none)
+        const Tin* Vn = nullptr;
+        if (un < n_units) {
+            const int4 wn = units[un];
+            Vn = volt + evs[wn.x].volt_off + (int64_t)wn.z * 2 * N;
+        }
         // byte offsets of this thread's bins in a coefficient row, clamped to a
         // valid bin past the band (to the first record of the twiddle table
         // when the band is empty)
@@ -1017,18 +1051,7 @@ __global__ __launch_bounds__(N / 8) __attribute__((amdgpu_waves_per_eu(4))) void
                 pm[q].q1 = hi.b;
             }
         };
-        Tin a[E], b[E];
-        const unsigned toff_in = (unsigned)t * (unsigned)sizeof(Tin);
-        auto load_traces = [&](int s) {
-            const __amdgpu_buffer_rsrc_t r = buffer_range(Ve + (int64_t)s * 2 * N, 2 * N * (unsigned)sizeof(Tin));
-#pragma unroll
-            for (int i = 0; i < E; ++i) {
-                a[i] = buffer_load_scalar<Tin>(r, toff_in, (int)(TT * i * sizeof(Tin)));
-                b[i] = buffer_load_scalar<Tin>(r, toff_in, (int)((N + TT * i) * sizeof(Tin)));
-            }
-        };
         MBin<T> pm[PF];
-        load_traces(s0);
         for (int s = s0; s < s1; ++s) {
             // 1. forward transform of the station, conj(F+(conj z)), through the
             // buffers in the inverse transforms' order (lb, la, lb: the same LDS
@@ -1076,8 +1099,12 @@ __global__ __launch_bounds__(N / 8) __attribute__((amdgpu_waves_per_eu(4))) void
                 }
                 __builtin_amdgcn_s_setprio(0);
                 // the last direction: the next station's traces (this station's
-                // X and coefficients are dead now), ahead of the stores
-                if (last && s + 1 < s1) load_traces(s + 1);
+                // X and coefficients are dead now), ahead of the stores; after
+                // the unit's last station, the next unit's first
+                if (last) {
+                    const Tin* nx = s + 1 < s1 ? Ve + (int64_t)(s + 1) * 2 * N : Vn;
+                    if (nx != nullptr) load_traces(nx);
+                }
                 lds_barrier();
 #pragma unroll
                 for (int i = 0; i < E; ++i) {
@@ -1103,6 +1130,7 @@ __global__ __launch_bounds__(N / 8) __attribute__((amdgpu_waves_per_eu(4))) void
             direction(D - 1, true);
         }
         __builtin_amdgcn_s_setprio(0);
+        u = un;
     }
 }
 
@@ -1408,8 +1436,9 @@ constexpr UnfoldVariant kUnfoldVariants[] = {
     {8, 8, TW_REG, false, false, true},    {16, 16, TW_REG, false, false, true},
     {8, 8, TW_HYB, false, false, true},    {8, 8, TW_HYB, false, false, false},
     {8, 8, TW_LF, false, false, true},     {8, 8, TW_LF, false, false, false},
+    {8, 8, TW_LFR, false, false, true},
 };
-constexpr int kNumVariants = 16;
+constexpr int kNumVariants = 17;
 
 // LDS one workgroup may allocate on gfx950 (the whole 160 KiB of a CU).
 constexpr int kMaxLdsPerBlock = 163840;
@@ -1430,6 +1459,9 @@ constexpr bool variant_built(int n, int v, int tsize)
     if (kUnfoldVariants[v].rmax > e) return false;
     if (kUnfoldVariants[v].pair && ((n / e) % 64 != 0 || e % 2 != 0)) return false;
     if (kUnfoldVariants[v].pp && 2 * (n + 16) * 2 * tsize > kMaxLdsPerBlock) return false;  // 2 x lds_elems
+    // every pass's twiddle pairs in registers: FP64 (one workgroup per CU,
+    // registers to spare); FP32 shapes need them for four waves per SIMD
+    if (kUnfoldVariants[v].twmode == TW_LFR && tsize != 8) return false;
     return true;
 }
 
@@ -1460,13 +1492,14 @@ static int ilog2(int n)
 
 // Selected variant per [precision][log2 N]; the defaults are the shapes
 // that measured fastest on MI355X (from 1024 samples up, E=8 with two LDS
-// buffers: for float and for double at 2048 and 4096 samples the early
-// twiddles in LDS and the next station's bins prefetched, for double at 1024
-// register twiddles; below, E=16 with register twiddles for float and table
-// twiddles for double).
+// buffers and the next station's bins prefetched: for float the fused
+// multiply-add butterflies with the early passes' twiddle pairs in LDS, for
+// double at 4096 samples the same butterflies with every pass's pairs in
+// registers, at 2048 the hybrid table, at 1024 register twiddles; below,
+// E=16 with register twiddles for float and table twiddles for double).
 static std::mutex g_var_mu;
-static int g_variant[2][13] = {{1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10, 12, 12},
-                               {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 12, 12, 12}};
+static int g_variant[2][13] = {{1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10, 12, 16},
+                               {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 12, 14, 14}};
 
 static int unfold_variant(int prec, int n)
 {
@@ -1560,6 +1593,26 @@ static hipError_t launch_fused(int n, hipStream_t st, const Tin* volt, const EvD
 }
 
 template <typename T, int N, int V>
+static int occupancy_nv();
+
+// Workgroups of unfold variant V the device holds at once (cached; 256 if
+// the occupancy query fails).
+template <typename T, int N, int V>
+static int resident_blocks()
+{
+    static const int blocks = [] {
+        int dev = 0, cus = 0;
+        const int occ = occupancy_nv<T, N, V>();
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || occ <= 0 ||
+            cus <= 0)
+            return 256;
+        return cus * occ;
+    }();
+    return blocks;
+}
+
+template <typename T, int N, int V>
 static hipError_t launch_unfold_nv(hipStream_t st, const EvDesc& ev0, const EvDesc* evs,
                                    const int4* units, int n_units, int spw, const XBin<T>* X,
                                    const MBin<T>* M, T* efield, const C2<T>* tw,
@@ -1571,10 +1624,17 @@ static hipError_t launch_unfold_nv(hipStream_t st, const EvDesc& ev0, const EvDe
     } else {
         using S = UShape<T, N, V>;
         if (n_units <= 0) return hipSuccess;
-        int grid = xcd_off != nullptr ? 8 * xcd_max_list : n_units;
+        int grid;
         if (counter != nullptr) {
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counter, 8);
             grid = std::min(n_units, persistent_blocks);
+        } else {
+            // no more blocks than the device holds at once: each loops over
+            // its share of the units, so the per-block set-up (twiddles, the
+            // LDS table) is paid once per block and the next unit's start
+            // overlaps the previous unit's stores
+            const int cap = resident_blocks<T, N, V>();
+            grid = xcd_off != nullptr ? 8 * std::max(1, std::min(xcd_max_list, cap / 8)) : std::min(n_units, cap);
         }
         hipLaunchKernelGGL((k_unfold<T, N, S::E, S::RMAX, S::TWMODE, S::WAVE, S::PAIR, S::PP>), dim3(grid), dim3(S::BLOCK), S::LDS, st,
                            ev0, evs, units, n_units, spw, X, M, efield, tw, counter, xcd_off);
@@ -1593,6 +1653,7 @@ static hipError_t launch_unfold_n(int v, hipStream_t st, const EvDesc& ev0, cons
 #define V_(VV) \
     case VV: return launch_unfold_nv<T, N, VV>(st, ev0, evs, units, n_units, spw, X, M, efield, tw, counter, persistent_blocks, xcd_off, xcd_max_list);
         V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11) V_(12) V_(13) V_(14) V_(15)
+        V_(16)
 #undef V_
     }
     return hipErrorInvalidValue;
@@ -1670,6 +1731,7 @@ static int persistent_blocks_for(int n, int v, int device)
             case 13: per_cu = occupancy_nv<T, NN, 13>(); break;                                 \
             case 14: per_cu = occupancy_nv<T, NN, 14>(); break;                                 \
             case 15: per_cu = occupancy_nv<T, NN, 15>(); break;                                 \
+            case 16: per_cu = occupancy_nv<T, NN, 16>(); break;                                 \
         }                                                                                       \
         break;
         AU_FOR_EACH_N(X_)
@@ -1971,6 +2033,35 @@ static void launch_coef(hipStream_t st, const au_table* tb, const EvDesc& ev0, c
                        M, counts, 0.0);
 }
 
+// Stations per work unit of a direction scan (one event, n_dir directions;
+// units (direction, station range) spread over a grid of `blocks` that each
+// loop over their share): 16, doubled while every block still gets at least
+// four units.  A unit's first station waits for the stores of the block's
+// previous unit (its bins are loaded after them), so fewer, longer units
+// leave fewer such waits: the FP64 scan of 124 stations x 2048 directions
+// runs 3 % faster with one unit per direction than with 16-station units.
+static int scan_stations_per_unit(int S, int64_t n_dir, int blocks)
+{
+    int spw = kStationsPerUnit;
+    while (spw < S && n_dir * (int64_t)((S + 2 * spw - 1) / (2 * spw)) >= 4 * (int64_t)std::max(blocks, 1)) spw *= 2;
+    return spw;
+}
+
+// Workgroups of unfold variant v the device holds at once, cached per
+// (precision, trace length, variant).
+static int scan_blocks(int prec, int n, int variant, int device)
+{
+    static std::atomic<int> cache[2][13][kNumVariants];
+    const int pi = prec == AU_PREC_FP64 ? 1 : 0, li = ilog2(n);
+    if (li < 0 || li > 12 || variant < 0 || variant >= kNumVariants) return 256;
+    int b = cache[pi][li][variant].load(std::memory_order_relaxed);
+    if (b == 0) {
+        b = au::persistent_blocks(prec, n, variant, device);
+        cache[pi][li][variant].store(b, std::memory_order_relaxed);
+    }
+    return b;
+}
+
 // Directions come from h_dirs (copied into the workspace's direction slot
 // first), from d_dirs (already in that slot, device memory), or, with both
 // null, the one direction (zen, az).
@@ -2013,11 +2104,12 @@ static au_status run_event(const au_table* tb, const au_event* ev, const EvParam
                               ev->fs_hz, ev->fallback_rel, ev->singular_rel, M, cnt);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_coef: ") + hipGetErrorString(e));
-    const int chunks = (p.S + kStationsPerUnit - 1) / kStationsPerUnit;
+    const int spw = scan_stations_per_unit(p.S, n_dir, scan_blocks(ev->prec, p.N, variant, tb->device));
+    const int chunks = (p.S + spw - 1) / spw;
     const int64_t n_units = (int64_t)n_dir * chunks;
     if (n_units > (int64_t)0x7fffffff) return fail(AU_EINVAL, "too many work units");
-    e = launch_unfold<T>(p.N, variant, st, ev0, nullptr, nullptr, (int)n_units,
-                         kStationsPerUnit, X, M, (T*)d_efield, tw, nullptr, 0);
+    e = launch_unfold<T>(p.N, variant, st, ev0, nullptr, nullptr, (int)n_units, spw, X, M, (T*)d_efield, tw,
+                         nullptr, 0);
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_unfold: ") + hipGetErrorString(e));
     return AU_OK;
 }
@@ -2153,9 +2245,11 @@ static au_status run_scan_scratch(const au_table* tb, const au_event* ev, const 
         e = launch_spectrum<float, T>(p.N, st, (const float*)d_volt, ev0, nullptr, nullptr, p.S, ev0.nb, X, tw);
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_spectrum: ") + hipGetErrorString(e));
     unsigned long long* cnt = (unsigned long long*)d_counts;
-    const int chunks = (p.S + kStationsPerUnit - 1) / kStationsPerUnit;
+    const int blocks = scan_blocks(ev->prec, p.N, variant, tb->device);
     for (int d0 = 0; d0 < n_dir; d0 += chunk) {
         const int nd = std::min(chunk, n_dir - d0);
+        const int spw = scan_stations_per_unit(p.S, nd, blocks);
+        const int chunks = (p.S + spw - 1) / spw;
         ev0.D = nd;
         if (tb->dtype == AU_F64)
             launch_coef<double, T>(st, tb, ev0, nullptr, nullptr, nd, d_dirs + 2 * (size_t)d0, 0.0, 0.0, ev->fs_hz,
@@ -2168,8 +2262,7 @@ static au_status run_scan_scratch(const au_table* tb, const au_event* ev, const 
         const int64_t n_units = (int64_t)nd * chunks;
         if (n_units > (int64_t)0x7fffffff) return fail(AU_EINVAL, "too many work units");
         T* out = (T*)d_efield + (size_t)d0 * p.S * 2 * p.N;
-        e = launch_unfold<T>(p.N, variant, st, ev0, nullptr, nullptr, (int)n_units, kStationsPerUnit, X, M, out, tw,
-                             nullptr, 0);
+        e = launch_unfold<T>(p.N, variant, st, ev0, nullptr, nullptr, (int)n_units, spw, X, M, out, tw, nullptr, 0);
         if (e != hipSuccess) return fail(AU_EDEVICE, std::string("k_unfold: ") + hipGetErrorString(e));
     }
     return AU_OK;

@@ -342,14 +342,19 @@ constexpr int lds_zero_slot() { return N + 1; }
 //             NS >= TT) for the fused multiply-add butterflies of lf_dft:
 //             per (pass, k) the (tangent, cosine) pairs of the angles the
 //             radix-R butterfly needs (lf_entries) instead of R-1 roots.
-enum { TW_TABLE = 0, TW_REG = 1, TW_SPLIT = 2, TW_HYB = 3, TW_LF = 4 };
+//   TW_LFR:   the TW_LF pairs of every pass in registers (no LDS table
+//             reads: for shapes with registers to spare whose transform is
+//             bound by LDS bandwidth, as FP64 at one workgroup per CU).
+enum { TW_TABLE = 0, TW_REG = 1, TW_SPLIT = 2, TW_HYB = 3, TW_LF = 4, TW_LFR = 5 };
 
 // Twiddles of the early passes in a per-workgroup LDS table.
 constexpr bool tw_lds_early(int mode) { return mode == TW_HYB || mode == TW_LF; }
-// (tangent, cosine) pairs per butterfly of a radix-R pass in TW_LF.
+// Fused multiply-add butterflies with (tangent, cosine) twiddle pairs.
+constexpr bool tw_lf(int mode) { return mode == TW_LF || mode == TW_LFR; }
+// (tangent, cosine) pairs per butterfly of a radix-R pass in TW_LF / TW_LFR.
 constexpr int lf_entries(int r) { return r == 8 ? 4 : (r == 4 ? 2 : 1); }
 // Twiddle entries per butterfly of a radix-R pass.
-constexpr int tw_per(int mode, int r) { return mode == TW_LF ? lf_entries(r) : r - 1; }
+constexpr int tw_per(int mode, int r) { return tw_lf(mode) ? lf_entries(r) : r - 1; }
 
 template <int N, int RMAX>
 constexpr int pass_radix(int ns) { return (N / ns < RMAX) ? N / ns : RMAX; }
@@ -362,7 +367,7 @@ constexpr int tw_offset(int ns_target)
         if (ns == 1) continue;
         const int r = pass_radix<N, RMAX>(ns);
         if (tw_lds_early(TWMODE) && ns < N / E) continue;
-        off += (TWMODE == TW_REG || tw_lds_early(TWMODE)) ? (E / r) * tw_per(TWMODE, r) : (r - 1);
+        off += (TWMODE == TW_REG || TWMODE == TW_LFR || tw_lds_early(TWMODE)) ? (E / r) * tw_per(TWMODE, r) : (r - 1);
     }
     return off;
 }
@@ -423,7 +428,7 @@ __device__ __forceinline__ void load_twiddles_from(C2<T>* __restrict__ w, const 
             constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
             if constexpr (tw_lds_early(TWMODE) && NS < TT) {
                 // in the LDS table (fill_lds_twiddles)
-            } else if constexpr (TWMODE == TW_LF) {
+            } else if constexpr (tw_lf(TWMODE)) {
                 constexpr int LE = lf_entries(R);
 #pragma unroll
                 for (int m = 0; m < B; ++m) {
@@ -588,14 +593,17 @@ __device__ __forceinline__ void fft_pass(C2<T> (&x)[E], C2<T>* __restrict__ lds,
         C2<T> v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = x[m + r * B];
-        if constexpr (TWMODE == TW_LF && NS > 1) {
+        if constexpr (tw_lf(TWMODE) && NS > 1) {
             constexpr int LE = lf_entries(R);
             constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
             C2<T> L[LE];
 #pragma unroll
-            for (int e = 0; e < LE; ++e)
-                L[e] = lf_sign<SIGN>(NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k]
-                                             : w[OFF + m * LE + e]);
+            for (int e = 0; e < LE; ++e) {
+                if constexpr (TWMODE == TW_LF && NS < TT)
+                    L[e] = lf_sign<SIGN>(ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k]);
+                else
+                    L[e] = lf_sign<SIGN>(w[OFF + m * LE + e]);
+            }
             lf_dft<R, SIGN>(v, L);
         } else {
             if constexpr (NS > 1) {
@@ -675,14 +683,17 @@ __device__ __forceinline__ void fft_pass_pp(C2<T> (&x)[E], C2<T>* __restrict__ l
         C2<T> v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = x[m + r * B];
-        if constexpr (TWMODE == TW_LF && NS > 1) {
+        if constexpr (tw_lf(TWMODE) && NS > 1) {
             constexpr int LE = lf_entries(R);
             constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
             C2<T> L[LE];
 #pragma unroll
-            for (int e = 0; e < LE; ++e)
-                L[e] = lf_sign<SIGN>(NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k]
-                                             : w[OFF + m * LE + e]);
+            for (int e = 0; e < LE; ++e) {
+                if constexpr (TWMODE == TW_LF && NS < TT)
+                    L[e] = lf_sign<SIGN>(ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k]);
+                else
+                    L[e] = lf_sign<SIGN>(w[OFF + m * LE + e]);
+            }
             lf_dft<R, SIGN>(v, L);
         } else {
             if constexpr (NS > 1) {
@@ -755,14 +766,17 @@ __device__ __forceinline__ void fft_pass2(C2<T> (&x)[E], C2<T> (&y)[E], C2<T>* _
             u[r] = x[m + r * B];
             v[r] = y[m + r * B];
         }
-        if constexpr (TWMODE == TW_LF && NS > 1) {
+        if constexpr (tw_lf(TWMODE) && NS > 1) {
             constexpr int LE = lf_entries(R);
             constexpr int OFF = tw_offset<N, E, RMAX, TWMODE>(NS);
             C2<T> L[LE];
 #pragma unroll
-            for (int e = 0; e < LE; ++e)
-                L[e] = lf_sign<SIGN>(NS < TT ? ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k]
-                                             : w[OFF + m * LE + e]);
+            for (int e = 0; e < LE; ++e) {
+                if constexpr (TWMODE == TW_LF && NS < TT)
+                    L[e] = lf_sign<SIGN>(ltw[ltw_offset<N, E, RMAX, TW_LF>(NS) + e * NS + k]);
+                else
+                    L[e] = lf_sign<SIGN>(w[OFF + m * LE + e]);
+            }
             lf_dft<R, SIGN>(u, L);
             lf_dft<R, SIGN>(v, L);
         } else {
