@@ -32,7 +32,7 @@ sys.path.insert(0, ROOT)
 # WRITE_SIZE x 1.000 (copy-probe calibration), keyed by kernel and launch size.
 PROFILED_TRAFFIC_SOURCE = "profiles/k_unfold_fp32_batched_256events.md"
 PROFILED_TRAFFIC_BYTES = {
-    ("k_unfold<float, 4096, 8, 8, 3, false, false, true>", 2047488): (1190285 + 65522433) * 1024,
+    ("k_unfold<float, 4096, 8, 8, 4, false, false, true>", 2047488): (1180268 + 65522388) * 1024,
 }
 HBM_PEAK_GBS = 8000.0
 
@@ -268,7 +268,7 @@ FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Dynamic VALU instructions (wave-instructions) per station-unfold of the dominant kernel, from the
 # committed SQ_INSTS_VALU profile of the same build and workload, keyed like the traffic.
 PROFILED_VALU_INSTR = {
-    ("k_unfold<float, 4096, 8, 8, 3, false, false, true>", 2047488): 2766.3,
+    ("k_unfold<float, 4096, 8, 8, 4, false, false, true>", 2047488): 2462.0,
 }
 # wave64 VALU issue without packed FP32: one instruction per SIMD every 4 cycles, 1024 SIMDs at 2.4 GHz
 VALU_ISSUE_PEAK_GINSTR = 256 * 4 * 2.4e9 / 4 / 1e9
@@ -277,7 +277,7 @@ VALU_ISSUE_PEAK_GINSTR = 256 * 4 * 2.4e9 / 4 / 1e9
 def valu_issue_view(cls):
     """The dominant launch against the VALU issue rate: profiled instructions per station-unfold x the
     launch's station-unfolds over its time, against the nominal-clock issue limit (the chip runs this
-    kernel at 1.8-1.9 GHz, so the limit at the sustained clock is about 0.78 of the nominal one)."""
+    kernel at 1.7-1.8 GHz, so the limit at the sustained clock is about 0.72 of the nominal one)."""
     per = PROFILED_VALU_INSTR.get((cls["kernel"], cls["station_unfolds"]))
     if per is None:
         return None
