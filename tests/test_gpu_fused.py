@@ -104,3 +104,40 @@ def test_fused_class_beside_an_unfused_one(api, fine32):
                          S.BAND_LO_HZ, S.BAND_HI_HZ, units=[[0, 0], [15, 11]])
     eo = p1.event_output(out1, 0)
     assert_fp32_close(np.stack([eo[0, 0].cpu().numpy(), eo[15, 11].cpu().numpy()]), ref, TOL_FP32, "fused 2048")
+
+
+@pytest.mark.parametrize("band", [(0, 40_000_000), (41_000_000, 41_010_000)], ids=["dc-40MHz", "empty"])
+def test_fused_plan_band_edges(api, fine32, band):
+    """A band that includes DC (bin 0 keeps real parts only) and a band narrower than one bin (no
+    in-band bin at all: zero traces), fused against separate stages and, with DC, against the oracle."""
+    import torch
+    t, tab = fine32
+    lo, hi = band
+    specs = [(9, 4096, S.direction_grid(2, 2)), (5, 2048, S.direction_grid(1, 3))]
+    say("fused plan band", band)
+    outs = []
+    vs = [S.traces(s, n, cfg=2, event=120 + e, dtype=np.float32) for e, (s, n, _) in enumerate(specs)]
+    for flags in (7, 7 | api.AU_PLAN_FUSED):
+        plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=flags, band_lo_hz=lo,
+                        band_hi_hz=hi)
+        volt = np.zeros(plan.volt_elems, dtype=np.float32)
+        for e, v in enumerate(vs):
+            volt[plan.volt_offsets[e]:plan.volt_offsets[e] + v.size] = v.ravel()
+        out = torch.full((plan.efield_elems,), float("nan"), dtype=torch.float32, device="cuda")
+        plan.run(torch.from_numpy(volt).cuda(), out)
+        torch.cuda.synchronize()
+        outs.append((plan, out))
+    (p0, o0), (p1, o1) = outs
+    for e, (s, n, d) in enumerate(specs):
+        a = p1.event_output(o1, e).cpu().numpy()
+        b = p0.event_output(o0, e).cpu().numpy()
+        assert not np.any(np.isnan(a))
+        if hi - lo < S.FS_HZ // n:
+            assert not np.any(a) and not np.any(b)
+            continue
+        assert station_errors(a, b).max() <= 1e-6, e
+        units = np.array([[0, 0], [len(d) - 1, s - 1]])
+        ref, _, _ = O.unfold(GF, t.astype(np.complex128), vs[e].astype(np.float64), np.asarray(d, dtype=np.float64),
+                             S.FS_HZ, lo, hi, units=units)
+        got = np.stack([a[di, si] for di, si in units])
+        assert_fp32_close(got, ref, TOL_FP32, "fused band %s event %d" % (band, e))
