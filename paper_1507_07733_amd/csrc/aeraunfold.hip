@@ -2034,16 +2034,21 @@ static void launch_coef(hipStream_t st, const au_table* tb, const EvDesc& ev0, c
 }
 
 // Stations per work unit of a direction scan (one event, n_dir directions;
-// units (direction, station range) spread over a grid of `blocks` that each
-// loop over their share): 16, doubled while every block still gets at least
-// four units.  A unit's first station waits for the stores of the block's
-// previous unit (its bins are loaded after them), so fewer, longer units
-// leave fewer such waits: the FP64 scan of 124 stations x 2048 directions
-// runs 3 % faster with one unit per direction than with 16-station units.
+// units (direction, station range) spread over a grid of up to `blocks`
+// that each loop over their share): from 16, halved while there are fewer
+// units than blocks (a small scan -- one event of ten stations and one
+// direction -- then runs a station per workgroup instead of all ten in one),
+// doubled while every block still gets at least four units.  A unit's first
+// station waits for the stores of the block's previous unit (its bins are
+// loaded after them), so fewer, longer units leave fewer such waits: the
+// FP64 scan of 124 stations x 2048 directions runs 3 % faster with one unit
+// per direction than with 16-station units.
 static int scan_stations_per_unit(int S, int64_t n_dir, int blocks)
 {
+    const int64_t b = std::max(blocks, 1);
     int spw = kStationsPerUnit;
-    while (spw < S && n_dir * (int64_t)((S + 2 * spw - 1) / (2 * spw)) >= 4 * (int64_t)std::max(blocks, 1)) spw *= 2;
+    while (spw > 1 && n_dir * (int64_t)((S + spw - 1) / spw) < b) spw /= 2;
+    while (spw < S && n_dir * (int64_t)((S + 2 * spw - 1) / (2 * spw)) >= 4 * b) spw *= 2;
     return spw;
 }
 
