@@ -1197,6 +1197,44 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
     }
     const unsigned nb = (unsigned)ev.nb, k_lo = (unsigned)ev.k_lo;
     const MBin<T>* __restrict__ Md = M + ev.m_off + (int64_t)d * ev.nb;
+    // Bins per thread loaded one station ahead (FP64, one transform pair per
+    // workgroup, which has the registers at two waves per SIMD): their loads
+    // then overlap the current station's transforms instead of opening the
+    // next station's staging.  Clamped like k_unfold's: a valid station, bin
+    // nb-1 for bins past the band, the twiddle table when the band is empty.
+    constexpr int PF = (sizeof(T) == 8 && E == 8 && G == 1 && DUAL) ? 2 : 0;
+    MBin<T> pm[PF > 0 ? PF : 1];
+    XBin<T> px[PF > 0 ? PF : 1];
+    auto prefetch = [&](int sv) {
+        const XBin<T>* __restrict__ xs = X + ev.x_off + (int64_t)sv * ev.nb;
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const unsigned j = min((unsigned)(t + TT * q), nb > 0 ? nb - 1 : 0u);
+            pm[q] = nb > 0 ? Md[j] : *reinterpret_cast<const MBin<T>*>(tw);
+            px[q] = nb > 0 ? xs[j] : *reinterpret_cast<const XBin<T>*>(tw);
+        }
+    };
+    if constexpr (PF > 0) prefetch(min(s0, s1 - 1));
+    // Z[k] = zp, Z[N-k] = conj zq; the Hilbert spectrum Zh[k] = -i Z[k],
+    // Zh[N-k] = i Z[N-k]; a lane with nothing to write (ok false) writes the
+    // spare pad slot, which no gather reads
+    auto stage = [&](int h, unsigned j, const C2<T>& zp, const C2<T>& zq, bool ok) {
+        const unsigned k = k_lo + j;
+        if (ok && k == 0) {
+            if (DUAL || h == 0) la[0] = packed_dc(zp, zq);
+            if (DUAL || h == 1) lb[0] = C2<T>{0, 0};
+        } else {
+            const int a = ok ? lpad<T>(k) : lds_pad_slot<N>(), b = ok ? lpad<T>(N - k) : lds_pad_slot<N>();
+            if (DUAL || h == 0) {
+                la[a] = zp;
+                la[b] = C2<T>{zq.re, -zq.im};
+            }
+            if (DUAL || h == 1) {
+                lb[a] = C2<T>{zp.im, -zp.re};
+                lb[b] = C2<T>{zq.im, zq.re};
+            }
+        }
+    };
     for (int base = s0; base < s1; base += G) {
         const int s = base + g;
         const bool active = s < s1;
@@ -1210,26 +1248,28 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
         __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int h = 0; h < (DUAL ? 1 : 2); ++h) {
-            if (active) {
+            if constexpr (PF > 0) {
+                // bins past the prefetched ones (a band wider than PF TT bins)
+                if (active && nb > (unsigned)(PF * TT))
+                    for (unsigned j = t + TT * PF; j < nb; j += TT) {
+                        C2<T> zp, zq;
+                        packed_bin(Md[j], Xs[j], zp, zq);
+                        stage(h, j, zp, zq, true);
+                    }
+#pragma unroll
+                for (int q = 0; q < PF; ++q) {
+                    const unsigned j = t + TT * q;
+                    C2<T> zp, zq;
+                    packed_bin(pm[q], px[q], zp, zq);
+                    stage(h, j, zp, zq, active && j < nb);
+                }
+                // the next station's bins, ahead of this station's transforms
+                prefetch(min(s + G, s1 - 1));
+            } else if (active) {
                 for (unsigned j = t; j < nb; j += TT) {
-                    // Z[k] = zp, Z[N-k] = conj zq; the Hilbert spectrum
-                    // Zh[k] = -i Z[k], Zh[N-k] = i Z[N-k]
                     C2<T> zp, zq;
                     packed_bin(Md[j], Xs[j], zp, zq);
-                    const unsigned k = k_lo + j;
-                    if (k == 0) {
-                        if (DUAL || h == 0) la[0] = packed_dc(zp, zq);
-                        if (DUAL || h == 1) lb[0] = C2<T>{0, 0};
-                    } else {
-                        if (DUAL || h == 0) {
-                            la[lpad<T>(k)] = zp;
-                            la[lpad<T>(N - k)] = C2<T>{zq.re, -zq.im};
-                        }
-                        if (DUAL || h == 1) {
-                            lb[lpad<T>(k)] = C2<T>{zp.im, -zp.re};
-                            lb[lpad<T>(N - k)] = C2<T>{zq.im, zq.re};
-                        }
-                    }
+                    stage(h, j, zp, zq, true);
                 }
             }
             lds_barrier();
