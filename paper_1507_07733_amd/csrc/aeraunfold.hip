@@ -857,8 +857,9 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
             // memory instructions and the short staging then go ahead of the
             // other workgroup's transform on the same SIMDs, which keeps the
             // store stream fed and shortens the barrier wait (+2-3 % at
-            // N = 4096).
-            __builtin_amdgcn_s_setprio(2);
+            // N = 4096).  Not in FP64, whose one workgroup per CU has no
+            // other workgroup to go ahead of (-2 % with the raise there).
+            if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(2);
             // Prefetch the next station's bins before this station's stores:
             // vector-memory completions are counted in issue order, so loads
             // issued after the stores would wait for every store to land.
