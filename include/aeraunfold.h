@@ -147,6 +147,13 @@ au_status au_band_bins(const au_event* ev, int32_t* k_lo, int32_t* n_band);
  *   d_efield: [S][2][N] output (E_theta, E_phi), float or double per ev->prec.
  *   d_work:   workspace of au_workspace_bytes(ev, 1) bytes, or NULL to let the
  *             library take it from the stream-ordered pool (hipMallocAsync).
+ * Events of 2048 or 4096 samples whose traces and table are in the compute
+ * precision and whose band holds at most N/4 bins run in one launch (one
+ * workgroup per station: forward transform, the direction's coefficients,
+ * solve, inverse transform) and leave d_work untouched (a given workspace
+ * is still checked for size); the results agree with a one-direction
+ * au_unfold_direction_scan to rounding (per station within 1e-6 of the peak
+ * in FP32, 1e-13 in FP64), the counters exactly.
  * Errors: AU_EINVAL, AU_ENOMEM (work_bytes too small or pool exhausted), AU_EDEVICE.
  */
 au_status au_unfold_event(const au_table* table, const au_event* ev, const void* d_volt,

@@ -409,6 +409,49 @@ __global__ __launch_bounds__(N / 8) void k_spectrum_stream(const Tin* __restrict
 // |det| < fallback_rel ||H||_F^2 in float, the determinant and inverse are
 // redone in double from the same float H.  Singular bins give zero coefs.
 // RESP: write the interpolated H instead (au_pattern_response).
+// The packed coefficients of one bin from its interpolated H (1/N folded
+// in): FP64 by the direct inverse; FP32 by the inverse on 2^-e H (exact
+// scaling, see pow2_normalise) with the FP64 determinant fallback when
+// |det| < fallback_rel ||H||_F^2.  Counts fallback and singular bins.
+template <typename T>
+__device__ __forceinline__ MBin<T> coef_from_h(const C2<T> (&h)[4], int n, T inv_n, double fallback_rel,
+                                               double singular_rel, unsigned int& n_fb, unsigned int& n_sg)
+{
+    MBin<T> m;
+    if constexpr (sizeof(T) == 4) {
+        C2<float> hs[4];
+        int e;
+        if (!pow2_normalise(h, hs, e)) {
+            m.p0 = m.p1 = m.q0 = m.q1 = C2<T>{0, 0};
+            ++n_sg;
+        } else {
+            const C2<float> det = csub(cmul(hs[0], hs[3]), cmul(hs[1], hs[2]));
+            float fro2 = 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fro2 += hs[i].re * hs[i].re + hs[i].im * hs[i].im;
+            const float ad2 = det.re * det.re + det.im * det.im;
+            const float thr = (float)fallback_rel * fro2;
+            if (ad2 < thr * thr) {
+                C2<double> hd[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) hd[i] = C2<double>{(double)hs[i].re, (double)hs[i].im};
+                MBin<double> md;
+                n_sg += invert2_scaled<double>(hd, ldexp(1.0 / (double)n, -e), singular_rel, md);
+                ++n_fb;
+                m.p0 = C2<T>{(T)md.p0.re, (T)md.p0.im};
+                m.p1 = C2<T>{(T)md.p1.re, (T)md.p1.im};
+                m.q0 = C2<T>{(T)md.q0.re, (T)md.q0.im};
+                m.q1 = C2<T>{(T)md.q1.re, (T)md.q1.im};
+            } else {
+                n_sg += invert2_scaled<T>(hs, ldexp(inv_n, -e), singular_rel, m);
+            }
+        }
+    } else {
+        n_sg += invert2<T>(h, inv_n, singular_rel, m);
+    }
+    return m;
+}
+
 template <typename Tt, typename T, bool RESP>
 __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ nodes, GridDev gd,
                                                  EvDesc ev0, const EvDesc* __restrict__ evs,
@@ -485,37 +528,8 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
                 m.p1 = h[1];
                 m.q0 = h[2];
                 m.q1 = h[3];
-            } else if constexpr (sizeof(T) == 4) {
-                // the fallback test and the inverse on 2^-e H (exact scaling, see pow2_normalise)
-                C2<float> hs[4];
-                int e;
-                if (!pow2_normalise(h, hs, e)) {
-                    m.p0 = m.p1 = m.q0 = m.q1 = C2<T>{0, 0};
-                    ++n_sg;
-                } else {
-                    const C2<float> det = csub(cmul(hs[0], hs[3]), cmul(hs[1], hs[2]));
-                    float fro2 = 0.f;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) fro2 += hs[i].re * hs[i].re + hs[i].im * hs[i].im;
-                    const float ad2 = det.re * det.re + det.im * det.im;
-                    const float thr = (float)fallback_rel * fro2;
-                    if (ad2 < thr * thr) {
-                        C2<double> hd[4];
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) hd[i] = C2<double>{(double)hs[i].re, (double)hs[i].im};
-                        MBin<double> md;
-                        n_sg += invert2_scaled<double>(hd, ldexp(1.0 / (double)ev.N, -e), singular_rel, md);
-                        ++n_fb;
-                        m.p0 = C2<T>{(T)md.p0.re, (T)md.p0.im};
-                        m.p1 = C2<T>{(T)md.p1.re, (T)md.p1.im};
-                        m.q0 = C2<T>{(T)md.q0.re, (T)md.q0.im};
-                        m.q1 = C2<T>{(T)md.q1.re, (T)md.q1.im};
-                    } else {
-                        n_sg += invert2_scaled<T>(hs, ldexp(inv_n, -e), singular_rel, m);
-                    }
-                }
             } else {
-                n_sg += invert2<T>(h, inv_n, singular_rel, m);
+                m = coef_from_h<T>(h, ev.N, inv_n, fallback_rel, singular_rel, n_fb, n_sg);
             }
             out[j] = m;
         }
@@ -1133,6 +1147,128 @@ __global__ __launch_bounds__(N / 8) __attribute__((amdgpu_waves_per_eu(4))) void
         __builtin_amdgcn_s_setprio(0);
         u = un;
     }
+}
+
+// ---------------------------------------------------------------------------
+// One event, one direction, in one launch (the latency path)
+// ---------------------------------------------------------------------------
+
+// The single-direction call (au_unfold_event) for 2048 and 4096 samples:
+// one workgroup per station runs the operations of the three launches of
+// the general path -- the forward transform and in-band split of its two
+// channel traces (as the fused kernel), the direction's coefficients of the
+// bins it stages (the angular slice at the band's frequency nodes in LDS,
+// then per bin the frequency interpolation and the inverse, as k_coef:
+// every workgroup computes the same direction's coefficients, a few hundred
+// bins), and the staging, inverse transform and stores of k_unfold -- so a
+// small event pays one launch instead of three.  Workgroup 0 counts the
+// fallback and singular bins (once per direction, as k_coef).  Needs bands
+// of at most 2 N/8 bins and at most kMaxSliceNodes frequency nodes.
+template <typename Tt, typename T, int N>
+__global__ __launch_bounds__(N / 8) void k_event_fused(const C2<Tt>* __restrict__ nodes, GridDev gd, EvDesc ev,
+                                                       const T* __restrict__ volt, double zen, double az, int64_t fs,
+                                                       double fallback_rel, double singular_rel,
+                                                       T* __restrict__ efield, const C2<T>* __restrict__ tw,
+                                                       unsigned long long* __restrict__ counts)
+{
+    constexpr int E = 8, RMAX = 8, TT = N / E, PF = 2;
+    static_assert(TT >= 256, "one transform per workgroup");
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ C2<T> sl[kMaxSliceNodes][4];
+    __shared__ unsigned int cnt[2];
+    const int t = threadIdx.x, s = blockIdx.x;
+    C2<T>* la = reinterpret_cast<C2<T>*>(smem);
+    C2<T>* lb = la + lds_elems<N>();
+    C2<T>* ltw = lb + lds_elems<N>();
+    C2<T> w[tw_count<N, E, RMAX, TW_LF>()];
+    load_twiddles<T, N, E, RMAX, TW_LF, +1>(w, tw, t);
+    fill_lds_twiddles<T, N, E, RMAX, +1, TW_LF>(ltw, tw, t, TT);
+    if (t == 0) zero_slot_clear<T, N>(smem, 0);
+    if (t < 2) cnt[t] = 0;
+    // the direction's angular slice at the frequency nodes the band spans
+    int iz, ia, ja;
+    double tz, ta;
+    angle_cells(gd, zen, az, iz, tz, ia, ja, ta);
+    const unsigned nb = (unsigned)ev.nb, k_lo = (unsigned)ev.k_lo;
+    int f_lo = 0, n_nodes = 0;
+    if (nb > 0) {
+        int f_hi;
+        double tdummy;
+        freq_cell(gd, (int64_t)k_lo, N, fs, f_lo, tdummy);
+        freq_cell(gd, (int64_t)(k_lo + nb - 1), N, fs, f_hi, tdummy);
+        n_nodes = f_hi - f_lo + 2;
+    }
+    for (int i = t; i < n_nodes; i += TT) slice4<Tt, T>(nodes, gd, f_lo + i, iz, (T)tz, ia, ja, (T)ta, sl[i]);
+    // the station's traces: forward transform conj(F+(conj z)), z = V_0 + i V_1
+    const T* __restrict__ V = volt + ev.volt_off + (int64_t)s * 2 * N;
+    C2<T> x[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) x[i] = C2<T>{V[t + TT * i], V[N + t + TT * i]};
+    vmem_wait_all();
+    lds_barrier();  // twiddle table, zero slot, slice and counters written
+    fft_pp<T, N, E, -1, TW_LF, RMAX, false>(x, lb, la, tw, t, w, ltw);
+    // in-band split of this thread's bins through la (gathered last before
+    // the transform's final exchange): X_0 = (Z[k] + conj Z[N-k]) / 2,
+    // X_1 = (Z[k] - conj Z[N-k]) / 2i
+#pragma unroll
+    for (int i = 0; i < E; ++i) la[lpad<T>(t + TT * i)] = x[i];
+    lds_barrier();
+    XBin<T> px[PF];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const unsigned j = (unsigned)(t + TT * q);
+        const unsigned k = k_lo + j;
+        const C2<T> za = la[j < nb ? lpad<T>(k) : lds_pad_slot<N>()];
+        const C2<T> zb = la[(j < nb && k != 0) ? lpad<T>(N - k) : lds_pad_slot<N>()];
+        px[q].x0 = C2<T>{(T)0.5 * (za.re + zb.re), (T)0.5 * (za.im - zb.im)};
+        px[q].x1 = C2<T>{(T)0.5 * (za.im + zb.im), (T)0.5 * (zb.re - za.re)};
+    }
+    lds_barrier();  // every split read done before the staging writes la
+    // the coefficients of this thread's bins, the packed solve, the staging
+    const T inv_n = (T)(1.0 / (double)N);
+    unsigned int n_fb = 0, n_sg = 0;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const unsigned j = t + TT * q;
+        const unsigned k = k_lo + j;
+        const bool ok = j < nb;
+        MBin<T> m{};
+        if (ok) {
+            int ifr;
+            double tf;
+            freq_cell(gd, (int64_t)k, N, fs, ifr, tf);
+            const int li = ifr - f_lo;
+            C2<T> h[4];
+#pragma unroll
+            for (int cp = 0; cp < 4; ++cp) h[cp] = clerp(sl[li][cp], sl[li + 1][cp], (T)tf);
+            m = coef_from_h<T>(h, N, inv_n, fallback_rel, singular_rel, n_fb, n_sg);
+        }
+        C2<T> zp, zq;
+        packed_bin(m, px[q], zp, zq);
+        la[ok ? lpad<T>(k) : lds_pad_slot<N>()] = zp;
+        la[(ok && k != 0) ? lpad<T>(N - k) : lds_pad_slot<N>()] = C2<T>{zq.re, -zq.im};
+        if (q == 0 && k_lo == 0u && ok && k == 0) la[0] = packed_dc(zp, zq);
+    }
+    if (s == 0 && counts != nullptr) {
+        if (n_fb) atomicAdd(&cnt[0], n_fb);
+        if (n_sg) atomicAdd(&cnt[1], n_sg);
+    }
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const unsigned k = t + TT * i;
+        const unsigned kk = (k <= N / 2) ? k : N - k;
+        x[i] = la[(kk - k_lo) < nb ? lpad<T>(k) : lds_zero_slot<N>()];
+    }
+    fft_pp<T, N, E, +1, TW_LF, RMAX, false>(x, lb, la, tw, t, w, ltw);
+    const __amdgpu_buffer_rsrc_t r = buffer_range(efield + ev.efield_off + (int64_t)s * 2 * N, 2 * N * (unsigned)sizeof(T));
+    const unsigned toff = (unsigned)t * (unsigned)sizeof(T);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        buffer_store_nt(x[i].re, r, toff, (int)(TT * i * sizeof(T)));
+        buffer_store_nt(x[i].im, r, toff, (int)((N + TT * i) * sizeof(T)));
+    }
+    if (s == 0 && counts != nullptr && t < 2 && cnt[t]) atomicAdd(&counts[t], (unsigned long long)cnt[t]);
 }
 
 // Shape of the envelope kernel.  FP32, and FP64 at 8 values per thread: the
@@ -2108,6 +2244,56 @@ static int scan_blocks(int prec, int n, int variant, int device)
     return b;
 }
 
+// The frequency node below bin k (freq_cell's quotient, exact on the host).
+static int64_t host_freq_node(const GridDev& g, int64_t k, int n, int64_t fs)
+{
+    const int64_t q = (k * fs - g.f0_hz * (int64_t)n) / ((int64_t)n * g.df_hz);
+    return std::min<int64_t>(q, g.n_freq - 2);
+}
+
+// The single-direction call in one launch (k_event_fused), where it applies:
+// 2048 or 4096 samples, traces and table in the compute precision, a band of
+// at most 2 N/8 bins spanning at most kMaxSliceNodes frequency nodes.
+// Returns false (nothing enqueued) where it does not apply.
+template <typename T>
+static bool event_fused(const au_table* tb, const au_event* ev, const EvParams& p, const void* d_volt, double zen,
+                        double az, void* d_efield, hipStream_t st, uint64_t* d_counts, au_status* rc)
+{
+    constexpr int tcode = sizeof(T) == 8 ? AU_F64 : AU_F32;
+    if ((p.N != 2048 && p.N != 4096) || ev->trace_dtype != tcode || tb->dtype != tcode || p.S < 1)
+        return false;
+    if (p.nb > 2 * (p.N / 8)) return false;
+    if (p.nb > 0) {
+        const int64_t f_lo = host_freq_node(tb->g, p.k_lo, p.N, ev->fs_hz);
+        const int64_t f_hi = host_freq_node(tb->g, (int64_t)p.k_lo + p.nb - 1, p.N, ev->fs_hz);
+        if (f_lo < 0 || f_hi - f_lo + 2 > kMaxSliceNodes) return false;
+    }
+    const C2<T>* tw = twiddles<T>(tb->device);
+    if (tw == nullptr) {
+        *rc = fail(AU_EDEVICE, "twiddle tables missing on this device");
+        return true;
+    }
+    EvDesc ev0{};
+    ev0.S = p.S;
+    ev0.N = p.N;
+    ev0.D = 1;
+    ev0.k_lo = p.k_lo;
+    ev0.nb = p.nb;
+#define EVF_(NN)                                                                                                 \
+    hipLaunchKernelGGL((k_event_fused<T, T, NN>), dim3(p.S), dim3(NN / 8),                                       \
+                       (2 * lds_elems<NN>() + ltw_count<NN, 8, 8, TW_LF>()) * sizeof(C2<T>), st,                  \
+                       (const C2<T>*)tb->d_nodes, tb->g, ev0, (const T*)d_volt, zen, az, ev->fs_hz,               \
+                       ev->fallback_rel, ev->singular_rel, (T*)d_efield, tw, (unsigned long long*)d_counts)
+    if (p.N == 2048)
+        EVF_(2048);
+    else
+        EVF_(4096);
+#undef EVF_
+    const hipError_t e = hipGetLastError();
+    *rc = e == hipSuccess ? AU_OK : fail(AU_EDEVICE, std::string("k_event_fused: ") + hipGetErrorString(e));
+    return true;
+}
+
 // Directions come from h_dirs (copied into the workspace's direction slot
 // first), from d_dirs (already in that slot, device memory), or, with both
 // null, the one direction (zen, az).
@@ -2181,6 +2367,15 @@ static au_status unfold_common(const au_table* tb, const au_event* ev, const voi
     hipStream_t st = (hipStream_t)stream;
     void* work = d_work;
     bool pooled = false;
+    if (work != nullptr && work_bytes < w.total) return fail(AU_ENOMEM, "workspace smaller than au_workspace_bytes");
+    // one direction given by value: one launch (k_event_fused) where it applies
+    if (h_dirs == nullptr && n_dir == 1) {
+        au_status rc = AU_OK;
+        const bool done = ev->prec == AU_PREC_FP64
+                              ? event_fused<double>(tb, ev, p, d_volt, zen, az, d_efield, st, d_counts, &rc)
+                              : event_fused<float>(tb, ev, p, d_volt, zen, az, d_efield, st, d_counts, &rc);
+        if (done) return rc;
+    }
     if (work == nullptr) {
         hipError_t e = hipMallocAsync(&work, w.total, st);
         if (e != hipSuccess) return fail(AU_ENOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));

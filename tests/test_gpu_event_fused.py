@@ -1,0 +1,127 @@
+"""The single-direction call in one launch (au_unfold_event at 2048 and 4096
+samples, traces and table in the compute precision, bands of at most N/4 bins:
+k_event_fused) against the general three-launch path (a direction scan of the
+same one direction) and against the oracle: the same operations (forward
+transform and split, the direction's coefficients, the packed solve and the
+inverse transform), so FP64 agrees to rounding and FP32 per station within
+1e-6; the same fallback and singular counts; every station of events of 1 to
+124 stations; bands that include DC, that are empty, and wider than N/4 bins
+(which keeps the general path)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1507_07733_amd import synth as S
+
+from helpers import TOL_FP32, TOL_FP64, assert_fp32_close, assert_traces_close, station_errors
+
+pytestmark = pytest.mark.gpu
+
+G = S.GRID_COARSE
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    from paper_1507_07733_amd import api as A
+    A.lib()
+    torch.cuda.init()
+    return A
+
+
+@pytest.fixture(scope="module")
+def tables(api):
+    t = S.pattern_table(G, cfg=1)
+    t32 = t.astype(np.complex64)
+    return {"fp64": (t, api.Table(G, t)), "fp32": (t32, api.Table(G, t32))}
+
+
+def both_paths(api, tab, ev, v, zen, az):
+    import torch
+    dv = torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    c1 = torch.zeros(2, dtype=torch.int64, device="cuda")
+    c3 = torch.zeros(2, dtype=torch.int64, device="cuda")
+    one = api.unfold_event(tab, ev, dv, zen, az, counts=c1)
+    three = api.unfold_direction_scan(tab, ev, dv, np.array([[zen, az]]), counts=c3)
+    torch.cuda.synchronize()
+    return one.cpu().numpy(), three.cpu().numpy()[0], c1.cpu().tolist(), c3.cpu().tolist()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,s", [(2048, 1), (2048, 10), (4096, 7), (4096, 124)])
+def test_one_launch_equals_three(api, tables, prec, n, s):
+    t, tab = tables[prec]
+    p = api.AU_PREC_FP64 if prec == "fp64" else api.AU_PREC_FP32
+    dt = np.float64 if prec == "fp64" else np.float32
+    ev = api.make_event(s, n, prec=p, trace_dtype=api.AU_F64 if prec == "fp64" else api.AU_F32)
+    v = S.traces(s, n, cfg=1, event=700 + s, dtype=dt)
+    zen, az = 37.5, 211.0
+    say("one launch", prec, "N", n, "S", s)
+    one, three, c1, c3 = both_paths(api, tab, ev, v, zen, az)
+    assert c1 == c3
+    if prec == "fp64":
+        scale = np.max(np.abs(three), axis=-1, keepdims=True)
+        assert np.max(np.abs(one - three) / np.maximum(scale, 1e-300)) <= 1e-13
+    else:
+        assert station_errors(one, three).max() <= 1e-6
+    stations = sorted({0, s // 2, s - 1})
+    units = np.array([[0, st] for st in stations])
+    ref, _, _ = O.unfold(G, t.astype(np.complex128), v.astype(np.float64), np.array([[zen, az]]), S.FS_HZ,
+                         S.BAND_LO_HZ, S.BAND_HI_HZ, units=units)
+    got = one[stations]
+    if prec == "fp64":
+        assert_traces_close(got, ref, TOL_FP64, "one launch")
+    else:
+        assert_fp32_close(got, ref, TOL_FP32, "one launch")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_one_launch_counts_near_the_horizon(api, tables, prec):
+    """At the horizon every in-band bin is singular (zero traces); counted once for the direction, not once
+    per station."""
+    t, tab = tables[prec]
+    p = api.AU_PREC_FP64 if prec == "fp64" else api.AU_PREC_FP32
+    dt = np.float64 if prec == "fp64" else np.float32
+    n, s = 2048, 6
+    ev = api.make_event(s, n, prec=p, trace_dtype=api.AU_F64 if prec == "fp64" else api.AU_F32)
+    v = S.traces(s, n, cfg=1, event=5, dtype=dt)
+    say("one launch horizon", prec)
+    one, three, c1, c3 = both_paths(api, tab, ev, v, 90.0, 10.0)
+    nb = api.band_bins(ev)[1]
+    assert c1 == c3 and c1[1] == nb
+    assert not np.any(one) and not np.any(three)
+
+
+@pytest.mark.parametrize("band", [(0, 40_000_000), (41_000_000, 41_010_000), (1_000_000, 99_000_000)],
+                         ids=["dc-40MHz", "empty", "wide"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_one_launch_band_edges(api, tables, prec, band):
+    t, tab = tables[prec]
+    lo, hi = band
+    p = api.AU_PREC_FP64 if prec == "fp64" else api.AU_PREC_FP32
+    dt = np.float64 if prec == "fp64" else np.float32
+    n, s = 4096, 5
+    ev = api.make_event(s, n, prec=p, trace_dtype=api.AU_F64 if prec == "fp64" else api.AU_F32, band_lo_hz=lo,
+                        band_hi_hz=hi)
+    v = S.traces(s, n, cfg=1, event=9, dtype=dt)
+    say("one launch band", band, prec)
+    one, three, c1, c3 = both_paths(api, tab, ev, v, 20.0, 45.0)
+    assert c1 == c3
+    if hi - lo < S.FS_HZ // n:
+        assert not np.any(one) and not np.any(three)
+        return
+    if prec == "fp64":
+        assert np.max(station_errors(one, three)) <= 1e-13
+    else:
+        assert station_errors(one, three).max() <= 1e-6
+    ref, _, _ = O.unfold(G, t.astype(np.complex128), v.astype(np.float64), np.array([[20.0, 45.0]]), S.FS_HZ, lo, hi,
+                         units=np.array([[0, 0], [0, s - 1]]))
+    got = one[[0, s - 1]]
+    if prec == "fp64":
+        assert_traces_close(got, ref, TOL_FP64, "band")
+    else:
+        assert_fp32_close(got, ref, TOL_FP32, "band")
