@@ -1090,7 +1090,7 @@ __global__ __launch_bounds__(N / 8) __attribute__((amdgpu_waves_per_eu(4))) void
                 const unsigned j = (unsigned)(t + TT * q);
                 const unsigned k = k_lo + j;
                 const C2<T> za = la[j < nb ? lpad<T>(k) : lds_pad_slot<N>()];
-                const C2<T> zb = la[(j < nb && k != 0) ? lpad<T>(N - k) : lds_pad_slot<N>()];
+                const C2<T> zb = la[j < nb ? lpad<T>((N - k) & (N - 1)) : lds_pad_slot<N>()];
                 px[q].x0 = C2<T>{(T)0.5 * (za.re + zb.re), (T)0.5 * (za.im - zb.im)};
                 px[q].x1 = C2<T>{(T)0.5 * (za.im + zb.im), (T)0.5 * (zb.re - za.re)};
             }
@@ -1219,7 +1219,7 @@ __global__ __launch_bounds__(N / 8) void k_event_fused(const C2<Tt>* __restrict_
         const unsigned j = (unsigned)(t + TT * q);
         const unsigned k = k_lo + j;
         const C2<T> za = la[j < nb ? lpad<T>(k) : lds_pad_slot<N>()];
-        const C2<T> zb = la[(j < nb && k != 0) ? lpad<T>(N - k) : lds_pad_slot<N>()];
+        const C2<T> zb = la[j < nb ? lpad<T>((N - k) & (N - 1)) : lds_pad_slot<N>()];
         px[q].x0 = C2<T>{(T)0.5 * (za.re + zb.re), (T)0.5 * (za.im - zb.im)};
         px[q].x1 = C2<T>{(T)0.5 * (za.im + zb.im), (T)0.5 * (zb.re - za.re)};
     }

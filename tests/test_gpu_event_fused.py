@@ -125,3 +125,35 @@ def test_one_launch_band_edges(api, tables, prec, band):
         assert_traces_close(got, ref, TOL_FP64, "band")
     else:
         assert_fp32_close(got, ref, TOL_FP32, "band")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_one_launch_dc_bin_carries_signal(api, prec, n):
+    """H = I passes the DC bin through (a pattern table's response vanishes at 0 Hz): traces with a
+    constant offset, a band from 0 Hz, one launch against three and the oracle."""
+    t = S.identity_table(G)
+    if prec == "fp32":
+        t = t.astype(np.complex64)
+    tab = api.Table(G, t)
+    p = api.AU_PREC_FP64 if prec == "fp64" else api.AU_PREC_FP32
+    dt = np.float64 if prec == "fp64" else np.float32
+    s = 4
+    ev = api.make_event(s, n, prec=p, trace_dtype=api.AU_F64 if prec == "fp64" else api.AU_F32, band_lo_hz=0,
+                        band_hi_hz=40_000_000)
+    v = (S.traces(s, n, cfg=1, event=11, dtype=dt) + dt(2.5)).astype(dt)
+    say("one launch, identity table, band from DC", prec, "N", n)
+    one, three, c1, c3 = both_paths(api, tab, ev, v, 25.0, 100.0)
+    assert c1 == c3
+    assert np.abs(three.mean(axis=-1)).min() > 1.0
+    if prec == "fp64":
+        assert np.max(station_errors(one, three)) <= 1e-13
+    else:
+        assert station_errors(one, three).max() <= 1e-6
+    ref, _, _ = O.unfold(G, t.astype(np.complex128), v.astype(np.float64), np.array([[25.0, 100.0]]), S.FS_HZ, 0,
+                         40_000_000, units=np.array([[0, 0], [0, s - 1]]))
+    got = one[[0, s - 1]]
+    if prec == "fp64":
+        assert_traces_close(got, ref, TOL_FP64, "dc")
+    else:
+        assert_fp32_close(got, ref, TOL_FP32, "dc")

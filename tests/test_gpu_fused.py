@@ -141,3 +141,38 @@ def test_fused_plan_band_edges(api, fine32, band):
                              S.FS_HZ, lo, hi, units=units)
         got = np.stack([a[di, si] for di, si in units])
         assert_fp32_close(got, ref, TOL_FP32, "fused band %s event %d" % (band, e))
+
+
+def test_fused_plan_dc_bin_carries_signal(api):
+    """With H = I at every node the DC bin passes through (a pattern table's response vanishes at 0 Hz,
+    which would hide a wrong DC bin): traces with a constant offset, a band from 0 Hz, fused against
+    separate stages and the oracle."""
+    import torch
+    g = S.GRID_COARSE
+    t = S.identity_table(g).astype(np.complex64)
+    tab = api.Table(g, t)
+    specs = [(6, 4096, S.direction_grid(2, 2)), (3, 2048, [[30.0, 60.0]])]
+    vs = [S.traces(s, n, cfg=2, event=150 + e, dtype=np.float32) + np.float32(3.0 + e)
+          for e, (s, n, _) in enumerate(specs)]
+    say("fused plan, identity table, band from DC")
+    outs = []
+    for flags in (7, 7 | api.AU_PLAN_FUSED):
+        plan = api.Plan(tab, specs, prec=api.AU_PREC_FP32, trace_dtype=api.AU_F32, flags=flags, band_lo_hz=0,
+                        band_hi_hz=40_000_000)
+        volt = np.zeros(plan.volt_elems, dtype=np.float32)
+        for e, v in enumerate(vs):
+            volt[plan.volt_offsets[e]:plan.volt_offsets[e] + v.size] = v.ravel()
+        out = torch.full((plan.efield_elems,), float("nan"), dtype=torch.float32, device="cuda")
+        plan.run(torch.from_numpy(volt).cuda(), out)
+        torch.cuda.synchronize()
+        outs.append((plan, out))
+    (p0, o0), (p1, o1) = outs
+    for e, (s, n, d) in enumerate(specs):
+        a = p1.event_output(o1, e).cpu().numpy()
+        b = p0.event_output(o0, e).cpu().numpy()
+        assert np.abs(b.mean(axis=-1)).min() > 1.0          # the offset reaches the field
+        assert station_errors(a, b).max() <= 1e-6, e
+        ref, _, _ = O.unfold(g, t.astype(np.complex128), vs[e].astype(np.float64), np.asarray(d, dtype=np.float64),
+                             S.FS_HZ, 0, 40_000_000, units=np.array([[0, 0], [len(d) - 1, s - 1]]))
+        got = np.stack([a[0, 0], a[len(d) - 1, s - 1]])
+        assert_fp32_close(got, ref, TOL_FP32, "fused dc event %d" % e)
