@@ -285,6 +285,10 @@ def test_workspace_argument_and_errors(api, coarse):
     with pytest.raises(api.AuError) as ei:
         api.workspace_bytes(tab, bad, 1)
     assert ei.value.status == api.AU_EINVAL
+    nyq = api.make_event(4, 2048, band_lo_hz=60_000_000, band_hi_hz=S.FS_HZ // 2)
+    with pytest.raises(api.AuError) as ei:
+        api.workspace_bytes(tab, nyq, 1)         # the Nyquist bin never enters a band
+    assert ei.value.status == api.AU_EINVAL
     ev32 = api.make_event(4, 2048, prec=api.AU_PREC_FP64)
     t32 = api.Table(G, t.astype(np.complex64))
     with pytest.raises(api.AuError):
@@ -313,6 +317,50 @@ def test_every_unfold_variant(api, coarse, n, prec):
             say("variant", vi, "E", e, "rmax", rmax, "twmode", twmode, "wave", wave, "pair", pair, "pp", pp, prec, "N", n)
             out = api.unfold_direction_scan(tab, ev, to_dev(v), dirs).cpu().numpy()
             assert_close(out, ref, prec == "fp32", "variant %d" % vi)
+    finally:
+        api.set_unfold_variant(p, n, keep)
+    assert built >= 4
+
+
+# (name, lo_hz, hi_hz, table): a band from DC with the identity table and offset traces (the DC bin
+# carries signal), one wider than two bins per thread at 4 096 samples, one bin, and a band narrower
+# than the threads of a transform (most threads hold no bin)
+VARIANT_BANDS = [("dc", 0, 40_000_000, "identity"), ("wide", 1_000_000, 99_000_000, "pattern"),
+                 ("one_bin", 50_000_000, 50_000_000, "pattern"), ("narrow", 61_000_000, 64_000_000, "pattern")]
+
+
+@pytest.mark.parametrize("band", VARIANT_BANDS, ids=[b[0] for b in VARIANT_BANDS])
+@pytest.mark.parametrize("n", [2048, 4096])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_every_unfold_variant_band_edges(api, coarse, identity, band, n, prec):
+    """Every built shape on bands where the bins a thread solves change: the paired-lane shapes
+    place bin k in register k / TT of thread k mod TT and its mirror in the partner lane."""
+    name, lo, hi, table = band
+    t, tab = identity if table == "identity" else coarse
+    p = api.AU_PREC_FP64 if prec == "fp64" else api.AU_PREC_FP32
+    dt = np.float64 if prec == "fp64" else np.float32
+    s = 3
+    v = S.traces(s, n, cfg=3, event=n + 1, dtype=dt)
+    if name == "dc":
+        v = (v + dt(2.5)).astype(dt)
+    dirs = np.array([[40.0, 120.0], [5.0, 3.0]])
+    ev = api.make_event(s, n, prec=p, trace_dtype=api.AU_F64 if prec == "fp64" else api.AU_F32, band_lo_hz=lo,
+                        band_hi_hz=hi)
+    ref, _, _ = O.unfold(G, np.asarray(t).astype(np.complex128), v.astype(np.float64), dirs, S.FS_HZ, lo, hi)
+    if name == "dc":
+        assert np.abs(ref.mean(axis=-1)).min() > 1.0
+    keep = api.get_unfold_variant(p, n)
+    built = 0
+    try:
+        for vi, (e, rmax, twmode, wave, pair, pp) in enumerate(api.unfold_variants()):
+            try:
+                api.set_unfold_variant(p, n, vi)
+            except api.AuError:
+                continue
+            built += 1
+            say("variant", vi, "pair", pair, "pp", pp, "band", name, prec, "N", n)
+            out = api.unfold_direction_scan(tab, ev, to_dev(v), dirs).cpu().numpy()
+            assert_close(out, ref, prec == "fp32", "variant %d band %s" % (vi, name))
     finally:
         api.set_unfold_variant(p, n, keep)
     assert built >= 4
