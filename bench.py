@@ -299,11 +299,23 @@ def alu_view(cls):
             "flops_per_unit": flops, "convention": "5 N log2 N per complex FFT + 28 flops per in-band bin"}
 
 
+def settle(fn, seconds=0.25):
+    """Call fn back to back for about `seconds`: an idle GPU lowers its clocks and needs tens of
+    milliseconds of load to return to its steady state (the 124-station FP64 scan takes 4.3-4.6 ms
+    per call after a 50 ms pause, 3.5-3.6 ms back to back), so a timed section starts after this."""
+    import torch
+    t0 = time.perf_counter()
+    while True:
+        fn()
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= seconds:
+            return
+
+
 def envelope_scan_rate(api, tab, ev, volt, dirs, work, reps, stream):
     """Station-unfolds/s of au_unfold_envelope_scan (peaks and their samples only, no traces)."""
     import torch
-    api.unfold_envelope_scan(tab, ev, volt, dirs, work=work)
-    torch.cuda.synchronize()
+    settle(lambda: api.unfold_envelope_scan(tab, ev, volt, dirs, work=work))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
@@ -845,9 +857,8 @@ def main():
         del efield
         torch.cuda.empty_cache()
         out1 = torch.empty((len(dirs1), s1, 2, n1), dtype=torch.float64, device=dev)
-        api.unfold_direction_scan(t1, ev, v1, dirs1, out=out1, work=work)
-        torch.cuda.synchronize()
-        k1 = max(2, args.steps // 3)
+        settle(lambda: api.unfold_direction_scan(t1, ev, v1, dirs1, out=out1, work=work))
+        k1 = max(10, args.steps)
         ev0.record(stream)
         for _ in range(k1):
             api.unfold_direction_scan(t1, ev, v1, dirs1, out=out1, work=work)
