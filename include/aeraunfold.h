@@ -517,7 +517,10 @@ au_status au_server_stats(au_server* server, au_server_counters* stats);
  * twiddles live (0 table, 1 registers, 2 registers times compile-time
  * constants, 3 an LDS table for the early passes and registers for the
  * rest, 4 as 3 with (tangent, cosine) pairs for fused multiply-add
- * butterflies), wave = 1 if a single wavefront
+ * butterflies, 5 the pairs of 4 for every pass in registers, 6 as 5 in the
+ * 4096-point double-precision transform whose first two exchanges stay
+ * inside the wavefront: one through the wavefront's own LDS slots, one as a
+ * register transpose with DPP and lane-swap moves), wave = 1 if a single wavefront
  * owns each transform (no workgroup barriers), pair = 1 if lanes L and L^32
  * hold mirror bins k and N-k so each in-band bin is solved once and its
  * mirror taken with a cross-lane swap, pp = 1 if each transform alternates

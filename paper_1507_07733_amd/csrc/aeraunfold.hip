@@ -587,7 +587,17 @@ __device__ __forceinline__ void touch(const C2<T>& v)
 
 // One in-band bin of the packed spectrum: Z[k] = E_theta + i E_phi and
 // Z[N-k] = conj E_theta + i conj E_phi (only the real parts at k = 0).
-template <typename T, int N>
+// (XW: in the digit-reversed slots of the 4096-point in-wave transform)
+template <typename T, int N, bool XW = false>
+__device__ __forceinline__ int stage_slot(unsigned k)
+{
+    if constexpr (XW)
+        return xw_slot(xw_pos((int)k));
+    else
+        return lpad<T>((int)k);
+}
+
+template <typename T, int N, bool XW = false>
 __device__ __forceinline__ void stage_bin(C2<T>* __restrict__ lds, unsigned k, const MBin<T>& m, const XBin<T>& xb)
 {
     C2<T> zp, zq;
@@ -595,8 +605,8 @@ __device__ __forceinline__ void stage_bin(C2<T>* __restrict__ lds, unsigned k, c
     if (k == 0) {
         lds[0] = packed_dc(zp, zq);
     } else {
-        lds[lpad<T>(k)] = zp;
-        lds[lpad<T>(N - k)] = C2<T>{zq.re, -zq.im};
+        lds[stage_slot<T, N, XW>(k)] = zp;
+        lds[stage_slot<T, N, XW>(N - k)] = C2<T>{zq.re, -zq.im};
     }
 }
 
@@ -644,7 +654,14 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
     // early twiddles live in LDS have the registers for it; in FP64 the
     // two-buffer shape, at two waves per SIMD (one workgroup per CU, which
     // its LDS allows anyway)
-    constexpr int PF = ((tw_lds_early(TWMODE) || TWMODE == TW_LFR) && E <= 8 && !PAIR && !WAVE && (sizeof(T) == 4 || PP)) ? AU_UNFOLD_PF : 0;
+    constexpr int PF = ((tw_lds_early(TWMODE) || TWMODE == TW_LFR || TWMODE == TW_LFW) && E <= 8 && !PAIR && !WAVE &&
+                        (sizeof(T) == 4 || PP)) ? AU_UNFOLD_PF : 0;
+    // the 4096-point transform with in-wavefront exchanges: the staging
+    // writes the digit-reversed order it reads, the first buffer holds the
+    // staging and the second its one exchange
+    constexpr bool XW = TWMODE == TW_LFW;
+    static_assert(!XW || (N == 4096 && E == 8 && RMAX == 8 && PP && !PAIR && !WAVE && G == 1 && PF > 0),
+                  "in-wave exchanges: the 4096-point shape only");
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sh_u;
     __shared__ int sh_list;
@@ -812,7 +829,7 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
                     // bins) are loaded here; the loop is skipped uniformly
                     // otherwise.
                     if (nb > (unsigned)(PF * TT) && (G == 1 || active))
-                        for (unsigned j = t + TT * PF; j < nb; j += TT) stage_bin<T, N>(lds, k_lo + j, Md[j], Xs[j]);
+                        for (unsigned j = t + TT * PF; j < nb; j += TT) stage_bin<T, N, XW>(lds, k_lo + j, Md[j], Xs[j]);
                     // The first PF bins of this thread were loaded ahead (at
                     // the unit's start, or before the previous station's
                     // stores).  Branch-free: every lane computes them, and a
@@ -826,8 +843,8 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
                         const bool ok = (G == 1 || active) && j < nb;
                         C2<T> zp, zq;
                         packed_bin(pm[q], px[q], zp, zq);
-                        lds[ok ? lpad<T>(k) : lds_pad_slot<N>()] = zp;
-                        lds[(ok && k != 0) ? lpad<T>(N - k) : lds_pad_slot<N>()] = C2<T>{zq.re, -zq.im};
+                        lds[ok ? stage_slot<T, N, XW>(k) : lds_pad_slot<N>()] = zp;
+                        lds[(ok && k != 0) ? stage_slot<T, N, XW>(N - k) : lds_pad_slot<N>()] = C2<T>{zq.re, -zq.im};
                         // a band that includes DC (a uniform test, skipped
                         // otherwise): bin 0 keeps real parts only
                         if (q == 0 && k_lo == 0u && ok && k == 0) lds[0] = packed_dc(zp, zq);
@@ -839,20 +856,30 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
                 lds_sync<WAVE>();
 #pragma unroll
                 for (int i = 0; i < E; ++i) {
-                    const unsigned k = t + TT * i;
+                    // position t + TT i holds element k (XW: digit-reversed)
+                    const unsigned q = t + TT * i;
+                    const unsigned k = XW ? (unsigned)xw_pos((int)q) : q;
                     const unsigned kk = (k <= N / 2) ? k : N - k;
                     const bool inb = active && (kk - k_lo) < nb;
                     // with the prefetch the registers are short: a zero slot
                     // in place of a per-bin select (the compiler keeps the
                     // eight addresses for the unit)
-                    if constexpr (PF > 0)
+                    if constexpr (XW)
+                        x[i] = lds[inb ? xw_slot((int)q) : lds_zero_slot<N>()];
+                    else if constexpr (PF > 0)
                         x[i] = lds[inb ? lpad<T>(k) : lds_zero_slot<N>()];
                     else
                         x[i] = inb ? lds[lpad<T>(k)] : C2<T>{0, 0};
                 }
                 if constexpr (!PP) lds_sync<WAVE>();
             }
-            if constexpr (PP) {
+            if constexpr (XW) {
+                // staging (and the wavefront-local exchange) in lds, the
+                // workgroup exchange in lds2: the next station's staging
+                // writes lds after this station's exchange barrier, which
+                // every thread passes after its last access to lds
+                fft4096_xw<T, +1>(x, lds, lds2, w, t);
+            } else if constexpr (PP) {
                 fft_pp<T, N, E, +1, TWMODE, RMAX, WAVE>(x, lds2, lds, tw, t, w, ltw);
                 // exchanges this station: the staging one (lds, unless PAIR)
                 // plus one per pass boundary, alternating from lds2; make the
@@ -1613,9 +1640,9 @@ constexpr UnfoldVariant kUnfoldVariants[] = {
     {8, 8, TW_REG, false, false, true},    {16, 16, TW_REG, false, false, true},
     {8, 8, TW_HYB, false, false, true},    {8, 8, TW_HYB, false, false, false},
     {8, 8, TW_LF, false, false, true},     {8, 8, TW_LF, false, false, false},
-    {8, 8, TW_LFR, false, false, true},
+    {8, 8, TW_LFR, false, false, true},    {8, 8, TW_LFW, false, false, true},
 };
-constexpr int kNumVariants = 17;
+constexpr int kNumVariants = 18;
 
 // LDS one workgroup may allocate on gfx950 (the whole 160 KiB of a CU).
 constexpr int kMaxLdsPerBlock = 163840;
@@ -1639,6 +1666,9 @@ constexpr bool variant_built(int n, int v, int tsize)
     // every pass's twiddle pairs in registers: FP64 (one workgroup per CU,
     // registers to spare); FP32 shapes need them for four waves per SIMD
     if (kUnfoldVariants[v].twmode == TW_LFR && tsize != 8) return false;
+    // the in-wavefront exchanges exist for the 4096-point transform only, in
+    // FP64 (the FP32 shape would spill at four waves per SIMD)
+    if (kUnfoldVariants[v].twmode == TW_LFW && (n != 4096 || tsize != 8)) return false;
     return true;
 }
 
@@ -1672,10 +1702,11 @@ static int ilog2(int n)
 // buffers and the next station's bins prefetched: for float the fused
 // multiply-add butterflies with the early passes' twiddle pairs in LDS, for
 // double at 4096 samples the same butterflies with every pass's pairs in
-// registers, at 2048 the hybrid table, at 1024 register twiddles; below,
-// E=16 with register twiddles for float and table twiddles for double).
+// registers and two of the three exchanges inside the wavefront, at 2048
+// the hybrid table, at 1024 register twiddles; below, E=16 with register
+// twiddles for float and table twiddles for double).
 static std::mutex g_var_mu;
-static int g_variant[2][13] = {{1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10, 12, 16},
+static int g_variant[2][13] = {{1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 10, 12, 17},
                                {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 12, 14, 14}};
 
 static int unfold_variant(int prec, int n)
@@ -1830,7 +1861,7 @@ static hipError_t launch_unfold_n(int v, hipStream_t st, const EvDesc& ev0, cons
 #define V_(VV) \
     case VV: return launch_unfold_nv<T, N, VV>(st, ev0, evs, units, n_units, spw, X, M, efield, tw, counter, persistent_blocks, xcd_off, xcd_max_list);
         V_(0) V_(1) V_(2) V_(3) V_(4) V_(5) V_(6) V_(7) V_(8) V_(9) V_(10) V_(11) V_(12) V_(13) V_(14) V_(15)
-        V_(16)
+        V_(16) V_(17)
 #undef V_
     }
     return hipErrorInvalidValue;
@@ -1909,6 +1940,7 @@ static int persistent_blocks_for(int n, int v, int device)
             case 14: per_cu = occupancy_nv<T, NN, 14>(); break;                                 \
             case 15: per_cu = occupancy_nv<T, NN, 15>(); break;                                 \
             case 16: per_cu = occupancy_nv<T, NN, 16>(); break;                                 \
+            case 17: per_cu = occupancy_nv<T, NN, 17>(); break;                                 \
         }                                                                                       \
         break;
         AU_FOR_EACH_N(X_)

@@ -345,12 +345,19 @@ constexpr int lds_zero_slot() { return N + 1; }
 //   TW_LFR:   the TW_LF pairs of every pass in registers (no LDS table
 //             reads: for shapes with registers to spare whose transform is
 //             bound by LDS bandwidth, as FP64 at one workgroup per CU).
-enum { TW_TABLE = 0, TW_REG = 1, TW_SPLIT = 2, TW_HYB = 3, TW_LF = 4, TW_LFR = 5 };
+//   TW_LFW:   TW_LFR's twiddles and butterflies in the 4096-point
+//             transform whose first two exchanges stay inside the
+//             wavefront (fft4096_xw): one through the wavefront's own LDS
+//             slots with no workgroup barrier, one as a register transpose;
+//             one workgroup exchange per transform instead of three.
+enum { TW_TABLE = 0, TW_REG = 1, TW_SPLIT = 2, TW_HYB = 3, TW_LF = 4, TW_LFR = 5, TW_LFW = 6 };
 
 // Twiddles of the early passes in a per-workgroup LDS table.
 constexpr bool tw_lds_early(int mode) { return mode == TW_HYB || mode == TW_LF; }
 // Fused multiply-add butterflies with (tangent, cosine) twiddle pairs.
-constexpr bool tw_lf(int mode) { return mode == TW_LF || mode == TW_LFR; }
+constexpr bool tw_lf(int mode) { return mode == TW_LF || mode == TW_LFR || mode == TW_LFW; }
+// Every pass's twiddles in registers.
+constexpr bool tw_all_reg(int mode) { return mode == TW_REG || mode == TW_LFR || mode == TW_LFW; }
 // (tangent, cosine) pairs per butterfly of a radix-R pass in TW_LF / TW_LFR.
 constexpr int lf_entries(int r) { return r == 8 ? 4 : (r == 4 ? 2 : 1); }
 // Twiddle entries per butterfly of a radix-R pass.
@@ -367,7 +374,7 @@ constexpr int tw_offset(int ns_target)
         if (ns == 1) continue;
         const int r = pass_radix<N, RMAX>(ns);
         if (tw_lds_early(TWMODE) && ns < N / E) continue;
-        off += (TWMODE == TW_REG || TWMODE == TW_LFR || tw_lds_early(TWMODE)) ? (E / r) * tw_per(TWMODE, r) : (r - 1);
+        off += (tw_all_reg(TWMODE) || tw_lds_early(TWMODE)) ? (E / r) * tw_per(TWMODE, r) : (r - 1);
     }
     return off;
 }
@@ -845,6 +852,161 @@ __device__ __forceinline__ void fft_pp(C2<T> (&x)[E], C2<T>* __restrict__ la, C2
 {
     static_assert((N & (N - 1)) == 0 && N >= E && (E & (E - 1)) == 0 && RMAX <= 32, "sizes");
     fft_pass_pp<T, N, E, (RMAX < E ? RMAX : E), TWMODE, WAVE, 1, SIGN>(x, la, lb, tw, w, t, ltw);
+}
+
+// ---------------------------------------------------------------------------
+// The 4096-point transform with two of its three exchanges inside the
+// wavefront (TW_LFW, 8 values per thread, 512 threads t = 64 w + l, wave w,
+// lane l = 8 lh + ll).  Positions p = 512 p3 + 64 p2 + 8 p1 + p0 in base-8
+// digits; the input is loaded digit-reversed (position p holds element
+// 512 p0 + 64 p1 + 8 p2 + p3), and four decimation-in-time radix-8 passes
+// combine along p0, p1, p2, p3 in turn, leaving the output in natural order.
+// Pass s multiplies input r by exp(SIGN 2 pi i r k / 8^s), k the number
+// formed by the digits below the one it combines, and runs the 8-point DFT:
+// with the layouts below k = t mod 8^(s-1), the factor of Stockham pass
+// NS = 8^(s-1) for thread t, so the TW_LFR registers serve unchanged.
+// Register index r holds the digit a pass combines; the other digits sit in
+// the thread index:
+//   pass 1: r = p0, w = p3, lh = p2, ll = p1
+//   pass 2: r = p1, w = p3, lh = p2, ll = p0   (r <-> ll: the wavefront's LDS)
+//   pass 3: r = p2, w = p3, lh = p1, ll = p0   (r <-> lh: register transpose)
+//   pass 4: r = p3, w = p2, lh = p1, ll = p0   (r <-> w: workgroup exchange)
+// so the output is x[r] = X[t + 512 r], as after the Stockham passes.  The
+// register transpose of lane bits 3-5 costs one VALU move per 32-bit word
+// and bit; lane bits 0-2 would take two (a DPP move and a select, or two
+// DPP moves), so that transpose goes through LDS, where a wavefront needs
+// no barrier.
+
+// Slot of position q in the LDS buffers of fft4096_xw: an XOR of bits 0-2
+// with bits 6-8 (a permutation of each aligned block of 8 positions), which
+// keeps the gathers and the exchange (64 consecutive positions per wave) and
+// the staging scatter (consecutive bins k to positions 64 (k mod 8) + ...)
+// free of bank conflicts for 8- and 16-byte elements.
+__device__ __forceinline__ constexpr int xw_slot(int q) { return q ^ ((q >> 6) & 7); }
+// The digit-reversed input order in base-8 digits 0 and 2 of a 4096-point
+// index (an involution): element e sits at the gather position xw_pos(e) of
+// the thread and register pass 1 takes it from, and position q holds element
+// xw_pos(q).
+__device__ __forceinline__ constexpr int xw_pos(int e)
+{
+    return (e & 0xE38) | ((e & 7) << 6) | ((e >> 6) & 7);
+}
+
+// One transpose step of a pair of 32-bit words held in registers r0 and
+// r1 = r0 + RB by every lane: lanes whose bit LB is clear take their
+// partner's (lane ^ LB) r0 word into r1, lanes whose bit is set take the
+// partner's r1 word into r0.  LB 16 and 32: the gfx950 lane-swap
+// instructions, which perform exactly this exchange between two registers.
+// LB 8: a DPP rotation by 8 within the row of 16 lanes (lane i's word to
+// lane i + 8 mod 16) that writes only the lanes taking a word (bank mask:
+// lanes 4 b .. 4 b + 3 form bank b of a row), the others keeping theirs.
+template <int LB>
+__device__ __forceinline__ void xw_swap_words(unsigned& a, unsigned& b)
+{
+    static_assert(LB == 8 || LB == 16 || LB == 32, "lane bits 3-5");
+    if constexpr (LB == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    } else if constexpr (LB == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    } else {
+        const unsigned b0 = b;
+        b = __builtin_amdgcn_update_dpp(b, a, 0x128, 0xF, 0x3, false);   // banks 0, 1 <- lane + 8
+        a = __builtin_amdgcn_update_dpp(a, b0, 0x128, 0xF, 0xC, false);  // banks 2, 3 <- lane - 8
+    }
+}
+
+template <int LB, typename T>
+__device__ __forceinline__ void xw_swap(C2<T>& x0, C2<T>& x1)
+{
+    struct Words {
+        unsigned v[sizeof(C2<T>) / 4];
+    };
+    Words a = __builtin_bit_cast(Words, x0), b = __builtin_bit_cast(Words, x1);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(C2<T>) / 4); ++i) xw_swap_words<LB>(a.v[i], b.v[i]);
+    x0 = __builtin_bit_cast(C2<T>, a);
+    x1 = __builtin_bit_cast(C2<T>, b);
+}
+
+// Transpose of the register index (bits 0-2) with lane bits 3-5: the value
+// of lane bits 3-5 = a in register b moves to lane bits 3-5 = b, register a.
+template <typename T>
+__device__ __forceinline__ void xw_transpose_hi(C2<T> (&x)[8])
+{
+#pragma unroll
+    for (int bit = 0; bit < 3; ++bit) {
+#pragma unroll
+        for (int r0 = 0; r0 < 8; ++r0) {
+            if ((r0 >> bit) & 1) continue;
+            if (bit == 0) xw_swap<8>(x[r0], x[r0 + 1]);
+            if (bit == 1) xw_swap<16>(x[r0], x[r0 + 2]);
+            if (bit == 2) xw_swap<32>(x[r0], x[r0 + 4]);
+        }
+    }
+}
+
+// One radix-8 pass in registers: inputs r times the pass-NS factors of the
+// thread (TW_LFR registers, none for NS = 1), then the 8-point DFT.
+template <typename T, int NS, int SIGN>
+__device__ __forceinline__ void xw_pass(C2<T> (&x)[8], const C2<T>* __restrict__ w)
+{
+    if constexpr (NS > 1) {
+        constexpr int LE = lf_entries(8);
+        constexpr int OFF = tw_offset<4096, 8, 8, TW_LFW>(NS);
+        C2<T> L[LE];
+#pragma unroll
+        for (int e = 0; e < LE; ++e) L[e] = lf_sign<SIGN>(w[OFF + e]);
+        lf_dft<8, SIGN>(x, L);
+    } else {
+        Dft<8, SIGN, T>::run(x);
+    }
+}
+
+// Slot of position q for the wavefront-local exchange of the low lane
+// digit: an XOR of bits 0-2 with bits 9-11, so that the transposed reads
+// (consecutive lanes 512 positions apart) fall in distinct banks.  It
+// permutes each aligned block of 8 positions, so a wavefront's gather
+// positions {t + 512 r} map onto themselves.
+__device__ __forceinline__ constexpr int xw_slot_lo(int q) { return q ^ ((q >> 9) & 7); }
+
+// x[r] holds position t + 512 r of the digit-reversed input (see above);
+// returns x[r] = output element t + 512 r.  `la` is a buffer of
+// lds_elems<4096>() slots that no other thread group uses; the caller must
+// not write it again before every thread has passed a barrier that follows
+// this call (it holds one exchange between a barrier and the gathers after
+// it).  The first transpose goes through `ls`, each wavefront in its own
+// gather positions {t + 512 r} of that buffer (the caller's staging buffer,
+// whose gathers this wavefront has issued before; a wavefront's LDS
+// operations complete in order), with no workgroup barrier.
+template <typename T, int SIGN>
+__device__ __forceinline__ void fft4096_xw(C2<T> (&x)[8], C2<T>* __restrict__ ls, C2<T>* __restrict__ la,
+                                           const C2<T>* __restrict__ w, int t)
+{
+    xw_pass<T, 1, SIGN>(x, w);
+    {
+        // register b of lane (lh, a) to position 512 b + 64 w + 8 lh + a;
+        // lane (lh, b) reads register a from there
+        const int base = t & ~7, ll = t & 7;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) ls[xw_slot_lo(512 * b + t)] = x[b];
+        lds_sync<true>();
+#pragma unroll
+        for (int a = 0; a < 8; ++a) x[a] = ls[xw_slot_lo(512 * ll + base + a)];
+    }
+    xw_pass<T, 8, SIGN>(x, w);
+    xw_transpose_hi(x);
+    xw_pass<T, 64, SIGN>(x, w);
+    const int wv = t >> 6, l = t & 63;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) la[xw_slot(512 * wv + 64 * r + l)] = x[r];
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] = la[xw_slot(512 * r + 64 * wv + l)];
+    xw_pass<T, 512, SIGN>(x, w);
 }
 
 // Full N-point transform of the group's sequence, exp(SIGN ...) kernel, no
