@@ -126,28 +126,24 @@ __device__ __forceinline__ C2<T> clerp(C2<T> a, C2<T> b, T t)
     return {s * a.re + t * b.re, s * a.im + t * b.im};
 }
 
-// The four (channel, component) entries at frequency node f, interpolated
-// along azimuth, then zenith (a direction's angular slice at that node).
-// Table layout [f][z][a][4] complex.
+// Entry cp of the four (channel, component) entries at frequency node f,
+// interpolated along azimuth, then zenith (a direction's angular slice at
+// that node).  Table layout [f][z][a][4] complex.  One entry per call, so
+// that a workgroup spreads a slice over (node, entry) pairs: four
+// independent loads per thread.
 template <typename Tt, typename T>
-__device__ __forceinline__ void slice4(const C2<Tt>* __restrict__ nodes, const GridDev& g, int f, int iz, T tz,
-                                       int ia, int ja, T ta, C2<T> out[4])
+__device__ __forceinline__ C2<T> slice1(const C2<Tt>* __restrict__ nodes, const GridDev& g, int f, int cp, int iz,
+                                        T tz, int ia, int ja, T ta)
 {
-    C2<T> za[2][4];
+    C2<T> za[2];
 #pragma unroll
     for (int dz = 0; dz < 2; ++dz) {
         const int64_t row = ((int64_t)f * g.n_zen + (iz + dz)) * g.n_az;
-        const C2<Tt>* p0 = nodes + (row + ia) * 4;
-        const C2<Tt>* p1 = nodes + (row + ja) * 4;
-#pragma unroll
-        for (int cp = 0; cp < 4; ++cp) {
-            const C2<T> a0{(T)p0[cp].re, (T)p0[cp].im};
-            const C2<T> a1{(T)p1[cp].re, (T)p1[cp].im};
-            za[dz][cp] = clerp(a0, a1, ta);
-        }
+        const C2<Tt> p0 = nodes[(row + ia) * 4 + cp];
+        const C2<Tt> p1 = nodes[(row + ja) * 4 + cp];
+        za[dz] = clerp(C2<T>{(T)p0.re, (T)p0.im}, C2<T>{(T)p1.re, (T)p1.im}, ta);
     }
-#pragma unroll
-    for (int cp = 0; cp < 4; ++cp) out[cp] = clerp(za[0][cp], za[1][cp], tz);
+    return clerp(za[0], za[1], tz);
 }
 
 // Frequency nodes a direction's angular slice holds in LDS at a time (the
@@ -504,34 +500,56 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
         freq_cell(gd, (int64_t)(ev.k_lo + ev.nb - 1), ev.N, fs, f_hi, tdummy);
         n_nodes = f_hi - f_lo + 2;
     }
+    constexpr int kRecWords = (int)(sizeof(MBin<T>) / 16);
+    __shared__ uint4 stage[kBlock * kRecWords];
+    const bool one_window = n_nodes <= kMaxSliceNodes;  // uniform
     for (int w0 = 0; w0 < n_nodes - 1; w0 += kMaxSliceNodes - 1) {
         const int wn = min(kMaxSliceNodes, n_nodes - w0);  // uniform over the workgroup
         if (w0 > 0) __syncthreads();                         // the previous window's reads are done
-        for (int i = threadIdx.x; i < wn; i += blockDim.x)
-            slice4<Tt, T>(nodes, gd, f_lo + w0 + i, iz, (T)tz, ia, ja, (T)ta, sl[i]);
+        for (int it = threadIdx.x; it < 4 * wn; it += blockDim.x)
+            sl[it >> 2][it & 3] = slice1<Tt, T>(nodes, gd, f_lo + w0 + (it >> 2), it & 3, iz, (T)tz, ia, ja, (T)ta);
         __syncthreads();
-        for (int j = threadIdx.x; j < ev.nb; j += blockDim.x) {
-            int ifr;
-            double tf;
-            freq_cell(gd, (int64_t)(ev.k_lo + j), ev.N, fs, ifr, tf);
-            const int li = ifr - f_lo - w0;
-            if (li < 0 || li > wn - 2) continue;  // in another window
-            if constexpr (RESP) {
-                if (wq > 0.0) tf = rint(tf * wq) / wq;
-            }
-            C2<T> h[4];
-#pragma unroll
-            for (int cp = 0; cp < 4; ++cp) h[cp] = clerp(sl[li][cp], sl[li + 1][cp], (T)tf);
+        for (int j0 = 0; j0 < ev.nb; j0 += blockDim.x) {  // uniform trip count
+            const int j = j0 + (int)threadIdx.x;
             MBin<T> m;
-            if constexpr (RESP) {
-                m.p0 = h[0];
-                m.p1 = h[1];
-                m.q0 = h[2];
-                m.q1 = h[3];
-            } else {
-                m = coef_from_h<T>(h, ev.N, inv_n, fallback_rel, singular_rel, n_fb, n_sg);
+            bool have = false;
+            if (j < ev.nb) {
+                int ifr;
+                double tf;
+                freq_cell(gd, (int64_t)(ev.k_lo + j), ev.N, fs, ifr, tf);
+                const int li = ifr - f_lo - w0;
+                if (li >= 0 && li <= wn - 2) {  // else in another window
+                    if constexpr (RESP) {
+                        if (wq > 0.0) tf = rint(tf * wq) / wq;
+                    }
+                    C2<T> h[4];
+#pragma unroll
+                    for (int cp = 0; cp < 4; ++cp) h[cp] = clerp(sl[li][cp], sl[li + 1][cp], (T)tf);
+                    if constexpr (RESP) {
+                        m.p0 = h[0];
+                        m.p1 = h[1];
+                        m.q0 = h[2];
+                        m.q1 = h[3];
+                    } else {
+                        m = coef_from_h<T>(h, ev.N, inv_n, fallback_rel, singular_rel, n_fb, n_sg);
+                    }
+                    have = true;
+                }
             }
-            out[j] = m;
+            if (one_window) {
+                // every bin of the band is in this window: the block's records
+                // go out through LDS as consecutive 16-byte words (a wave's
+                // store covers 1 KiB of the row instead of 16 bytes of each of
+                // 64 records)
+                reinterpret_cast<MBin<T>*>(stage)[threadIdx.x] = m;
+                __syncthreads();
+                const int words = min((int)blockDim.x, ev.nb - j0) * kRecWords;
+                uint4* dst = reinterpret_cast<uint4*>(out + j0);
+                for (int c = threadIdx.x; c < words; c += blockDim.x) dst[c] = stage[c];
+                __syncthreads();
+            } else if (have) {
+                out[j] = m;
+            }
         }
     }
     if (!RESP && counts != nullptr) {
@@ -1225,7 +1243,8 @@ __global__ __launch_bounds__(N / 8) void k_event_fused(const C2<Tt>* __restrict_
         freq_cell(gd, (int64_t)(k_lo + nb - 1), N, fs, f_hi, tdummy);
         n_nodes = f_hi - f_lo + 2;
     }
-    for (int i = t; i < n_nodes; i += TT) slice4<Tt, T>(nodes, gd, f_lo + i, iz, (T)tz, ia, ja, (T)ta, sl[i]);
+    for (int it = t; it < 4 * n_nodes; it += TT)
+        sl[it >> 2][it & 3] = slice1<Tt, T>(nodes, gd, f_lo + (it >> 2), it & 3, iz, (T)tz, ia, ja, (T)ta);
     // the station's traces: forward transform conj(F+(conj z)), z = V_0 + i V_1
     const T* __restrict__ V = volt + ev.volt_off + (int64_t)s * 2 * N;
     C2<T> x[E];
