@@ -413,13 +413,18 @@ template <typename T>
 __device__ __forceinline__ MBin<T> coef_from_h(const C2<T> (&h)[4], int n, T inv_n, double fallback_rel,
                                                double singular_rel, unsigned int& n_fb, unsigned int& n_sg)
 {
+    // the counts go through locals added once at the end: increments of the
+    // two references on different branches became a select of their
+    // addresses, i.e. the counters in scratch memory with a wait for every
+    // outstanding memory operation at each bin
     MBin<T> m;
+    unsigned int fb = 0, sg = 0;
     if constexpr (sizeof(T) == 4) {
         C2<float> hs[4];
         int e;
         if (!pow2_normalise(h, hs, e)) {
             m.p0 = m.p1 = m.q0 = m.q1 = C2<T>{0, 0};
-            ++n_sg;
+            sg = 1;
         } else {
             const C2<float> det = csub(cmul(hs[0], hs[3]), cmul(hs[1], hs[2]));
             float fro2 = 0.f;
@@ -432,19 +437,21 @@ __device__ __forceinline__ MBin<T> coef_from_h(const C2<T> (&h)[4], int n, T inv
 #pragma unroll
                 for (int i = 0; i < 4; ++i) hd[i] = C2<double>{(double)hs[i].re, (double)hs[i].im};
                 MBin<double> md;
-                n_sg += invert2_scaled<double>(hd, ldexp(1.0 / (double)n, -e), singular_rel, md);
-                ++n_fb;
+                sg = (unsigned int)invert2_scaled<double>(hd, ldexp(1.0 / (double)n, -e), singular_rel, md);
+                fb = 1;
                 m.p0 = C2<T>{(T)md.p0.re, (T)md.p0.im};
                 m.p1 = C2<T>{(T)md.p1.re, (T)md.p1.im};
                 m.q0 = C2<T>{(T)md.q0.re, (T)md.q0.im};
                 m.q1 = C2<T>{(T)md.q1.re, (T)md.q1.im};
             } else {
-                n_sg += invert2_scaled<T>(hs, ldexp(inv_n, -e), singular_rel, m);
+                sg = (unsigned int)invert2_scaled<T>(hs, ldexp(inv_n, -e), singular_rel, m);
             }
         }
     } else {
-        n_sg += invert2<T>(h, inv_n, singular_rel, m);
+        sg = (unsigned int)invert2<T>(h, inv_n, singular_rel, m);
     }
+    n_fb += fb;
+    n_sg += sg;
     return m;
 }
 
