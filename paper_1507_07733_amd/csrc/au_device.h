@@ -358,7 +358,7 @@ constexpr bool tw_lds_early(int mode) { return mode == TW_HYB || mode == TW_LF; 
 constexpr bool tw_lf(int mode) { return mode == TW_LF || mode == TW_LFR || mode == TW_LFW; }
 // Every pass's twiddles in registers.
 constexpr bool tw_all_reg(int mode) { return mode == TW_REG || mode == TW_LFR || mode == TW_LFW; }
-// (tangent, cosine) pairs per butterfly of a radix-R pass in TW_LF / TW_LFR.
+// (tangent, cosine) pairs per butterfly of a radix-R pass in TW_LF, TW_LFR, TW_LFW.
 constexpr int lf_entries(int r) { return r == 8 ? 4 : (r == 4 ? 2 : 1); }
 // Twiddle entries per butterfly of a radix-R pass.
 constexpr int tw_per(int mode, int r) { return tw_lf(mode) ? lf_entries(r) : r - 1; }
@@ -872,10 +872,11 @@ __device__ __forceinline__ void fft_pp(C2<T> (&x)[E], C2<T>* __restrict__ la, C2
 //   pass 3: r = p2, w = p3, lh = p1, ll = p0   (r <-> lh: register transpose)
 //   pass 4: r = p3, w = p2, lh = p1, ll = p0   (r <-> w: workgroup exchange)
 // so the output is x[r] = X[t + 512 r], as after the Stockham passes.  The
-// register transpose of lane bits 3-5 costs one VALU move per 32-bit word
-// and bit; lane bits 0-2 would take two (a DPP move and a select, or two
-// DPP moves), so that transpose goes through LDS, where a wavefront needs
-// no barrier.
+// register transpose of lane bits 3-5 costs at most one VALU move per
+// 32-bit word and bit (a bank-masked DPP rotation for bit 3, plus a copy per
+// pair of words; one lane swap per two words for bits 4 and 5); lane bits
+// 0-2 would take two (a DPP move and a select), so that transpose goes
+// through LDS, where a wavefront needs no barrier.
 
 // Slot of position q in the LDS buffers of fft4096_xw: an XOR of bits 0-2
 // with bits 6-8 (a permutation of each aligned block of 8 positions), which
