@@ -719,6 +719,8 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
     // list (persistent: from that list's counter, then from the other lists
     // once it is empty), and those rows are fetched into one XCD's L2 only.
     if (threadIdx.x == 0) sh_list = blockIdx.x & 7;
+    // XW: the band whose out-of-band slots of the staging buffer hold zeros
+    unsigned zb_klo = ~0u, zb_nb = ~0u;
     for (int iter = 0;; ++iter) {
         int u;
         if (counter != nullptr) {
@@ -773,6 +775,20 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
         const EvDesc ev = evs ? evs[e] : ev0;
         const MBin<T>* __restrict__ Md = M + ev.m_off + (int64_t)d * ev.nb;
         const unsigned nb = (unsigned)ev.nb, k_lo = (unsigned)ev.k_lo;
+        if constexpr (XW) {
+            // The staging writes in-band slots (and the pad slot) only and
+            // nothing else writes this buffer, so zeros written once per
+            // band stay: the gathers read every slot unconditionally.
+            // (Every gather of the previous station is done: its exchange
+            // barrier has passed.)
+            if (k_lo != zb_klo || nb != zb_nb) {  // uniform
+#pragma unroll
+                for (int i = 0; i < E; ++i) lds[xw_slot(t + TT * i)] = C2<T>{0, 0};
+                lds_barrier();
+                zb_klo = k_lo;
+                zb_nb = nb;
+            }
+        }
         MBin<T> pm[PF > 0 ? PF : 1];
         XBin<T> px[PF > 0 ? PF : 1];
         // loads of PF bins of station s (clamped: a valid station, bin nb-1 for
@@ -881,29 +897,30 @@ __attribute__((amdgpu_waves_per_eu(unfold_min_waves<T, E, TWMODE, PAIR, PP>())))
                 lds_sync<WAVE>();
 #pragma unroll
                 for (int i = 0; i < E; ++i) {
-                    // position t + TT i holds element k (XW: digit-reversed)
-                    const unsigned q = t + TT * i;
-                    const unsigned k = XW ? (unsigned)xw_pos((int)q) : q;
-                    const unsigned kk = (k <= N / 2) ? k : N - k;
-                    const bool inb = active && (kk - k_lo) < nb;
-                    // with the prefetch the registers are short: a zero slot
-                    // in place of a per-bin select (the compiler keeps the
-                    // eight addresses for the unit)
-                    if constexpr (XW)
-                        x[i] = lds[inb ? xw_slot((int)q) : lds_zero_slot<N>()];
-                    else if constexpr (PF > 0)
-                        x[i] = lds[inb ? lpad<T>(k) : lds_zero_slot<N>()];
-                    else
-                        x[i] = inb ? lds[lpad<T>(k)] : C2<T>{0, 0};
+                    if constexpr (XW) {
+                        // position t + TT i of the digit-reversed order; out
+                        // of band it holds the zero written for the band
+                        x[i] = lds[xw_slot((int)(t + TT * i))];
+                    } else {
+                        const unsigned k = t + TT * i;
+                        const unsigned kk = (k <= N / 2) ? k : N - k;
+                        const bool inb = active && (kk - k_lo) < nb;
+                        // with the prefetch the registers are short: a zero
+                        // slot in place of a per-bin select (the compiler
+                        // keeps the eight addresses for the unit)
+                        if constexpr (PF > 0)
+                            x[i] = lds[inb ? lpad<T>(k) : lds_zero_slot<N>()];
+                        else
+                            x[i] = inb ? lds[lpad<T>(k)] : C2<T>{0, 0};
+                    }
                 }
                 if constexpr (!PP) lds_sync<WAVE>();
             }
             if constexpr (XW) {
-                // staging (and the wavefront-local exchange) in lds, the
-                // workgroup exchange in lds2: the next station's staging
-                // writes lds after this station's exchange barrier, which
-                // every thread passes after its last access to lds
-                fft4096_xw<T, +1>(x, lds, lds2, w, t);
+                // staging in lds, both exchanges in lds2: the next station's
+                // staging writes lds after this station's exchange barrier,
+                // which every thread passes after its gathers from lds
+                fft4096_xw<T, +1>(x, lds2, w, t);
             } else if constexpr (PP) {
                 fft_pp<T, N, E, +1, TWMODE, RMAX, WAVE>(x, lds2, lds, tw, t, w, ltw);
                 // exchanges this station: the staging one (lds, unless PAIR)

@@ -868,7 +868,7 @@ __device__ __forceinline__ void fft_pp(C2<T> (&x)[E], C2<T>* __restrict__ la, C2
 // Register index r holds the digit a pass combines; the other digits sit in
 // the thread index:
 //   pass 1: r = p0, w = p3, lh = p2, ll = p1
-//   pass 2: r = p1, w = p3, lh = p2, ll = p0   (r <-> ll: the wavefront's LDS)
+//   pass 2: r = p1, w = p3, lh = p2, ll = p0   (r <-> ll: the wavefront's LDS block)
 //   pass 3: r = p2, w = p3, lh = p1, ll = p0   (r <-> lh: register transpose)
 //   pass 4: r = p3, w = p2, lh = p1, ll = p0   (r <-> w: workgroup exchange)
 // so the output is x[r] = X[t + 512 r], as after the Stockham passes.  The
@@ -879,10 +879,11 @@ __device__ __forceinline__ void fft_pp(C2<T> (&x)[E], C2<T>* __restrict__ la, C2
 // through LDS, where a wavefront needs no barrier.
 
 // Slot of position q in the LDS buffers of fft4096_xw: an XOR of bits 0-2
-// with bits 6-8 (a permutation of each aligned block of 8 positions), which
-// keeps the gathers and the exchange (64 consecutive positions per wave) and
-// the staging scatter (consecutive bins k to positions 64 (k mod 8) + ...)
-// free of bank conflicts for 8- and 16-byte elements.
+// with bits 6-8 (a permutation of each aligned block of 8 positions, so a
+// block of 512 stays in place), which keeps the gathers and the exchange (64
+// consecutive positions per wave) and the staging scatter (consecutive bins
+// k to positions 64 (k mod 8) + ...) free of bank conflicts for 8- and
+// 16-byte elements.
 __device__ __forceinline__ constexpr int xw_slot(int q) { return q ^ ((q >> 6) & 7); }
 // The digit-reversed input order in base-8 digits 0 and 2 of a 4096-point
 // index (an involution): element e sits at the gather position xw_pos(e) of
@@ -967,36 +968,33 @@ __device__ __forceinline__ void xw_pass(C2<T> (&x)[8], const C2<T>* __restrict__
     }
 }
 
-// Slot of position q for the wavefront-local exchange of the low lane
-// digit: an XOR of bits 0-2 with bits 9-11, so that the transposed reads
-// (consecutive lanes 512 positions apart) fall in distinct banks.  It
-// permutes each aligned block of 8 positions, so a wavefront's gather
-// positions {t + 512 r} map onto themselves.
-__device__ __forceinline__ constexpr int xw_slot_lo(int q) { return q ^ ((q >> 9) & 7); }
-
 // x[r] holds position t + 512 r of the digit-reversed input (see above);
 // returns x[r] = output element t + 512 r.  `la` is a buffer of
 // lds_elems<4096>() slots that no other thread group uses; the caller must
 // not write it again before every thread has passed a barrier that follows
 // this call (it holds one exchange between a barrier and the gathers after
-// it).  The first transpose goes through `ls`, each wavefront in its own
-// gather positions {t + 512 r} of that buffer (the caller's staging buffer,
-// whose gathers this wavefront has issued before; a wavefront's LDS
-// operations complete in order), with no workgroup barrier.
+// it).  The first transpose goes through the wavefront's own 512 slots of
+// `la` (a wavefront's LDS operations complete in order, and every other
+// wavefront's reads of `la` from the previous call precede the caller's
+// barrier before this one), with no workgroup barrier.
 template <typename T, int SIGN>
-__device__ __forceinline__ void fft4096_xw(C2<T> (&x)[8], C2<T>* __restrict__ ls, C2<T>* __restrict__ la,
-                                           const C2<T>* __restrict__ w, int t)
+__device__ __forceinline__ void fft4096_xw(C2<T> (&x)[8], C2<T>* __restrict__ la, const C2<T>* __restrict__ w,
+                                           int t)
 {
     xw_pass<T, 1, SIGN>(x, w);
     {
-        // register b of lane (lh, a) to position 512 b + 64 w + 8 lh + a;
-        // lane (lh, b) reads register a from there
-        const int base = t & ~7, ll = t & 7;
+        // in the wavefront's own block of `la`, the slots its workgroup
+        // exchange below writes (xw_slot keeps a block in place): register b
+        // of lane l at 64 b + (l ^ b); lane (lh, ll) reads register a at
+        // 64 ll + ((8 lh + a) ^ ll) -- for 16 consecutive lanes 8 (lh mod 2)
+        // + (a ^ ll) mod 16 are distinct, so no two share a bank
+        C2<T>* __restrict__ blk = la + 512 * (t >> 6);
+        const int l = t & 63, ll = t & 7, lh8 = t & 0x38;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) ls[xw_slot_lo(512 * b + t)] = x[b];
+        for (int b = 0; b < 8; ++b) blk[64 * b + (l ^ b)] = x[b];
         lds_sync<true>();
 #pragma unroll
-        for (int a = 0; a < 8; ++a) x[a] = ls[xw_slot_lo(512 * ll + base + a)];
+        for (int a = 0; a < 8; ++a) x[a] = blk[64 * ll + ((lh8 + a) ^ ll)];
     }
     xw_pass<T, 8, SIGN>(x, w);
     xw_transpose_hi(x);
