@@ -1368,6 +1368,11 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
     constexpr int NW = (TT + 63) / 64;  // waves per group
     constexpr int TWM = env_twmode<T, E>();
     constexpr bool DUAL = env_dual<T, E>();
+    // FP64 at 4096 samples: the two transforms in fft4096_xw2's form; the
+    // first buffer holds the staged Z (digit-reversed, zeros out of band)
+    // and later the Hilbert transform's workgroup exchange, the second the
+    // wavefront-local transposes, the trace's exchange and the reduction
+    constexpr bool XWE = sizeof(T) == 8 && N == 4096 && E == 8 && G == 1 && DUAL && TWM == TW_LF;
     // one event (ev0; workgroup = direction x chunk of spw stations), or many
     // (units[b] = (event, direction, s0, s1) with descriptors evs[]; then
     // ev.efield_off is the element offset of the event's [D][S][3] peak and
@@ -1400,6 +1405,11 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
     load_twiddles<T, N, E, E, TWM, +1>(w, tw, t);
     if constexpr (tw_lds_early(TWM)) {
         fill_lds_twiddles<T, N, E, E, +1, TWM>(ltw, tw, threadIdx.x, blockDim.x);
+        if constexpr (XWE) {
+            // the staging buffer's zeros (the staging writes in-band slots only)
+#pragma unroll
+            for (int i = 0; i < E; ++i) la[xw_slot(t + TT * i)] = C2<T>{0, 0};
+        }
         lds_barrier();
     }
     const unsigned nb = (unsigned)ev.nb, k_lo = (unsigned)ev.k_lo;
@@ -1409,7 +1419,9 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
     // then overlap the current station's transforms instead of opening the
     // next station's staging.  Clamped like k_unfold's: a valid station, bin
     // nb-1 for bins past the band, the twiddle table when the band is empty.
-    constexpr int PF = (sizeof(T) == 8 && E == 8 && G == 1 && DUAL) ? 2 : 0;
+    // Not in the in-wavefront form, which needs those registers (with them it
+    // spills and runs 9 % slower).
+    constexpr int PF = (!XWE && sizeof(T) == 8 && E == 8 && G == 1 && DUAL) ? 2 : 0;
     MBin<T> pm[PF > 0 ? PF : 1];
     XBin<T> px[PF > 0 ? PF : 1];
     auto prefetch = [&](int sv) {
@@ -1427,6 +1439,16 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
     // spare pad slot, which no gather reads
     auto stage = [&](int h, unsigned j, const C2<T>& zp, const C2<T>& zq, bool ok) {
         const unsigned k = k_lo + j;
+        if constexpr (XWE) {
+            // Z only: the gathers derive Zh
+            if (ok && k == 0) {
+                la[0] = packed_dc(zp, zq);
+            } else {
+                la[ok ? stage_slot<T, N, true>(k) : lds_pad_slot<N>()] = zp;
+                la[ok ? stage_slot<T, N, true>(N - k) : lds_pad_slot<N>()] = C2<T>{zq.re, -zq.im};
+            }
+            return;
+        }
         if (ok && k == 0) {
             if (DUAL || h == 0) la[0] = packed_dc(zp, zq);
             if (DUAL || h == 1) lb[0] = C2<T>{0, 0};
@@ -1480,6 +1502,18 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                 }
             }
             lds_barrier();
+            if constexpr (XWE) {
+                // position t + TT i holds element 512 i + c, c < 512: below
+                // N/2 for i < 4, where Zh = -i Z, above for i >= 4, Zh = i Z;
+                // Zh = 0 at DC (thread 0, register 0)
+#pragma unroll
+                for (int i = 0; i < E; ++i) {
+                    x[i] = la[xw_slot(t + TT * i)];
+                    xh[i] = i < E / 2 ? C2<T>{x[i].im, -x[i].re} : C2<T>{-x[i].im, x[i].re};
+                }
+                if (t == 0) xh[0] = C2<T>{0, 0};
+                continue;  // no barrier: the transposes write the other buffer
+            }
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 const unsigned k = t + TT * i;
@@ -1491,7 +1525,9 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
             lds_barrier();
         }
         __builtin_amdgcn_s_setprio(0);
-        if constexpr (DUAL) {
+        if constexpr (XWE) {
+            fft4096_xw2<T, +1, TWM>(x, xh, lb, la, w, t, ltw);
+        } else if constexpr (DUAL) {
             fft2<T, N, E, +1, TWM, E>(x, xh, la, lb, tw, t, w, ltw);
         } else {
             fft<T, N, E, +1>(x, la, tw, t);
@@ -1541,7 +1577,7 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
             // component c (TT / 64 candidates per lane and a butterfly)
             // while the other waves go on -- a fraction of the VALU work of a
             // three-component butterfly in every wave.
-            T* cv = reinterpret_cast<T*>(la);
+            T* cv = reinterpret_cast<T*>(XWE ? lb : la);
             int* ci = reinterpret_cast<int*>(cv + 3 * TT);
             static_assert(3 * TT * (sizeof(T) + sizeof(int)) <= lds_elems<N>() * sizeof(C2<T>), "scratch");
 #pragma unroll
@@ -1551,6 +1587,12 @@ __global__ __launch_bounds__((N / E) > kBlock ? (N / E) : kBlock) void k_unfold_
                 ci[c * TT + t] = bi[c];
             }
             lds_barrier();
+            if constexpr (XWE) {
+                // every read of the Hilbert exchange in the first buffer is
+                // behind that barrier: its zeros back before the closing one
+#pragma unroll
+                for (int i = 0; i < E; ++i) la[xw_slot(t + TT * i)] = C2<T>{0, 0};
+            }
             const int wv = t >> 6, lane = t & 63;
             const int cc = c_lo + wv;  // the component this wave reduces
             if (cc < 3 && active) {  // whole waves: no barrier inside

@@ -953,15 +953,22 @@ __device__ __forceinline__ void xw_transpose_hi(C2<T> (&x)[8])
 
 // One radix-8 pass in registers: inputs r times the pass-NS factors of the
 // thread (TW_LFR registers, none for NS = 1), then the 8-point DFT.
-template <typename T, int NS, int SIGN>
-__device__ __forceinline__ void xw_pass(C2<T> (&x)[8], const C2<T>* __restrict__ w)
+template <typename T, int NS, int SIGN, int TWMODE = TW_LFW>
+__device__ __forceinline__ void xw_pass(C2<T> (&x)[8], const C2<T>* __restrict__ w,
+                                        const C2<T>* __restrict__ ltw = nullptr, int t = 0)
 {
     if constexpr (NS > 1) {
         constexpr int LE = lf_entries(8);
-        constexpr int OFF = tw_offset<4096, 8, 8, TW_LFW>(NS);
+        constexpr int OFF = tw_offset<4096, 8, 8, TWMODE>(NS);
         C2<T> L[LE];
 #pragma unroll
-        for (int e = 0; e < LE; ++e) L[e] = lf_sign<SIGN>(w[OFF + e]);
+        for (int e = 0; e < LE; ++e) {
+            // TW_LF: the early passes' pairs from the LDS table
+            if constexpr (tw_lds_early(TWMODE) && NS < 512)
+                L[e] = lf_sign<SIGN>(ltw[ltw_offset<4096, 8, 8, TW_LF>(NS) + e * NS + (t & (NS - 1))]);
+            else
+                L[e] = lf_sign<SIGN>(w[OFF + e]);
+        }
         lf_dft<8, SIGN>(x, L);
     } else {
         Dft<8, SIGN, T>::run(x);
@@ -1006,6 +1013,57 @@ __device__ __forceinline__ void fft4096_xw(C2<T> (&x)[8], C2<T>* __restrict__ la
 #pragma unroll
     for (int r = 0; r < 8; ++r) x[r] = la[xw_slot(512 * r + 64 * wv + l)];
     xw_pass<T, 512, SIGN>(x, w);
+}
+
+// Two 4096-point transforms (x and y, the same layout, direction and
+// twiddles) in fft4096_xw's form: both first transposes, one after the
+// other, in the wavefront's own block of `la`; both second transposes in
+// registers; the workgroup exchange of x through `la` and, after its
+// barrier, that of y through `lb` (the caller's staging buffer: every
+// wavefront's gathers from it precede its first exchange write, so the
+// first barrier also ends every use of `lb` by the caller).  The caller
+// must not write `la` or `lb` again before every thread has passed a
+// barrier that follows this call.
+template <typename T, int SIGN, int TWMODE>
+__device__ __forceinline__ void fft4096_xw2(C2<T> (&x)[8], C2<T> (&y)[8], C2<T>* __restrict__ la,
+                                            C2<T>* __restrict__ lb, const C2<T>* __restrict__ w, int t,
+                                            const C2<T>* __restrict__ ltw)
+{
+    xw_pass<T, 1, SIGN, TWMODE>(x, w, ltw, t);
+    xw_pass<T, 1, SIGN, TWMODE>(y, w, ltw, t);
+    {
+        C2<T>* __restrict__ blk = la + 512 * (t >> 6);
+        const int l = t & 63, ll = t & 7, lh8 = t & 0x38;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) blk[64 * b + (l ^ b)] = x[b];
+        lds_sync<true>();
+#pragma unroll
+        for (int a = 0; a < 8; ++a) x[a] = blk[64 * ll + ((lh8 + a) ^ ll)];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) blk[64 * b + (l ^ b)] = y[b];
+        lds_sync<true>();
+#pragma unroll
+        for (int a = 0; a < 8; ++a) y[a] = blk[64 * ll + ((lh8 + a) ^ ll)];
+    }
+    xw_pass<T, 8, SIGN, TWMODE>(x, w, ltw, t);
+    xw_pass<T, 8, SIGN, TWMODE>(y, w, ltw, t);
+    xw_transpose_hi(x);
+    xw_transpose_hi(y);
+    xw_pass<T, 64, SIGN, TWMODE>(x, w, ltw, t);
+    xw_pass<T, 64, SIGN, TWMODE>(y, w, ltw, t);
+    const int wv = t >> 6, l = t & 63;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) la[xw_slot(512 * wv + 64 * r + l)] = x[r];
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) x[r] = la[xw_slot(512 * r + 64 * wv + l)];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) lb[xw_slot(512 * wv + 64 * r + l)] = y[r];
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) y[r] = lb[xw_slot(512 * r + 64 * wv + l)];
+    xw_pass<T, 512, SIGN, TWMODE>(x, w, ltw, t);
+    xw_pass<T, 512, SIGN, TWMODE>(y, w, ltw, t);
 }
 
 // Full N-point transform of the group's sequence, exp(SIGN ...) kernel, no
