@@ -462,7 +462,8 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
                                                  const double* __restrict__ dirs, double zen1,
                                                  double az1, int64_t fs, double fallback_rel,
                                                  double singular_rel, MBin<T>* __restrict__ M,
-                                                 unsigned long long* __restrict__ counts, double wq)
+                                                 unsigned long long* __restrict__ counts, double wq,
+                                                 const int* __restrict__ skip = nullptr, int skip_stride = 0)
 {
     __shared__ unsigned int cnt[2];
     if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
@@ -473,6 +474,8 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
         e = w.x;
         d = w.y;
     }
+    // a converged reconstruction loop: its envelope launch is skipped too
+    if (skip != nullptr && skip[(int64_t)e * skip_stride]) return;
     const EvDesc ev = evs ? evs[e] : ev0;
     double zen = zen1, az = az1;
     if (dirs != nullptr) {
@@ -2320,11 +2323,12 @@ extern "C" au_status au_workspace_bytes(const au_table* tb, const au_event* ev, 
 template <typename Tt, typename T>
 static void launch_coef(hipStream_t st, const au_table* tb, const EvDesc& ev0, const EvDesc* evs,
                         const int2* units, int n_units, const double* dirs, double zen, double az,
-                        int64_t fs, double fb, double sg, MBin<T>* M, unsigned long long* counts)
+                        int64_t fs, double fb, double sg, MBin<T>* M, unsigned long long* counts,
+                        const int* skip = nullptr, int skip_stride = 0)
 {
     hipLaunchKernelGGL((k_coef<Tt, T, false>), dim3(n_units), dim3(kBlock), 0, st,
                        (const C2<Tt>*)tb->d_nodes, tb->g, ev0, evs, units, dirs, zen, az, fs, fb, sg,
-                       M, counts, 0.0);
+                       M, counts, 0.0, skip, skip_stride);
 }
 
 // Stations per work unit of a direction scan (one event, n_dir directions;
@@ -2682,7 +2686,7 @@ static au_status pattern_response(const au_table* tb, const au_event* ev, int32_
 #define RESP_(TT, T)                                                                        \
     hipLaunchKernelGGL((k_coef<TT, T, true>), dim3(n_dir), dim3(kBlock), 0, st,            \
                        (const C2<TT>*)tb->d_nodes, tb->g, ev0, nullptr, nullptr, dirs, 0.0, 0.0, \
-                       ev->fs_hz, 0.0, 0.0, (MBin<T>*)d_resp, nullptr, wq)
+                       ev->fs_hz, 0.0, 0.0, (MBin<T>*)d_resp, nullptr, wq, nullptr, 0)
     if (f64)
         RESP_(double, double);
     else if (tb->dtype == AU_F64)
@@ -3796,6 +3800,28 @@ au_status check_recon(const au_table* tb, const au_event* ev, int32_t max_iter, 
 
 }  // namespace
 
+// A pinned host buffer of the calling thread of at least `bytes`, kept for
+// the thread's lifetime (null if it cannot be allocated: callers then copy
+// to pageable memory).  A call reads it only after synchronizing its
+// stream, so growing it frees no buffer still being written.
+static void* pinned_scratch(size_t bytes)
+{
+    thread_local void* buf = nullptr;
+    thread_local size_t cap = 0;
+    if (bytes > cap) {
+        if (buf != nullptr) (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        if (hipHostMalloc(&buf, bytes, hipHostMallocDefault) != hipSuccess) {
+            buf = nullptr;
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        cap = bytes;
+    }
+    return buf;
+}
+
 template <typename T>
 static au_status run_reconstruct(const au_table* tb, const au_event* ev, const EvParams& p, const void* d_volt,
                                  const double* h_pos, int max_iter, void* d_efield, void* d_peak, void* d_work,
@@ -3844,10 +3870,10 @@ static au_status run_reconstruct(const au_table* tb, const au_event* ev, const E
         if (last) break;
         if (tb->dtype == AU_F64)
             launch_coef<double, T>(st, tb, ev0, nullptr, nullptr, 1, cur, 0, 0, ev->fs_hz, ev->fallback_rel,
-                                   ev->singular_rel, M, nullptr);
+                                   ev->singular_rel, M, nullptr, (const int*)state, 0);
         else
             launch_coef<float, T>(st, tb, ev0, nullptr, nullptr, 1, cur, 0, 0, ev->fs_hz, ev->fallback_rel,
-                                  ev->singular_rel, M, nullptr);
+                                  ev->singular_rel, M, nullptr, (const int*)state, 0);
         const int spw = env_spw(p.S, 1);
         const int chunks = (p.S + spw - 1) / spw;
         switch (p.N) {
@@ -3860,6 +3886,19 @@ static au_status run_reconstruct(const au_table* tb, const au_event* ev, const E
             default: e = hipErrorInvalidValue;
         }
         if (e != hipSuccess) return fail(AU_EDEVICE, std::string("reconstruction step: ") + hipGetErrorString(e));
+    }
+    // the results (times, directions, state: one contiguous region of the
+    // workspace) in one copy through pinned memory, instead of three staged
+    // copies from pageable memory that each wait for the one before
+    const size_t res_bytes = r.hist + r.dirs + r.cur + sizeof(int32_t) * 4;
+    unsigned char* hb = (unsigned char*)pinned_scratch(res_bytes);
+    if (hb != nullptr) {
+        HIP_TRY(hipMemcpyAsync(hb, hist, res_bytes, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::memcpy(h_times, hb, sizeof(int32_t) * (size_t)(max_iter + 1) * p.S);
+        std::memcpy(h_dirs, hb + r.hist, sizeof(double) * 2 * max_iter);
+        std::memcpy(h_state, hb + r.hist + r.dirs + r.cur, sizeof(int32_t) * 4);
+        return AU_OK;
     }
     HIP_TRY(hipMemcpyAsync(h_state, state, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(h_dirs, dirs, sizeof(double) * 2 * max_iter, hipMemcpyDeviceToHost, st));
@@ -4327,10 +4366,10 @@ static au_status run_reconstruct_batch(const au_table* tb, const au_event* ev, c
         if (last) break;
         if (tb->dtype == AU_F64)
             launch_coef<double, T>(st, tb, ev0, evs, cunits, n_events, cur, 0, 0, ev->fs_hz, ev->fallback_rel,
-                                   ev->singular_rel, M, nullptr);
+                                   ev->singular_rel, M, nullptr, (const int*)state, 4);
         else
             launch_coef<float, T>(st, tb, ev0, evs, cunits, n_events, cur, 0, 0, ev->fs_hz, ev->fallback_rel,
-                                  ev->singular_rel, M, nullptr);
+                                  ev->singular_rel, M, nullptr, (const int*)state, 4);
         switch (p.N) {
 #define X_(NN)                                                                                          \
     case NN:                                                                                            \
