@@ -3800,10 +3800,12 @@ au_status check_recon(const au_table* tb, const au_event* ev, int32_t max_iter, 
 
 }  // namespace
 
-// A pinned host buffer of the calling thread of at least `bytes`, kept for
-// the thread's lifetime (null if it cannot be allocated: callers then copy
-// to pageable memory).  A call reads it only after synchronizing its
-// stream, so growing it frees no buffer still being written.
+// A pinned host buffer of the calling thread of at least `bytes` (null if it
+// cannot be allocated: callers then copy to pageable memory).  One per
+// thread that calls it, grown as needed and never freed otherwise (a few
+// KiB: the results of one reconstruction).  A call reads it only after
+// synchronizing its stream, so growing it frees no buffer still being
+// written.
 static void* pinned_scratch(size_t bytes)
 {
     thread_local void* buf = nullptr;
