@@ -999,7 +999,6 @@ __device__ __forceinline__ V buffer_load_scalar(__amdgpu_buffer_rsrc_t r, unsign
     if constexpr (sizeof(V) == 4) {
         return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
     } else {
-        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
         return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
     }
 }
