@@ -455,22 +455,22 @@ __device__ __forceinline__ MBin<T> coef_from_h(const C2<T> (&h)[4], int n, T inv
     return m;
 }
 
+// The work of workgroup bx of k_coef.  dirs and skip may be written earlier
+// in the same kernel (by another thread of the workgroup, before a barrier).
 template <typename Tt, typename T, bool RESP>
-__global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ nodes, GridDev gd,
-                                                 EvDesc ev0, const EvDesc* __restrict__ evs,
-                                                 const int2* __restrict__ units,
-                                                 const double* __restrict__ dirs, double zen1,
-                                                 double az1, int64_t fs, double fallback_rel,
-                                                 double singular_rel, MBin<T>* __restrict__ M,
-                                                 unsigned long long* __restrict__ counts, double wq,
-                                                 const int* __restrict__ skip = nullptr, int skip_stride = 0)
+__device__ __forceinline__ void coef_block(int bx, const C2<Tt>* __restrict__ nodes, const GridDev& gd,
+                                           const EvDesc& ev0, const EvDesc* __restrict__ evs,
+                                           const int2* __restrict__ units, const double* dirs, double zen1,
+                                           double az1, int64_t fs, double fallback_rel, double singular_rel,
+                                           MBin<T>* __restrict__ M, unsigned long long* __restrict__ counts,
+                                           double wq, const int* skip, int skip_stride)
 {
     __shared__ unsigned int cnt[2];
     if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
     __syncthreads();
-    int e = 0, d = blockIdx.x;
+    int e = 0, d = bx;
     if (units != nullptr) {
-        const int2 w = units[blockIdx.x];
+        const int2 w = units[bx];
         e = w.x;
         d = w.y;
     }
@@ -569,6 +569,20 @@ __global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ node
         if (threadIdx.x < 2 && cnt[threadIdx.x])
             atomicAdd(&counts[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
     }
+}
+
+template <typename Tt, typename T, bool RESP>
+__global__ __launch_bounds__(kBlock) void k_coef(const C2<Tt>* __restrict__ nodes, GridDev gd,
+                                                 EvDesc ev0, const EvDesc* __restrict__ evs,
+                                                 const int2* __restrict__ units,
+                                                 const double* __restrict__ dirs, double zen1,
+                                                 double az1, int64_t fs, double fallback_rel,
+                                                 double singular_rel, MBin<T>* __restrict__ M,
+                                                 unsigned long long* __restrict__ counts, double wq,
+                                                 const int* __restrict__ skip = nullptr, int skip_stride = 0)
+{
+    coef_block<Tt, T, RESP>(blockIdx.x, nodes, gd, ev0, evs, units, dirs, zen1, az1, fs, fallback_rel, singular_rel,
+                            M, counts, wq, skip, skip_stride);
 }
 
 // E-field traces of one (event, direction, station range) per block; each
@@ -3690,14 +3704,12 @@ __global__ __launch_bounds__(kBlock) void k_volt_timing(const Tin* __restrict__ 
 // Many events: workgroup e takes event e, whose stations are [so, so + S) of
 // the Stot stations (ev_st[e] = (so, S)), with state, cur and dirs
 // (max_iter directions) per event.  One event: ev_st == nullptr, Stot = S.
-__global__ __launch_bounds__(kBlock) void k_recon_step(int it, int last, int S, double dt_ns,
-                                                        const double* __restrict__ pos,
-                                                        const int* __restrict__ env_arg, int* __restrict__ hist,
-                                                        double* __restrict__ dirs, double* __restrict__ cur,
-                                                        int* __restrict__ state, const int2* __restrict__ ev_st,
-                                                        int Stot, int max_iter)
+// The work of workgroup e (thread 0 writes the results).
+__device__ __forceinline__ void recon_step_block(int e, int it, int last, int S, double dt_ns,
+                                                 const double* __restrict__ pos, const int* __restrict__ env_arg,
+                                                 int* __restrict__ hist, double* dirs, double* cur, int* state,
+                                                 const int2* __restrict__ ev_st, int Stot, int max_iter)
 {
-    const int e = blockIdx.x;
     int so = 0;
     if (ev_st != nullptr) {
         so = ev_st[e].x;
@@ -3765,6 +3777,37 @@ __global__ __launch_bounds__(kBlock) void k_recon_step(int it, int last, int S, 
     cur[0] = zen;
     cur[1] = az;
     state[1] = it + 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_recon_step(int it, int last, int S, double dt_ns,
+                                                        const double* __restrict__ pos,
+                                                        const int* __restrict__ env_arg, int* __restrict__ hist,
+                                                        double* __restrict__ dirs, double* __restrict__ cur,
+                                                        int* __restrict__ state, const int2* __restrict__ ev_st,
+                                                        int Stot, int max_iter)
+{
+    recon_step_block(blockIdx.x, it, last, S, dt_ns, pos, env_arg, hist, dirs, cur, state, ev_st, Stot, max_iter);
+}
+
+// One event's step `it` (not the last) and, unless it stopped the loop, the
+// coefficient rows of the direction it produced: the step's two
+// single-workgroup launches (k_recon_step, then k_coef of one direction
+// skipped on the stop flag) as one.  The step's thread 0 writes the direction
+// and the flag before the barrier that precedes the coefficients' reads.
+template <typename Tt, typename T>
+__global__ __launch_bounds__(kBlock) void k_recon_step_coef(int it, int S, double dt_ns,
+                                                             const double* __restrict__ pos,
+                                                             const int* __restrict__ env_arg,
+                                                             int* __restrict__ hist, double* dirs, double* cur,
+                                                             int* state, int max_iter,
+                                                             const C2<Tt>* __restrict__ nodes, GridDev gd,
+                                                             EvDesc ev0, int64_t fs, double fallback_rel,
+                                                             double singular_rel, MBin<T>* __restrict__ M)
+{
+    recon_step_block(0, it, 0, S, dt_ns, pos, env_arg, hist, dirs, cur, state, nullptr, S, max_iter);
+    __syncthreads();
+    coef_block<Tt, T, false>(0, nodes, gd, ev0, nullptr, nullptr, cur, 0.0, 0.0, fs, fallback_rel, singular_rel, M,
+                             nullptr, 0.0, state, 0);
 }
 
 namespace {
@@ -3865,16 +3908,22 @@ static au_status run_reconstruct(const au_table* tb, const au_event* ev, const E
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("spectrum/timing: ") + hipGetErrorString(e));
     const double dt_ns = 1e9 / (double)ev->fs_hz;
     for (int it = 0; it <= max_iter; ++it) {
-        const int last = it == max_iter;
-        hipLaunchKernelGGL(k_recon_step, dim3(1), dim3(kBlock), 0, st, it, last, p.S, dt_ns, (const double*)pos,
-                           (const int*)arg, hist, dirs, cur, state, (const int2*)nullptr, p.S, max_iter);
-        if (last) break;
+        if (it == max_iter) {
+            // the step after the final unfold: convergence check only
+            hipLaunchKernelGGL(k_recon_step, dim3(1), dim3(kBlock), 0, st, it, 1, p.S, dt_ns, (const double*)pos,
+                               (const int*)arg, hist, dirs, cur, state, (const int2*)nullptr, p.S, max_iter);
+            break;
+        }
         if (tb->dtype == AU_F64)
-            launch_coef<double, T>(st, tb, ev0, nullptr, nullptr, 1, cur, 0, 0, ev->fs_hz, ev->fallback_rel,
-                                   ev->singular_rel, M, nullptr, (const int*)state, 0);
+            hipLaunchKernelGGL((k_recon_step_coef<double, T>), dim3(1), dim3(kBlock), 0, st, it, p.S, dt_ns,
+                               (const double*)pos, (const int*)arg, hist, dirs, cur, state, max_iter,
+                               (const C2<double>*)tb->d_nodes, tb->g, ev0, ev->fs_hz, ev->fallback_rel,
+                               ev->singular_rel, M);
         else
-            launch_coef<float, T>(st, tb, ev0, nullptr, nullptr, 1, cur, 0, 0, ev->fs_hz, ev->fallback_rel,
-                                  ev->singular_rel, M, nullptr, (const int*)state, 0);
+            hipLaunchKernelGGL((k_recon_step_coef<float, T>), dim3(1), dim3(kBlock), 0, st, it, p.S, dt_ns,
+                               (const double*)pos, (const int*)arg, hist, dirs, cur, state, max_iter,
+                               (const C2<float>*)tb->d_nodes, tb->g, ev0, ev->fs_hz, ev->fallback_rel,
+                               ev->singular_rel, M);
         const int spw = env_spw(p.S, 1);
         const int chunks = (p.S + spw - 1) / spw;
         switch (p.N) {
