@@ -3907,55 +3907,80 @@ static au_status run_reconstruct(const au_table* tb, const au_event* ev, const E
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return fail(AU_EDEVICE, std::string("spectrum/timing: ") + hipGetErrorString(e));
     const double dt_ns = 1e9 / (double)ev->fs_hz;
-    for (int it = 0; it <= max_iter; ++it) {
-        if (it == max_iter) {
-            // the step after the final unfold: convergence check only
+    // The loop's launches, in order: op 2 it is step `it` (with the
+    // coefficient rows of its direction; for it = max_iter the final
+    // convergence check alone), op 2 it + 1 the unfold and envelope timing of
+    // pass `it`.  Once the device stop flag is set every later launch is a
+    // no-op, so the host enqueues them in chunks, each ending with a step,
+    // and reads the results after each chunk: when the loop has stopped (the
+    // usual case after the first chunk, which ends with step 2) the rest is
+    // never enqueued.  The results equal those of the whole sequence.
+    const int n_ops = 2 * max_iter + 1;
+    const int spw = env_spw(p.S, 1);
+    const int chunks = (p.S + spw - 1) / spw;
+    auto enqueue_op = [&](int op) -> au_status {
+        const int it = op / 2;
+        hipError_t e = hipSuccess;
+        if (op % 2 == 0 && it == max_iter) {
             hipLaunchKernelGGL(k_recon_step, dim3(1), dim3(kBlock), 0, st, it, 1, p.S, dt_ns, (const double*)pos,
                                (const int*)arg, hist, dirs, cur, state, (const int2*)nullptr, p.S, max_iter);
-            break;
-        }
-        if (tb->dtype == AU_F64)
-            hipLaunchKernelGGL((k_recon_step_coef<double, T>), dim3(1), dim3(kBlock), 0, st, it, p.S, dt_ns,
-                               (const double*)pos, (const int*)arg, hist, dirs, cur, state, max_iter,
-                               (const C2<double>*)tb->d_nodes, tb->g, ev0, ev->fs_hz, ev->fallback_rel,
-                               ev->singular_rel, M);
-        else
-            hipLaunchKernelGGL((k_recon_step_coef<float, T>), dim3(1), dim3(kBlock), 0, st, it, p.S, dt_ns,
-                               (const double*)pos, (const int*)arg, hist, dirs, cur, state, max_iter,
-                               (const C2<float>*)tb->d_nodes, tb->g, ev0, ev->fs_hz, ev->fallback_rel,
-                               ev->singular_rel, M);
-        const int spw = env_spw(p.S, 1);
-        const int chunks = (p.S + spw - 1) / spw;
-        switch (p.N) {
+        } else if (op % 2 == 0) {
+            if (tb->dtype == AU_F64)
+                hipLaunchKernelGGL((k_recon_step_coef<double, T>), dim3(1), dim3(kBlock), 0, st, it, p.S, dt_ns,
+                                   (const double*)pos, (const int*)arg, hist, dirs, cur, state, max_iter,
+                                   (const C2<double>*)tb->d_nodes, tb->g, ev0, ev->fs_hz, ev->fallback_rel,
+                                   ev->singular_rel, M);
+            else
+                hipLaunchKernelGGL((k_recon_step_coef<float, T>), dim3(1), dim3(kBlock), 0, st, it, p.S, dt_ns,
+                                   (const double*)pos, (const int*)arg, hist, dirs, cur, state, max_iter,
+                                   (const C2<float>*)tb->d_nodes, tb->g, ev0, ev->fs_hz, ev->fallback_rel,
+                                   ev->singular_rel, M);
+        } else {
+            switch (p.N) {
 #define X_(NN)                                                                                               \
     case NN:                                                                                                 \
         e = launch_env_n<T, NN>(st, ev0, spw, chunks, X, M, (T*)d_efield, peak, arg, tw, (const int*)state); \
         break;
-            AU_FOR_EACH_N(X_)
+                AU_FOR_EACH_N(X_)
 #undef X_
-            default: e = hipErrorInvalidValue;
+                default: e = hipErrorInvalidValue;
+            }
         }
+        if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) return fail(AU_EDEVICE, std::string("reconstruction step: ") + hipGetErrorString(e));
-    }
+        return AU_OK;
+    };
     // the results (times, directions, state: one contiguous region of the
     // workspace) in one copy through pinned memory, instead of three staged
     // copies from pageable memory that each wait for the one before
     const size_t res_bytes = r.hist + r.dirs + r.cur + sizeof(int32_t) * 4;
     unsigned char* hb = (unsigned char*)pinned_scratch(res_bytes);
-    if (hb != nullptr) {
-        HIP_TRY(hipMemcpyAsync(hb, hist, res_bytes, hipMemcpyDeviceToHost, st));
+    auto fetch = [&]() -> au_status {
+        if (hb != nullptr) {
+            HIP_TRY(hipMemcpyAsync(hb, hist, res_bytes, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            std::memcpy(h_times, hb, sizeof(int32_t) * (size_t)(max_iter + 1) * p.S);
+            std::memcpy(h_dirs, hb + r.hist, sizeof(double) * 2 * max_iter);
+            std::memcpy(h_state, hb + r.hist + r.dirs + r.cur, sizeof(int32_t) * 4);
+            return AU_OK;
+        }
+        HIP_TRY(hipMemcpyAsync(h_state, state, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(h_dirs, dirs, sizeof(double) * 2 * max_iter, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(h_times, hist, sizeof(int32_t) * (size_t)(max_iter + 1) * p.S, hipMemcpyDeviceToHost,
+                               st));
         HIP_TRY(hipStreamSynchronize(st));
-        std::memcpy(h_times, hb, sizeof(int32_t) * (size_t)(max_iter + 1) * p.S);
-        std::memcpy(h_dirs, hb + r.hist, sizeof(double) * 2 * max_iter);
-        std::memcpy(h_state, hb + r.hist + r.dirs + r.cur, sizeof(int32_t) * 4);
         return AU_OK;
+    };
+    int op = 0;
+    for (int check = std::min(4, n_ops - 1);; check = std::min(check + 8, n_ops - 1)) {
+        for (; op <= check; ++op) {
+            const au_status s = enqueue_op(op);
+            if (s != AU_OK) return s;
+        }
+        const au_status s = fetch();
+        if (s != AU_OK) return s;
+        if (h_state[0] != 0 || op >= n_ops) return AU_OK;
     }
-    HIP_TRY(hipMemcpyAsync(h_state, state, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(h_dirs, dirs, sizeof(double) * 2 * max_iter, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(h_times, hist, sizeof(int32_t) * (size_t)(max_iter + 1) * p.S, hipMemcpyDeviceToHost,
-                           st));
-    HIP_TRY(hipStreamSynchronize(st));
-    return AU_OK;
 }
 
 extern "C" au_status au_reconstruct_workspace_bytes(const au_table* tb, const au_event* ev, int32_t max_iter,
