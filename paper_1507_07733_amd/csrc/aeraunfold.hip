@@ -3720,7 +3720,13 @@ __device__ __forceinline__ void recon_step_block(int e, int it, int last, int S,
     dirs += (int64_t)2 * max_iter * e;
     pos += 2 * (int64_t)so;
     env_arg += 3 * (int64_t)so;
-    if (state[0]) return;
+    if (it == 0) {
+        // the first step starts the event's state (the workspace may hold a
+        // previous call's); nothing reads it before this step
+        if (threadIdx.x == 0) state[0] = state[1] = state[2] = state[3] = 0;
+    } else if (state[0]) {
+        return;
+    }
     int* __restrict__ row = hist + (int64_t)it * Stot + so;
     if (it > 0) {
         int changed = 0;
@@ -3845,9 +3851,9 @@ au_status check_recon(const au_table* tb, const au_event* ev, int32_t max_iter, 
 // A pinned host buffer of the calling thread of at least `bytes` (null if it
 // cannot be allocated: callers then copy to pageable memory).  One per
 // thread that calls it, grown as needed and never freed otherwise (a few
-// KiB: the results of one reconstruction).  A call reads it only after
-// synchronizing its stream, so growing it frees no buffer still being
-// written.
+// KiB: one reconstruction's station positions and results).  Every call
+// that uses it waits for its stream before returning, so growing it frees
+// no buffer that a copy still uses.
 static void* pinned_scratch(size_t bytes)
 {
     thread_local void* buf = nullptr;
@@ -3884,8 +3890,19 @@ static au_status run_reconstruct(const au_table* tb, const au_event* ev, const E
     double* pos = (double*)(q += r.state);
     T* peak = d_peak ? (T*)d_peak : (T*)(q += r.pos);
     int* arg = (int*)(base + r.total - r.arg);
-    HIP_TRY(hipMemcpyAsync(pos, h_pos, sizeof(double) * 2 * p.S, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (unsigned int*)state, 4);
+    // The thread's pinned buffer: the results region (times, directions,
+    // state), then the station positions, which go up from there as an
+    // asynchronous copy instead of a staged pageable one.  (The previous call
+    // on this thread ended with a wait for its stream.)
+    const size_t res_bytes = r.hist + r.dirs + r.cur + sizeof(int32_t) * 4;
+    const size_t pos_bytes = sizeof(double) * 2 * p.S;
+    unsigned char* hb = (unsigned char*)pinned_scratch(res_bytes + pos_bytes);
+    if (hb != nullptr) {
+        std::memcpy(hb + res_bytes, h_pos, pos_bytes);
+        HIP_TRY(hipMemcpyAsync(pos, hb + res_bytes, pos_bytes, hipMemcpyHostToDevice, st));
+    } else {
+        HIP_TRY(hipMemcpyAsync(pos, h_pos, pos_bytes, hipMemcpyHostToDevice, st));
+    }
     EvDesc ev0{};
     ev0.S = p.S;
     ev0.N = p.N;
@@ -3953,8 +3970,6 @@ static au_status run_reconstruct(const au_table* tb, const au_event* ev, const E
     // the results (times, directions, state: one contiguous region of the
     // workspace) in one copy through pinned memory, instead of three staged
     // copies from pageable memory that each wait for the one before
-    const size_t res_bytes = r.hist + r.dirs + r.cur + sizeof(int32_t) * 4;
-    unsigned char* hb = (unsigned char*)pinned_scratch(res_bytes);
     auto fetch = [&]() -> au_status {
         if (hb != nullptr) {
             HIP_TRY(hipMemcpyAsync(hb, hist, res_bytes, hipMemcpyDeviceToHost, st));
