@@ -52,6 +52,29 @@ def check_passes(g, t, v, pos, rec, tol):
             assert env[rec.times[i + 1][s]] >= env.max() * (1 - 2 * tol), (i, s)
 
 
+@pytest.mark.parametrize("max_iter", [5, 10])
+def test_reconstruct_every_pass_when_not_converging(api, max_iter):
+    """Noise traces whose loop never settles (the oracle runs every pass without converging): the
+    device loop's launches then go out in several chunks, each ending with a read of the results,
+    and every pass must still be the oracle's."""
+    import torch
+    g = S.GRID_COARSE
+    t = S.pattern_table(g, cfg=0)
+    tab = api.Table(g, t)
+    n_st, n = 12, 1024
+    pos = S.station_positions(n_st, area_km2=6.0 * n_st / 124)
+    v = S.traces(n_st, n, cfg=0, event=905)
+    o_dirs, o_times, o_conv = O.reconstruct(g, t, v, pos, S.FS_HZ, S.BAND_LO_HZ, S.BAND_HI_HZ, max_iter=max_iter)
+    assert len(o_dirs) == max_iter and not o_conv  # the case this test is for
+    ev = api.make_event(n_st, n)
+    say("reconstruct fp64 noise S", n_st, "N", n, "max_iter", max_iter)
+    rec = api.reconstruct(tab, ev, torch.from_numpy(v).cuda(), pos, max_iter=max_iter)
+    check_passes(g, t, v, pos, rec, TOL_FP64)
+    assert rec.times.shape == o_times.shape and np.array_equal(rec.times, o_times)
+    assert rec.converged == o_conv
+    assert np.max(np.abs(rec.dirs - o_dirs)) < 1e-9
+
+
 @pytest.mark.parametrize("n_st,n,zen,az", [(40, 2048, 35.0, 120.0), (124, 4096, 55.0, 250.0),
                                            (124, 2048, 20.0, 10.0)])
 def test_reconstruct_fp64_matches_oracle(api, n_st, n, zen, az):
