@@ -4428,8 +4428,7 @@ static au_status run_reconstruct_batch(const au_table* tb, const au_event* ev, c
     HIP_TRY(hipMemcpyAsync(eunits, heu.data(), heu.size() * sizeof(int4), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(evst, hst.data(), hst.size() * sizeof(int2), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(pos, h_pos, sizeof(double) * 2 * stot, hipMemcpyHostToDevice, st));
-    const int zero_blocks = (int)((4 * (int64_t)n_events + 255) / 256);
-    hipLaunchKernelGGL(k_zero_u32, dim3(zero_blocks), dim3(256), 0, st, (unsigned int*)state, 4 * n_events);
+    // (each event's state is cleared by its first step)
     EvDesc ev0{};
     ev0.N = p.N;
     ev0.k_lo = p.k_lo;
